@@ -1,0 +1,248 @@
+"""Seeded synthetic inputs for nonnegative tensor completion.
+
+This module only *draws inputs*: observed index sets, planted nonnegative CPD
+factors, observed values, a train/test split and optional FP32 initial
+factors.  It holds none of the solver's arithmetic (no sampling of
+minibatches, no gradients, no step sizes), so the FP64 oracle and the HIP
+library can both consume what it produces without sharing any method code.
+
+Data model (Section II): the planted tensor is the CPD of nonnegative factors
+``U^(m)`` with i.i.d. Uniform[0,1] entries (eq. Xo_densef); observations are
+``X = X^o + E`` on an index set ``Omega`` (eq. M_def).  The experiments of
+Section IV draw Gaussian noise ``N(0, sigma^2)``; the second argument is read
+as a variance.
+
+All randomness comes from NumPy's PCG64 seeded by the caller, so every array
+is reproducible from ``(recipe, seed)``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    """One completion instance: dims, train/test COO and the planted truth."""
+
+    dims: List[int]
+    rank: int                     # rank used by the solver
+    coords: np.ndarray            # int32 [nnz, N], 0-based, train
+    values: np.ndarray            # float32 [nnz], train
+    test_coords: np.ndarray       # int32 [n_test, N]
+    test_values: np.ndarray       # float32 [n_test]
+    planted: Optional[List[np.ndarray]] = None   # FP64 planted factors
+    snr: Optional[float] = None   # ||M*X^o||^2 / ||M*E||^2 (Section IV-B)
+    name: str = ""
+
+    @property
+    def nmodes(self) -> int:
+        return len(self.dims)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.values.shape[0])
+
+
+# ---------------------------------------------------------------- index sets
+def _zipf_cdf(n: int, s: float) -> np.ndarray:
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-s)
+    c = np.cumsum(w)
+    c /= c[-1]
+    return c
+
+
+def _draw_mode(rng, n: int, count: int, zipf_s: Optional[float], relabel: np.ndarray,
+               cdf: Optional[np.ndarray]) -> np.ndarray:
+    if zipf_s is None:
+        return rng.integers(0, n, size=count, dtype=np.int64)
+    u = rng.random(count)
+    rank = np.searchsorted(cdf, u, side="right")        # 0-based rank, P(r) ~ (r+1)^-s
+    np.minimum(rank, n - 1, out=rank)
+    return relabel[rank]
+
+
+def distinct_cells(rng, dims: Sequence[int], nnz: int, zipf_s: Optional[float] = None) -> np.ndarray:
+    """``nnz`` distinct cells of the grid ``dims``, in random order.
+
+    Uniform positions when ``zipf_s`` is None; otherwise each mode's index is
+    Zipf(s) over a seeded random relabelling of its range, cells are
+    de-duplicated on a linearised int64 key, and the set is topped up with
+    fresh draws until ``nnz`` distinct cells exist.
+    """
+    dims = [int(d) for d in dims]
+    total = 1
+    for d in dims:
+        total *= d
+    if nnz > total:
+        raise ValueError("more cells requested than the grid holds")
+    if total >= 2 ** 62:
+        raise ValueError("grid too large for an int64 key")
+    strides = [1] * len(dims)
+    for m in range(len(dims) - 2, -1, -1):
+        strides[m] = strides[m + 1] * dims[m + 1]
+    cdfs, relabels = [], []
+    for d in dims:
+        if zipf_s is None:
+            cdfs.append(None)
+            relabels.append(None)
+        else:
+            cdfs.append(_zipf_cdf(d, zipf_s))
+            relabels.append(rng.permutation(d).astype(np.int64))
+    if zipf_s is None and nnz * 4 > total:
+        # dense fraction: a random subset of the grid directly
+        keys = rng.choice(total, size=nnz, replace=False).astype(np.int64)
+    else:
+        keys = np.empty(0, dtype=np.int64)
+        while keys.shape[0] < nnz:
+            deficit = nnz - keys.shape[0]
+            draw = int(deficit * 1.2) + 1024
+            new = np.zeros(draw, dtype=np.int64)
+            for m, d in enumerate(dims):
+                new += _draw_mode(rng, d, draw, zipf_s, relabels[m], cdfs[m]) * strides[m]
+            keys = np.unique(np.concatenate([keys, new]))
+        keys = keys[rng.permutation(keys.shape[0])[:nnz]]
+    coords = np.empty((nnz, len(dims)), dtype=np.int32)
+    rem = keys
+    for m in range(len(dims)):
+        coords[:, m] = rem // strides[m]
+        rem = rem % strides[m]
+    return coords
+
+
+# ------------------------------------------------------------------- values
+def planted_factors(rng, dims: Sequence[int], rank: int) -> List[np.ndarray]:
+    """i.i.d. Uniform[0,1] nonnegative factors (Section IV-B)."""
+    return [rng.random((int(d), rank)) for d in dims]
+
+
+def planted_values(factors: Sequence[np.ndarray], coords: np.ndarray, chunk: int = 1 << 21) -> np.ndarray:
+    """FP64 entries of the planted CPD at ``coords`` (eq. Xo_densef)."""
+    nnz = coords.shape[0]
+    out = np.empty(nnz, dtype=np.float64)
+    for s in range(0, nnz, chunk):
+        e = min(nnz, s + chunk)
+        acc = factors[0][coords[s:e, 0]].copy()
+        for m in range(1, len(factors)):
+            acc *= factors[m][coords[s:e, m]]
+        out[s:e] = acc.sum(axis=1)
+    return out
+
+
+def split_holdout(rng, coords: np.ndarray, values: np.ndarray, test_frac: float):
+    n = coords.shape[0]
+    n_test = int(round(n * test_frac))
+    perm = rng.permutation(n)
+    te, tr = perm[:n_test], perm[n_test:]
+    return coords[tr], values[tr], coords[te], values[te]
+
+
+def make_problem(dims: Sequence[int], nnz: int, planted_rank: int, *, rank: Optional[int] = None,
+                 zipf_s: Optional[float] = None, noise_var: float = 0.0, value_model: str = "exact",
+                 test_frac: float = 0.1, seed: int = 0, name: str = "",
+                 grid_factors: Optional[int] = None) -> Problem:
+    """Draw one instance.
+
+    value_model:
+      * ``exact``   -- X = X^o (+ noise if ``noise_var`` > 0)
+      * ``clip0``   -- X = max(0, X^o + E)
+      * ``ratings`` -- affine map of X^o onto [1,5] by its empirical min/max
+        over the observed cells, plus noise, rounded to an integer, clipped to 1..5
+    grid_factors: if set, planted factors are drawn from the dyadic grid
+      {0, 1/g, ..., 1} so every CPD value is exact in FP32 and FP64.
+    """
+    rng = np.random.default_rng(seed)
+    dims = [int(d) for d in dims]
+    coords = distinct_cells(rng, dims, nnz, zipf_s)
+    if grid_factors:
+        fac = [rng.integers(0, grid_factors + 1, size=(d, planted_rank)) / float(grid_factors) for d in dims]
+    else:
+        fac = planted_factors(rng, dims, planted_rank)
+    xo = planted_values(fac, coords)
+    if value_model == "ratings":
+        lo, hi = float(xo.min()), float(xo.max())
+        xo = 1.0 + 4.0 * (xo - lo) / (hi - lo if hi > lo else 1.0)
+    noise = rng.normal(0.0, math.sqrt(noise_var), size=nnz) if noise_var > 0 else np.zeros(nnz)
+    x = xo + noise
+    if value_model == "ratings":
+        x = np.clip(np.rint(x), 1.0, 5.0)
+    elif value_model == "clip0":
+        x = np.maximum(x, 0.0)
+    en = float(np.sum((x - xo) ** 2))
+    snr = float(np.sum(xo ** 2)) / en if en > 0 else math.inf
+    vals = x.astype(np.float32)
+    trc, trv, tec, tev = split_holdout(rng, coords, vals, test_frac)
+    return Problem(dims=dims, rank=rank or planted_rank, coords=np.ascontiguousarray(trc),
+                   values=np.ascontiguousarray(trv), test_coords=np.ascontiguousarray(tec),
+                   test_values=np.ascontiguousarray(tev), planted=fac, snr=snr, name=name)
+
+
+def uniform_init(dims: Sequence[int], rank: int, seed: int, scale: float = 1.0) -> List[np.ndarray]:
+    """FP32 initial factors, Uniform[0,1) * scale (an explicit, caller-side U_0)."""
+    rng = np.random.default_rng(seed + 0x5EED)
+    return [(rng.random((int(d), rank), dtype=np.float32) * np.float32(scale)).astype(np.float32)
+            for d in dims]
+
+
+def init_scale(values: np.ndarray, rank: int, nmodes: int) -> float:
+    """Scale s so that a CPD of Uniform[0,s) factors matches the data mean."""
+    mean = float(np.mean(values.astype(np.float64)))
+    return float(np.float32((max(mean, 1e-30) / (rank * 2.0 ** (-nmodes))) ** (1.0 / nmodes)))
+
+
+# ------------------------------------------------------------------ recipes
+def tiny(seed: int = 0, dims=(7, 6, 5), nnz: int = 120, rank: int = 3, **kw) -> Problem:
+    """Small instance for brute-force checks."""
+    kw.setdefault("test_frac", 0.1)
+    return make_problem(dims, nnz, rank, seed=seed, name="tiny", **kw)
+
+
+def c0(seed: int = 0) -> Problem:
+    """3-way 100x80x60, 24,000 uniform cells, planted rank 8, exact CPD, 10% test."""
+    return make_problem((100, 80, 60), 24000, 8, zipf_s=None, noise_var=0.0,
+                        value_model="exact", test_frac=0.1, seed=seed, name="c0")
+
+
+def c1(seed: int = 0, scale: float = 1.0) -> Problem:
+    """3-way 480,000x18,000x2,000, 100M Zipf(1.1) cells, rank-16 ratings 1..5 with
+    N(0,0.1) noise, 5% test.  ``scale`` < 1 shrinks nnz (dims kept) for smaller runs."""
+    nnz = int(round(100_000_000 * scale))
+    return make_problem((480_000, 18_000, 2_000), nnz, 16, zipf_s=1.1, noise_var=0.1,
+                        value_model="ratings", test_frac=0.05, seed=seed, name="c1")
+
+
+def c1_small(seed: int = 0) -> Problem:
+    """Same recipe as c1 on a 1/100-scale grid and nnz (parity-sized, Zipf skew kept)."""
+    return make_problem((4_800, 1_800, 200), 1_000_000, 16, zipf_s=1.1, noise_var=0.1,
+                        value_model="ratings", test_frac=0.05, seed=seed, name="c1_small")
+
+
+def c2(seed: int = 0, scale: float = 1.0) -> Problem:
+    """4-way 1,000,000x500,000x1,000x100, 500M Zipf(1.05) cells, rank-32 CPD +
+    N(0,0.05) clipped at 0, 5% test."""
+    nnz = int(round(500_000_000 * scale))
+    return make_problem((1_000_000, 500_000, 1_000, 100), nnz, 32, zipf_s=1.05, noise_var=0.05,
+                        value_model="clip0", test_frac=0.05, seed=seed, name="c2")
+
+
+def c3_shapes(n_instances: int = 256, base_seed: int = 1000):
+    """Size mixture of the batching workload: per instance dims log-U[50,2000],
+    nnz log-U[10k,2M] capped at half the grid, rank from {8,16,32}."""
+    out = []
+    for i in range(n_instances):
+        rng = np.random.default_rng(base_seed + i)
+        dims = [int(round(math.exp(rng.uniform(math.log(50), math.log(2000))))) for _ in range(3)]
+        nnz = int(round(math.exp(rng.uniform(math.log(10_000), math.log(2_000_000)))))
+        cap = (dims[0] * dims[1] * dims[2]) // 2
+        nnz = min(nnz, cap)
+        rank = int(rng.choice([8, 16, 32]))
+        out.append((dims, nnz, rank, base_seed + i))
+    return out
+
+
+def c3_instance(dims, nnz, rank, seed) -> Problem:
+    return make_problem(dims, nnz, rank, zipf_s=None, noise_var=0.01, value_model="exact",
+                        test_frac=0.05, seed=seed, name="c3")

@@ -1,0 +1,166 @@
+/*
+ * ntc.h -- C ABI of libntc: AO accelerated stochastic nonnegative tensor
+ * completion on one AMD MI355X (gfx950).
+ *
+ * Method: Siaminou, Papagiannakos, Kolomvakis, Liavas, "Accelerated
+ * Stochastic Gradient for Nonnegative Tensor Completion and Parallel
+ * Implementation" (arXiv 2109.09534).
+ *   - Section II, eq. (Problem_TC): minimise 1/2 ||M * (X - [[U^(1..N)]])||_F^2
+ *     + lambda/2 sum_i ||U^(i)||_F^2 over nonnegative factors.
+ *   - Alg. 2: circular (Gauss-Seidel) updates of the modes; each mode update
+ *     is the NMC problem of eq. (matrix_NMC) solved by Alg. 1.
+ *   - Alg. 1: MAX_INNER row-wise steps; row p draws B_{l,p} = floor(c n_p) of
+ *     its n_p observed entries (Section II-B), forms the sampled gradient and
+ *     the row Hessian H_{l,p}, takes L_p = max eig(H_{l,p}) by the power
+ *     method, steps A <- (Y - grad/L_p)_+ and extrapolates with
+ *     beta = (sqrt(L_p) - sqrt(lambda)) / (sqrt(L_p) + sqrt(lambda)).
+ *
+ * Conventions for every entry point:
+ *   - Every pointer argument is HOST memory owned by the caller, read or
+ *     written before the call returns, unless stated otherwise.  Device memory
+ *     belongs to the handle and is freed by ntc_release.
+ *   - Indices are 0-based.  Factors are row-major FP32 arrays [I_m][R].
+ *   - Every call returns an ntc_status; on failure ntc_last_error() gives a
+ *     thread-local message.  Asynchronous device faults surface at the next
+ *     synchronising call as NTC_EDEVICE.
+ *   - One handle is driven by one host thread at a time; different handles
+ *     are independent.  Work is enqueued on the stream given at creation.
+ */
+#ifndef NTC_H
+#define NTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ntc_problem *ntc_handle;
+
+typedef enum {
+    NTC_OK = 0,
+    NTC_EINVAL = -1,       /* invalid argument (message says which) */
+    NTC_ENOMEM = -2,       /* device or host allocation failed */
+    NTC_EDEVICE = -3,      /* HIP runtime error, including asynchronous faults */
+    NTC_EUNSUPPORTED = -4, /* valid request this build does not support */
+    NTC_ENONFINITE = -5,   /* the loss evaluated to a non-finite value */
+    NTC_ESTATE = -6        /* call not valid in the handle's current state */
+} ntc_status;
+
+/* Optional device allocator (e.g. PyTorch's caching allocator).  alloc
+ * returns device memory usable on `stream`, or NULL; free releases it. */
+typedef void *(*ntc_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*ntc_free_fn)(void *ptr, void *ctx);
+
+typedef struct ntc_params {
+    double c;             /* minibatch fraction, 0 < c <= 1 (Section II-B asks c < 1;
+                             c == 1 makes every minibatch the whole row) */
+    double lambda;        /* ridge weight >= 0 (eq. Problem_TC); not scaled by c */
+    int32_t max_inner;    /* MAX_INNER of Alg. 1, >= 1 */
+    int32_t power_iters;  /* normalised power-method products per row, >= 0 (default 20) */
+    uint64_t seed;        /* Philox key of the minibatch sampler and the default init */
+    int32_t gather_bf16;  /* 1: gather other-mode factor rows from a BF16 shadow copy
+                             (FP32 master factors, FP32 accumulation) */
+    int32_t reserved0;
+    int64_t n_test;             /* optional held-out entries for ntc_loss (0 = none) */
+    const int32_t *test_coords; /* [n_test][nmodes], host, copied */
+    const float *test_values;   /* [n_test], host, copied */
+    const float *const *init_factors; /* NULL: Philox Uniform[0,1)*s init (see ntc_create);
+                                         else nmodes host arrays [I_m][R], entries >= 0 */
+    void *stream;               /* hipStream_t; NULL = the null stream */
+    ntc_alloc_fn dev_alloc;     /* optional; NULL = hipMalloc */
+    ntc_free_fn dev_free;
+    void *alloc_ctx;
+} ntc_params;
+
+/* Fill *p with defaults: c = 0.1, lambda = 1e-3, max_inner = 1,
+ * power_iters = 20, seed = 0, FP32 gathers, no test set, default init,
+ * null stream, hipMalloc. */
+void ntc_params_default(ntc_params *p);
+
+/* Create a problem from the observed entries (Section II: X on Omega).
+ *   nmodes in [2, 8]; dims[m] in [1, 2^31); nnz in [0, 2^31);
+ *   coords [nnz][nmodes] int32, 0 <= coords < dims; values [nnz] finite FP32;
+ *   rank R in [1, 64].
+ * Builds one CSR per mode (entries stably sorted by i_m: the unfolding
+ * X_(i), M_(i) of Section II), a static row schedule from
+ * B_p = floor(c n_p), uploads everything and initialises the factors:
+ * either the caller's init_factors, or Philox4x32-10 uniforms
+ * u = (word >> 8) * 2^-24 times s = (mean(values) / (R 2^-N))^(1/N) rounded
+ * to FP32.  The sweep counter k starts at 0.  Duplicate coordinates are
+ * treated as separate observations.  On failure *out is NULL. */
+ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                      const int32_t *coords, const float *values, int32_t rank, const ntc_params *p);
+
+/* Enqueue `nsweeps` iterations of Alg. 2 (each: modes 0..N-1 in order, each
+ * mode one S_NMC call of Alg. 1 with MAX_INNER inner steps), advancing k by
+ * one per sweep.  Asynchronous: returns once the work is enqueued. */
+ntc_status ntc_sweep(ntc_handle h, int32_t nsweeps);
+
+/* Enqueue one S_NMC call (Alg. 1) for `mode` at the current k without
+ * advancing k: the body of Alg. 2's inner loop for one i. */
+ntc_status ntc_update_mode(ntc_handle h, int32_t mode);
+
+/* Synchronise and evaluate, in FP64 on the device with a deterministic
+ * two-stage reduction: out[0] = objective of eq. (Problem_TC) on the
+ * training entries, out[1] = train RMSE, out[2] = test RMSE,
+ * out[3] = test relative error ||x - x_hat|| / ||x|| (0 without a test set).
+ * Returns NTC_ENONFINITE if any of them is not finite. */
+ntc_status ntc_loss(ntc_handle h, double out[4]);
+
+/* Synchronise and copy mode `mode`'s FP32 factor [I_m][R] to host_out. */
+ntc_status ntc_get_factors(ntc_handle h, int32_t mode, float *host_out);
+
+/* Copy a host FP32 factor [I_m][R] (entries >= 0, finite) into the handle
+ * (also refreshes the BF16 shadow). */
+ntc_status ntc_set_factors(ntc_handle h, int32_t mode, const float *host_in);
+
+/* Copy mode `mode`'s factor into caller-owned DEVICE memory dev_out
+ * (I_m * R floats), ordered on the handle's stream. */
+ntc_status ntc_get_factors_device(ntc_handle h, int32_t mode, float *dev_out);
+
+/* Sweep counter k (the Philox counter word of the sampler).  With the
+ * factors it is the whole state: resuming from (factors, k) reproduces an
+ * uninterrupted run bit-exactly. */
+ntc_status ntc_get_sweep(ntc_handle h, int64_t *k);
+ntc_status ntc_set_sweep(ntc_handle h, int64_t k);
+
+/* Problem facts: the number of sampled entries one sweep consumes
+ * (sum over modes and inner steps of sum_p B_p) and the number of rows that
+ * take a step per sweep. */
+ntc_status ntc_get_work(ntc_handle h, int64_t *updates_per_sweep, int64_t *row_steps_per_sweep);
+
+/* Positions (within the row, in [0, n_p)) of the minibatch that row `row` of
+ * `mode` draws at sweep k and inner step l, computed BY THE DEVICE sampler
+ * (Section II-B: B_p = floor(c n_p) entries, uniformly, without
+ * replacement).  pos_out holds >= n_p int32; *count receives B_p.
+ * Synchronising. */
+ntc_status ntc_debug_sample(ntc_handle h, int64_t k, int32_t mode, int32_t l, int64_t row,
+                            int32_t *pos_out, int32_t *count);
+
+/* The same positions computed by the library's HOST copy of the sampler for
+ * a row of length n (no device, no handle).  pos_out holds >= floor(c n)
+ * int32; returns the count through *count. */
+ntc_status ntc_host_sample(uint64_t seed, int64_t k, int32_t mode, int32_t l, int64_t row, int64_t n,
+                           double c, int32_t *pos_out, int64_t *count);
+
+/* The library's host CSR build for one mode, without a device: rowptr_out
+ * [dims[mode]+1] int64 and perm_out [nnz] int64 (COO entry ids, stably
+ * sorted by coordinate `mode`). */
+ntc_status ntc_host_csr(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords,
+                        int32_t mode, int64_t *rowptr_out, int64_t *perm_out);
+
+/* Release all device and host memory of h (NULL is accepted). */
+ntc_status ntc_release(ntc_handle h);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *ntc_last_error(void);
+
+/* Version string of the library build. */
+const char *ntc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NTC_H */

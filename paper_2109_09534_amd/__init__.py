@@ -1,0 +1,323 @@
+"""Python binding of libntc (AO accelerated stochastic nonnegative tensor
+completion on an MI355X).
+
+Argument marshalling only: every step of the method runs in the HIP library
+behind the C ABI of ``include/ntc.h``.  PyTorch is used, optionally, for the
+HIP stream the work is enqueued on and for device memory (its caching
+allocator).  If ``libntc.so`` has not been built, importing works but every
+call raises ``LibraryMissing`` -- there is no CPU fallback.
+
+PyTorch wheels bundle their own HIP runtime under the same soname
+(libamdhip64.so.7) as the system ROCm runtime libntc links.  Whichever is
+loaded first serves the whole process: to share streams and memory with
+torch, import torch before the first call into this module; torch interop
+is refused when two HIP runtimes are mapped.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = ["Problem", "NtcError", "LibraryMissing", "lib", "host_sample", "host_csr", "library_path",
+           "hip_runtimes"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libntc.so")
+
+NTC_OK, NTC_EINVAL, NTC_ENOMEM, NTC_EDEVICE, NTC_EUNSUPPORTED, NTC_ENONFINITE, NTC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+_STATUS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "ENONFINITE", -6: "ESTATE"}
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class NtcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ntc {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("c", ctypes.c_double),
+        ("lam", ctypes.c_double),
+        ("max_inner", ctypes.c_int32),
+        ("power_iters", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("gather_bf16", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("n_test", ctypes.c_int64),
+        ("test_coords", _i32p),
+        ("test_values", _f32p),
+        ("init_factors", ctypes.POINTER(_f32p)),
+        ("stream", ctypes.c_void_p),
+        ("dev_alloc", _ALLOC_FN),
+        ("dev_free", _FREE_FN),
+        ("alloc_ctx", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point of include/ntc.h
+_SIGNATURES = [
+    ("ntc_params_default", None, [ctypes.POINTER(_Params)]),
+    ("ntc_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, _i64p, ctypes.c_int64, _i32p,
+                                  _f32p, ctypes.c_int32, ctypes.POINTER(_Params)]),
+    ("ntc_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("ntc_update_mode", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("ntc_loss", ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    ("ntc_get_factors", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f32p]),
+    ("ntc_set_factors", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f32p]),
+    ("ntc_get_factors_device", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    ("ntc_get_sweep", ctypes.c_int, [ctypes.c_void_p, _i64p]),
+    ("ntc_set_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    ("ntc_get_work", ctypes.c_int, [ctypes.c_void_p, _i64p, _i64p]),
+    ("ntc_debug_sample", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int64, _i32p, _i32p]),
+    ("ntc_host_sample", ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _i32p, _i64p]),
+    ("ntc_host_csr", ctypes.c_int, [ctypes.c_int32, _i64p, ctypes.c_int64, _i32p, ctypes.c_int32, _i64p, _i64p]),
+    ("ntc_release", ctypes.c_int, [ctypes.c_void_p]),
+    ("ntc_last_error", ctypes.c_char_p, []),
+    ("ntc_version", ctypes.c_char_p, []),
+]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded libntc.so; raises LibraryMissing if it was never built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise LibraryMissing(f"{_LIB_PATH} is not built; run `python -m paper_2109_09534_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def hip_runtimes() -> List[str]:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return sorted(paths)
+
+
+def _require_single_runtime():
+    rt = hip_runtimes()
+    if len(rt) > 1:
+        raise NtcError(NTC_ESTATE, "two HIP runtimes are loaded (" + ", ".join(rt) + "); import torch before "
+                       "paper_2109_09534_amd to share streams and memory with it")
+
+
+def _check(status: int):
+    if status != NTC_OK:
+        raise NtcError(status, lib().ntc_last_error().decode(errors="replace"))
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def host_sample(seed: int, k: int, mode: int, l: int, row: int, n: int, c: float) -> np.ndarray:
+    """The library's host copy of the minibatch sampler (no device)."""
+    out = np.zeros(max(1, n), dtype=np.int32)
+    cnt = ctypes.c_int64(0)
+    _check(lib().ntc_host_sample(seed, k, mode, l, row, n, c, _p(out, _i32p), ctypes.byref(cnt)))
+    return out[: cnt.value].copy()
+
+
+def host_csr(dims: Sequence[int], coords: np.ndarray, mode: int):
+    """The library's host CSR build of one mode: (rowptr, perm)."""
+    d = np.asarray(dims, dtype=np.int64)
+    co = np.ascontiguousarray(coords, dtype=np.int32)
+    nnz = co.shape[0]
+    rp = np.zeros(int(d[mode]) + 1, dtype=np.int64)
+    perm = np.zeros(max(1, nnz), dtype=np.int64)
+    _check(lib().ntc_host_csr(len(dims), _p(d, _i64p), nnz, _p(co, _i32p), mode, _p(rp, _i64p), _p(perm, _i64p)))
+    return rp, perm[:nnz]
+
+
+class _TorchAllocator:
+    """Routes the library's device allocations through torch's caching allocator."""
+
+    def __init__(self, device: int):
+        import torch
+        self._torch = torch
+        self._device = device
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self._device, stream))
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc = _ALLOC_FN(_alloc)
+        self.free = _FREE_FN(_free)
+
+
+class Problem:
+    """One completion instance resident on the GPU (ntc_create ... ntc_release).
+
+    ``stream``: None or 0 for the null stream, a raw hipStream_t int, or a
+    ``torch.cuda.Stream`` (torch must share libntc's HIP runtime).
+    ``torch_allocator``: route device memory through torch's caching allocator.
+    """
+
+    def __init__(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *,
+                 c: float = 0.1, lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
+                 gather_bf16: bool = False, test_coords: Optional[np.ndarray] = None,
+                 test_values: Optional[np.ndarray] = None, init: Optional[Sequence[np.ndarray]] = None,
+                 stream=None, torch_allocator: bool = False):
+        L = lib()
+        self.dims = [int(d) for d in dims]
+        self.N = len(self.dims)
+        self.R = int(rank)
+        d = np.asarray(self.dims, dtype=np.int64)
+        co = np.ascontiguousarray(coords, dtype=np.int32)
+        va = np.ascontiguousarray(values, dtype=np.float32)
+        if co.ndim != 2 or co.shape[1] != self.N or co.shape[0] != va.shape[0]:
+            raise ValueError("coords must be [nnz, nmodes] and values [nnz]")
+        prm = _Params()
+        L.ntc_params_default(ctypes.byref(prm))
+        prm.c, prm.lam, prm.max_inner, prm.power_iters, prm.seed = c, lam, max_inner, power_iters, seed
+        prm.gather_bf16 = 1 if gather_bf16 else 0
+        keep = [d, co, va]
+        if test_coords is not None:
+            tc = np.ascontiguousarray(test_coords, dtype=np.int32)
+            tv = np.ascontiguousarray(test_values, dtype=np.float32)
+            keep += [tc, tv]
+            prm.n_test = tv.shape[0]
+            prm.test_coords = _p(tc, _i32p)
+            prm.test_values = _p(tv, _f32p)
+        if init is not None:
+            arrs = [np.ascontiguousarray(u, dtype=np.float32).reshape(-1) for u in init]
+            keep += arrs
+            ptrs = (_f32p * self.N)(*[_p(a, _f32p) for a in arrs])
+            keep.append(ptrs)
+            prm.init_factors = ptrs
+        if torch_allocator or (stream is not None and not isinstance(stream, int)):
+            _require_single_runtime()
+        prm.stream = self._stream_handle(stream)
+        self._allocator = None
+        if torch_allocator:
+            import torch
+            self._allocator = _TorchAllocator(torch.cuda.current_device())
+            prm.dev_alloc = self._allocator.alloc
+            prm.dev_free = self._allocator.free
+        h = ctypes.c_void_p()
+        _check(L.ntc_create(ctypes.byref(h), self.N, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
+                            self.R, ctypes.byref(prm)))
+        self._h = h
+        self.c, self.lam, self.max_inner, self.power_iters, self.seed = c, lam, max_inner, power_iters, seed
+        self.gather_bf16 = gather_bf16
+
+    @staticmethod
+    def _stream_handle(stream):
+        if stream is None or stream == 0:
+            return None
+        if isinstance(stream, int):
+            return stream
+        return stream.cuda_stream
+
+    # -------------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ntc_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- method
+    def sweep(self, n: int = 1):
+        _check(lib().ntc_sweep(self._h, n))
+
+    def update_mode(self, mode: int):
+        _check(lib().ntc_update_mode(self._h, mode))
+
+    def loss(self) -> np.ndarray:
+        """[objective, train RMSE, test RMSE, test relative error]."""
+        out = np.zeros(4, dtype=np.float64)
+        _check(lib().ntc_loss(self._h, _p(out, _f64p)))
+        return out
+
+    def factors(self, mode: int) -> np.ndarray:
+        out = np.zeros((self.dims[mode], self.R), dtype=np.float32)
+        _check(lib().ntc_get_factors(self._h, mode, _p(out, _f32p)))
+        return out
+
+    def all_factors(self) -> List[np.ndarray]:
+        return [self.factors(m) for m in range(self.N)]
+
+    def set_factors(self, mode: int, U: np.ndarray):
+        U = np.ascontiguousarray(U, dtype=np.float32)
+        if U.shape != (self.dims[mode], self.R):
+            raise ValueError("factor shape mismatch")
+        _check(lib().ntc_set_factors(self._h, mode, _p(U, _f32p)))
+
+    def factors_into(self, mode: int, tensor):
+        """Copy mode's factor into a device torch tensor (float32, I x R)."""
+        if tensor.dtype.itemsize != 4 or tensor.numel() != self.dims[mode] * self.R or not tensor.is_contiguous():
+            raise ValueError("need a contiguous float32 tensor of I_m * R elements")
+        _check(lib().ntc_get_factors_device(self._h, mode, ctypes.c_void_p(tensor.data_ptr())))
+
+    @property
+    def sweep_count(self) -> int:
+        k = ctypes.c_int64(0)
+        _check(lib().ntc_get_sweep(self._h, ctypes.byref(k)))
+        return k.value
+
+    @sweep_count.setter
+    def sweep_count(self, k: int):
+        _check(lib().ntc_set_sweep(self._h, k))
+
+    def work(self):
+        """(sampled-entry updates per sweep, row steps per sweep)."""
+        u = ctypes.c_int64(0)
+        r = ctypes.c_int64(0)
+        _check(lib().ntc_get_work(self._h, ctypes.byref(u), ctypes.byref(r)))
+        return u.value, r.value
+
+    def debug_sample(self, k: int, mode: int, l: int, row: int, n_hint: int) -> np.ndarray:
+        """Positions drawn by the device sampler for one row (n_hint >= row length)."""
+        out = np.zeros(max(1, n_hint), dtype=np.int32)
+        cnt = ctypes.c_int32(0)
+        _check(lib().ntc_debug_sample(self._h, k, mode, l, row, _p(out, _i32p), ctypes.byref(cnt)))
+        return out[: cnt.value].copy()

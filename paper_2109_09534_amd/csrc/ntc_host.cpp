@@ -1,0 +1,721 @@
+// Host side of libntc: argument checks, the CSR-per-mode build, the static
+// row schedule, device memory, and the C ABI declared in include/ntc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "ntc.h"
+#include "ntc_internal.h"
+#include "ntc_rng.h"
+
+using ntc::Item;
+using ntc::SplitRow;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ntc_status fail(ntc_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define NTC_HIP(expr)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess)                                                                            \
+            return fail(NTC_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_));         \
+    } while (0)
+
+int padded_rank(int R)
+{
+    return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+}
+
+int record_words(int nmodes)
+{
+    return nmodes <= 4 ? 4 : 8;
+}
+
+// Samples per work item: a fixed amount of work per wave (the wave consumes
+// 64/RP samples per step).
+int item_samples(int rp)
+{
+    return 512 * (64 / rp);
+}
+
+unsigned host_threads()
+{
+    unsigned t = std::thread::hardware_concurrency();
+    if (t == 0)
+        t = 1;
+    return std::min(t, 16u);
+}
+
+template <typename F>
+void parallel_for(int64_t n, F &&f)
+{
+    const unsigned T = host_threads();
+    if (T <= 1 || n < 1 << 16) {
+        f(0, 0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < T; ++t) {
+        const int64_t a = n * t / T, b = n * (t + 1) / T;
+        th.emplace_back([&f, t, a, b] { f(t, a, b); });
+    }
+    for (auto &x : th)
+        x.join();
+}
+
+// Stable counting sort of the COO entries by coordinate `mode`, done in T
+// contiguous chunks so that ties keep COO order.  Writes rowptr [I+1] and,
+// if given, the records [nnz][rw] (other-mode coordinates in increasing mode
+// order, then the value bits) and/or the permutation [nnz].
+void csr_build(int nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords, const float *values, int mode,
+               int rw, std::vector<int64_t> &rowptr, uint32_t *records, int64_t *perm)
+{
+    const int64_t I = dims[mode];
+    const unsigned T = (nnz < (1 << 16)) ? 1u : host_threads();
+    std::vector<uint32_t> cnt(static_cast<size_t>(T) * static_cast<size_t>(I), 0u);
+    std::vector<std::thread> th;
+    auto chunk = [&](unsigned t, int64_t &a, int64_t &b) {
+        a = nnz * t / T;
+        b = nnz * (t + 1) / T;
+    };
+    auto count = [&](unsigned t) {
+        int64_t a, b;
+        chunk(t, a, b);
+        uint32_t *c = cnt.data() + static_cast<size_t>(t) * I;
+        for (int64_t e = a; e < b; ++e)
+            ++c[coords[e * nmodes + mode]];
+    };
+    for (unsigned t = 0; t < T; ++t)
+        th.emplace_back(count, t);
+    for (auto &x : th)
+        x.join();
+    th.clear();
+    rowptr.assign(static_cast<size_t>(I) + 1, 0);
+    for (int64_t p = 0; p < I; ++p) {
+        int64_t run = rowptr[p];
+        for (unsigned t = 0; t < T; ++t) {
+            uint32_t &c = cnt[static_cast<size_t>(t) * I + p];
+            const uint32_t v = c;
+            c = static_cast<uint32_t>(run);
+            run += v;
+        }
+        rowptr[p + 1] = run;
+    }
+    auto scatter = [&](unsigned t) {
+        int64_t a, b;
+        chunk(t, a, b);
+        uint32_t *off = cnt.data() + static_cast<size_t>(t) * I;
+        for (int64_t e = a; e < b; ++e) {
+            const int32_t *ce = coords + e * nmodes;
+            const uint32_t pos = off[ce[mode]]++;
+            if (perm)
+                perm[pos] = e;
+            if (records) {
+                uint32_t *rec = records + static_cast<int64_t>(pos) * rw;
+                int w = 0;
+                for (int m = 0; m < nmodes; ++m)
+                    if (m != mode)
+                        rec[w++] = static_cast<uint32_t>(ce[m]);
+                uint32_t vb;
+                std::memcpy(&vb, values + e, 4);
+                rec[w++] = vb;
+                for (; w < rw; ++w)
+                    rec[w] = 0u;
+            }
+        }
+    };
+    for (unsigned t = 0; t < T; ++t)
+        th.emplace_back(scatter, t);
+    for (auto &x : th)
+        x.join();
+}
+
+struct ModeState {
+    int64_t I = 0;
+    int64_t *rowptr = nullptr;
+    uint32_t *records = nullptr;
+    Item *items = nullptr;
+    SplitRow *split = nullptr;
+    int32_t n_items = 0;
+    int32_t n_split = 0;
+    int32_t n_slots = 0;
+    int64_t samples = 0;
+    int64_t active_rows = 0;
+    std::vector<int64_t> h_rowptr;
+};
+
+}  // namespace
+
+struct ntc_problem {
+    int N = 0, R = 0, RP = 0, rw = 0;
+    int64_t dims[ntc::kMaxModes] = {};
+    int64_t nnz = 0;
+    double c = 0.1, lambda = 1e-3;
+    int max_inner = 1, power_iters = 20;
+    uint64_t seed = 0;
+    bool bf16 = false;
+    int64_t k = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    ntc_alloc_fn alloc = nullptr;
+    ntc_free_fn dfree = nullptr;
+    void *actx = nullptr;
+    std::vector<void *> owned;
+    float *U[ntc::kMaxModes] = {};
+    uint16_t *U16[ntc::kMaxModes] = {};
+    float *Y = nullptr;
+    double *partials = nullptr;
+    ModeState md[ntc::kMaxModes];
+    int64_t n_test = 0;
+    int32_t *test_coords = nullptr;
+    float *test_values = nullptr;
+    double *loss_part = nullptr;
+    double *loss_out = nullptr;
+    int32_t *dbg = nullptr;  // debug sampler output [max row length + 1]
+    int64_t max_row = 0;
+
+    void *dalloc(size_t bytes)
+    {
+        if (bytes == 0)
+            bytes = 256;
+        void *p = nullptr;
+        if (alloc) {
+            p = alloc(bytes, stream, actx);
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        if (p)
+            owned.push_back(p);
+        return p;
+    }
+
+    ~ntc_problem()
+    {
+        if (owned.empty())
+            return;
+        if (stream)
+            (void)hipStreamSynchronize(stream);
+        else
+            (void)hipDeviceSynchronize();
+        for (void *p : owned) {
+            if (dfree)
+                dfree(p, actx);
+            else
+                (void)hipFree(p);
+        }
+    }
+};
+
+namespace {
+
+ntc_status alloc_or_fail(ntc_problem *h, void **dst, size_t bytes, const char *what)
+{
+    *dst = h->dalloc(bytes);
+    if (!*dst)
+        return fail(NTC_ENOMEM, std::string("device allocation failed: ") + what + " (" + std::to_string(bytes) +
+                                    " bytes)");
+    return NTC_OK;
+}
+
+#define NTC_TRY(expr)                 \
+    do {                              \
+        ntc_status s_ = (expr);       \
+        if (s_ != NTC_OK)             \
+            return s_;                \
+    } while (0)
+
+ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
+{
+    ntc::RowArgs a{};
+    const ModeState &m = h->md[mode];
+    a.rowptr = m.rowptr;
+    a.records = m.records;
+    a.items = m.items;
+    a.split = m.split;
+    int w = 0;
+    for (int mm = 0; mm < h->N; ++mm) {
+        if (mm == mode)
+            continue;
+        a.gath[w] = h->U[mm];
+        a.gath16[w] = h->U16[mm];
+        ++w;
+    }
+    a.A = h->U[mode];
+    a.Y = h->Y;
+    a.A16 = h->U16[mode];
+    a.partials = h->partials;
+    a.seed = h->seed;
+    a.k = h->k;
+    a.lambda = h->lambda;
+    a.mode = mode;
+    a.l = l;
+    a.nmodes = h->N;
+    a.rec_words = h->rw;
+    a.R = h->R;
+    a.max_inner = h->max_inner;
+    a.power_iters = h->power_iters;
+    a.n_items = m.n_items;
+    a.n_split = m.n_split;
+    return a;
+}
+
+ntc_status enqueue_mode(ntc_problem *h, int mode)
+{
+    for (int l = 0; l < h->max_inner; ++l) {
+        const ntc::RowArgs a = row_args(h, mode, l);
+        NTC_HIP(ntc::launch_row_items(a, h->RP, h->bf16, h->stream));
+        NTC_HIP(ntc::launch_row_finalize(a, h->RP, h->bf16, h->stream));
+    }
+    return NTC_OK;
+}
+
+ntc_status sync(ntc_problem *h)
+{
+    NTC_HIP(hipStreamSynchronize(h->stream));
+    return NTC_OK;
+}
+
+ntc_status check_mode(ntc_problem *h, int32_t mode)
+{
+    if (!h)
+        return fail(NTC_EINVAL, "null handle");
+    if (mode < 0 || mode >= h->N)
+        return fail(NTC_EINVAL, "mode out of range");
+    return NTC_OK;
+}
+
+ntc_status validate_factor(const float *src, int64_t count, int mode)
+{
+    for (int64_t t = 0; t < count; ++t)
+        if (!(src[t] >= 0.0f) || !std::isfinite(src[t]))
+            return fail(NTC_EINVAL, "factor of mode " + std::to_string(mode) +
+                                        " has a negative or non-finite entry at " + std::to_string(t));
+    return NTC_OK;
+}
+
+ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t nnz, const int32_t *coords,
+                       const float *values, int32_t R, const ntc_params &p)
+{
+    if (N < 2 || N > ntc::kMaxModes)
+        return fail(NTC_EINVAL, "nmodes must be in [2, 8]");
+    if (R < 1 || R > ntc::kMaxRank)
+        return fail(NTC_EINVAL, "rank must be in [1, 64]");
+    if (!dims)
+        return fail(NTC_EINVAL, "dims is null");
+    if (nnz < 0 || nnz >= (int64_t(1) << 31))
+        return fail(NTC_EINVAL, "nnz must be in [0, 2^31)");
+    if (nnz > 0 && (!coords || !values))
+        return fail(NTC_EINVAL, "coords/values are null");
+    if (!(p.c > 0.0 && p.c <= 1.0))
+        return fail(NTC_EINVAL, "c must be in (0, 1]");
+    if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda))
+        return fail(NTC_EINVAL, "lambda must be finite and >= 0");
+    if (p.max_inner < 1 || p.max_inner > 0xFFFF)
+        return fail(NTC_EINVAL, "max_inner must be in [1, 65535]");
+    if (p.power_iters < 0)
+        return fail(NTC_EINVAL, "power_iters must be >= 0");
+    if (p.n_test < 0 || (p.n_test > 0 && (!p.test_coords || !p.test_values)))
+        return fail(NTC_EINVAL, "test set pointers are null");
+    for (int m = 0; m < N; ++m)
+        if (dims[m] < 1 || dims[m] >= (int64_t(1) << 31))
+            return fail(NTC_EINVAL, "dims[" + std::to_string(m) + "] must be in [1, 2^31)");
+    for (int64_t e = 0; e < nnz; ++e) {
+        for (int m = 0; m < N; ++m) {
+            const int32_t x = coords[e * N + m];
+            if (x < 0 || x >= dims[m])
+                return fail(NTC_EINVAL, "coordinate out of range at entry " + std::to_string(e));
+        }
+        if (!std::isfinite(values[e]))
+            return fail(NTC_EINVAL, "non-finite value at entry " + std::to_string(e));
+    }
+    for (int64_t e = 0; e < p.n_test; ++e) {
+        for (int m = 0; m < N; ++m) {
+            const int32_t x = p.test_coords[e * N + m];
+            if (x < 0 || x >= dims[m])
+                return fail(NTC_EINVAL, "test coordinate out of range at entry " + std::to_string(e));
+        }
+        if (!std::isfinite(p.test_values[e]))
+            return fail(NTC_EINVAL, "non-finite test value at entry " + std::to_string(e));
+    }
+    if (p.init_factors)
+        for (int m = 0; m < N; ++m) {
+            if (!p.init_factors[m])
+                return fail(NTC_EINVAL, "init_factors[" + std::to_string(m) + "] is null");
+            NTC_TRY(validate_factor(p.init_factors[m], dims[m] * R, m));
+        }
+
+    h->N = N;
+    h->R = R;
+    h->RP = padded_rank(R);
+    h->rw = record_words(N);
+    h->nnz = nnz;
+    h->c = p.c;
+    h->lambda = p.lambda;
+    h->max_inner = p.max_inner;
+    h->power_iters = p.power_iters;
+    h->seed = p.seed;
+    h->bf16 = p.gather_bf16 != 0;
+    h->stream = static_cast<hipStream_t>(p.stream);
+    h->alloc = p.dev_alloc;
+    h->dfree = p.dev_free;
+    h->actx = p.alloc_ctx;
+    NTC_HIP(hipGetDevice(&h->device));
+    for (int m = 0; m < N; ++m)
+        h->dims[m] = dims[m];
+
+    // factors and shadows
+    int64_t maxI = 0;
+    for (int m = 0; m < N; ++m) {
+        const int64_t cntm = dims[m] * R;
+        maxI = std::max(maxI, dims[m]);
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U[m]), cntm * sizeof(float), "factor"));
+        if (h->bf16)
+            NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U16[m]), cntm * sizeof(uint16_t), "bf16 shadow"));
+    }
+    if (h->max_inner > 1)
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->Y), maxI * R * sizeof(float), "Y buffer"));
+
+    // CSR per mode and the static schedule
+    std::vector<uint32_t> rec(static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw);
+    const int rp = h->RP;
+    const int smax = item_samples(rp);
+    int32_t max_slots = 0;
+    for (int m = 0; m < N; ++m) {
+        ModeState &md = h->md[m];
+        md.I = dims[m];
+        csr_build(N, dims, nnz, coords, values, m, h->rw, md.h_rowptr, rec.data(), nullptr);
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.rowptr), (md.I + 1) * sizeof(int64_t), "rowptr"));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.records),
+                              static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw * 4, "records"));
+        NTC_HIP(hipMemcpy(md.rowptr, md.h_rowptr.data(), (md.I + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+        NTC_HIP(hipMemcpy(md.records, rec.data(), static_cast<size_t>(nnz) * h->rw * 4, hipMemcpyHostToDevice));
+        std::vector<int32_t> rows;
+        std::vector<int64_t> bsz(static_cast<size_t>(md.I));
+        for (int64_t r = 0; r < md.I; ++r) {
+            const int64_t n = md.h_rowptr[r + 1] - md.h_rowptr[r];
+            h->max_row = std::max(h->max_row, n);
+            bsz[r] = ntc::minibatch_size(h->c, n);
+            if (bsz[r] > 0)
+                rows.push_back(static_cast<int32_t>(r));
+        }
+        std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return bsz[a] > bsz[b]; });
+        std::vector<Item> items;
+        std::vector<SplitRow> split;
+        int32_t slot = 0;
+        for (int32_t r : rows) {
+            const int64_t b = bsz[r];
+            md.samples += b;
+            md.active_rows += 1;
+            if (b <= smax) {
+                items.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
+            } else {
+                const int32_t s0 = slot;
+                for (int64_t j0 = 0; j0 < b; j0 += smax)
+                    items.push_back(Item{r, static_cast<int32_t>(j0), static_cast<int32_t>(std::min(b, j0 + smax)),
+                                         slot++});
+                split.push_back(SplitRow{r, s0, slot - s0, 0});
+            }
+        }
+        md.n_items = static_cast<int32_t>(items.size());
+        md.n_split = static_cast<int32_t>(split.size());
+        md.n_slots = slot;
+        max_slots = std::max(max_slots, slot);
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.items), items.size() * sizeof(Item), "items"));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.split), split.size() * sizeof(SplitRow), "split"));
+        if (!items.empty())
+            NTC_HIP(hipMemcpy(md.items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+        if (!split.empty())
+            NTC_HIP(hipMemcpy(md.split, split.data(), split.size() * sizeof(SplitRow), hipMemcpyHostToDevice));
+    }
+    rec.clear();
+    rec.shrink_to_fit();
+    NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->partials),
+                          static_cast<size_t>(std::max(max_slots, 1)) * (rp + rp * rp) * sizeof(double), "partials"));
+
+    // held-out set and loss buffers
+    h->n_test = p.n_test;
+    NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->test_coords),
+                          static_cast<size_t>(std::max<int64_t>(p.n_test, 1)) * N * sizeof(int32_t), "test coords"));
+    NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->test_values),
+                          static_cast<size_t>(std::max<int64_t>(p.n_test, 1)) * sizeof(float), "test values"));
+    if (p.n_test > 0) {
+        NTC_HIP(hipMemcpy(h->test_coords, p.test_coords, p.n_test * N * sizeof(int32_t), hipMemcpyHostToDevice));
+        NTC_HIP(hipMemcpy(h->test_values, p.test_values, p.n_test * sizeof(float), hipMemcpyHostToDevice));
+    }
+    NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->loss_part), 4 * ntc::kLossBlocks * sizeof(double),
+                          "loss partials"));
+    NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->loss_out), 4 * sizeof(double), "loss out"));
+    NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->dbg), (h->max_row + 1) * sizeof(int32_t), "debug"));
+
+    // initial factors
+    if (p.init_factors) {
+        for (int m = 0; m < N; ++m) {
+            NTC_HIP(hipMemcpy(h->U[m], p.init_factors[m], dims[m] * R * sizeof(float), hipMemcpyHostToDevice));
+            if (h->bf16)
+                NTC_HIP(ntc::launch_to_bf16(h->U[m], h->U16[m], dims[m] * R, h->stream));
+        }
+    } else {
+        double sum = 0.0;
+        for (int64_t e = 0; e < nnz; ++e)
+            sum += static_cast<double>(values[e]);
+        double mean = nnz > 0 ? sum / static_cast<double>(nnz) : 0.0;
+        if (!(mean > 1e-30))
+            mean = 1e-30;
+        const float s = static_cast<float>(
+            std::pow(mean / (static_cast<double>(R) * std::pow(2.0, -static_cast<double>(N))), 1.0 / static_cast<double>(N)));
+        for (int m = 0; m < N; ++m)
+            NTC_HIP(ntc::launch_init_factor(h->U[m], h->U16[m], dims[m] * R, m, h->seed, s, h->stream));
+    }
+    return sync(h);
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+void ntc_params_default(ntc_params *p)
+{
+    if (!p)
+        return;
+    std::memset(p, 0, sizeof(*p));
+    p->c = 0.1;
+    p->lambda = 1e-3;
+    p->max_inner = 1;
+    p->power_iters = 20;
+}
+
+ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords,
+                      const float *values, int32_t rank, const ntc_params *p)
+{
+    if (!out)
+        return fail(NTC_EINVAL, "out is null");
+    *out = nullptr;
+    ntc_params def;
+    ntc_params_default(&def);
+    ntc_problem *h = new (std::nothrow) ntc_problem();
+    if (!h)
+        return fail(NTC_ENOMEM, "host allocation failed");
+    ntc_status s;
+    try {
+        s = create_impl(h, nmodes, dims, nnz, coords, values, rank, p ? *p : def);
+    } catch (const std::bad_alloc &) {
+        s = fail(NTC_ENOMEM, "host allocation failed");
+    }
+    if (s != NTC_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return NTC_OK;
+}
+
+ntc_status ntc_sweep(ntc_handle h, int32_t nsweeps)
+{
+    if (!h)
+        return fail(NTC_EINVAL, "null handle");
+    if (nsweeps < 0)
+        return fail(NTC_EINVAL, "nsweeps must be >= 0");
+    for (int32_t s = 0; s < nsweeps; ++s) {
+        for (int m = 0; m < h->N; ++m)
+            NTC_TRY(enqueue_mode(h, m));
+        h->k += 1;
+    }
+    return NTC_OK;
+}
+
+ntc_status ntc_update_mode(ntc_handle h, int32_t mode)
+{
+    NTC_TRY(check_mode(h, mode));
+    return enqueue_mode(h, mode);
+}
+
+ntc_status ntc_loss(ntc_handle h, double out[4])
+{
+    if (!h || !out)
+        return fail(NTC_EINVAL, "null argument");
+    ntc::LossArgs a{};
+    a.rowptr0 = h->md[0].rowptr;
+    a.records0 = h->md[0].records;
+    a.nnz = h->nnz;
+    a.I0 = h->dims[0];
+    a.test_coords = h->test_coords;
+    a.test_values = h->test_values;
+    a.n_test = h->n_test;
+    for (int m = 0; m < h->N; ++m) {
+        a.U[m] = h->U[m];
+        a.dims[m] = h->dims[m];
+    }
+    a.nmodes = h->N;
+    a.rec_words = h->rw;
+    a.R = h->R;
+    a.part = h->loss_part;
+    a.out = h->loss_out;
+    NTC_HIP(ntc::launch_loss(a, h->stream));
+    double s[4];
+    NTC_HIP(hipMemcpyAsync(s, h->loss_out, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    NTC_TRY(sync(h));
+    out[0] = 0.5 * s[0] + 0.5 * h->lambda * s[3];
+    out[1] = h->nnz > 0 ? std::sqrt(s[0] / static_cast<double>(h->nnz)) : 0.0;
+    out[2] = h->n_test > 0 ? std::sqrt(s[1] / static_cast<double>(h->n_test)) : 0.0;
+    out[3] = (h->n_test > 0 && s[2] > 0.0) ? std::sqrt(s[1]) / std::sqrt(s[2]) : 0.0;
+    for (int q = 0; q < 4; ++q)
+        if (!std::isfinite(out[q]))
+            return fail(NTC_ENONFINITE, "loss is not finite");
+    return NTC_OK;
+}
+
+ntc_status ntc_get_factors(ntc_handle h, int32_t mode, float *host_out)
+{
+    NTC_TRY(check_mode(h, mode));
+    if (!host_out)
+        return fail(NTC_EINVAL, "host_out is null");
+    NTC_HIP(hipMemcpyAsync(host_out, h->U[mode], h->dims[mode] * h->R * sizeof(float), hipMemcpyDeviceToHost,
+                           h->stream));
+    return sync(h);
+}
+
+ntc_status ntc_set_factors(ntc_handle h, int32_t mode, const float *host_in)
+{
+    NTC_TRY(check_mode(h, mode));
+    if (!host_in)
+        return fail(NTC_EINVAL, "host_in is null");
+    NTC_TRY(validate_factor(host_in, h->dims[mode] * h->R, mode));
+    NTC_TRY(sync(h));
+    NTC_HIP(hipMemcpy(h->U[mode], host_in, h->dims[mode] * h->R * sizeof(float), hipMemcpyHostToDevice));
+    if (h->bf16)
+        NTC_HIP(ntc::launch_to_bf16(h->U[mode], h->U16[mode], h->dims[mode] * h->R, h->stream));
+    return sync(h);
+}
+
+ntc_status ntc_get_factors_device(ntc_handle h, int32_t mode, float *dev_out)
+{
+    NTC_TRY(check_mode(h, mode));
+    if (!dev_out)
+        return fail(NTC_EINVAL, "dev_out is null");
+    NTC_HIP(hipMemcpyAsync(dev_out, h->U[mode], h->dims[mode] * h->R * sizeof(float), hipMemcpyDeviceToDevice,
+                           h->stream));
+    return NTC_OK;
+}
+
+ntc_status ntc_get_sweep(ntc_handle h, int64_t *k)
+{
+    if (!h || !k)
+        return fail(NTC_EINVAL, "null argument");
+    *k = h->k;
+    return NTC_OK;
+}
+
+ntc_status ntc_set_sweep(ntc_handle h, int64_t k)
+{
+    if (!h)
+        return fail(NTC_EINVAL, "null handle");
+    if (k < 0)
+        return fail(NTC_EINVAL, "k must be >= 0");
+    h->k = k;
+    return NTC_OK;
+}
+
+ntc_status ntc_get_work(ntc_handle h, int64_t *updates_per_sweep, int64_t *row_steps_per_sweep)
+{
+    if (!h)
+        return fail(NTC_EINVAL, "null handle");
+    int64_t u = 0, r = 0;
+    for (int m = 0; m < h->N; ++m) {
+        u += h->md[m].samples * h->max_inner;
+        r += h->md[m].active_rows * h->max_inner;
+    }
+    if (updates_per_sweep)
+        *updates_per_sweep = u;
+    if (row_steps_per_sweep)
+        *row_steps_per_sweep = r;
+    return NTC_OK;
+}
+
+ntc_status ntc_debug_sample(ntc_handle h, int64_t k, int32_t mode, int32_t l, int64_t row, int32_t *pos_out,
+                            int32_t *count)
+{
+    NTC_TRY(check_mode(h, mode));
+    if (!pos_out || !count)
+        return fail(NTC_EINVAL, "null argument");
+    if (row < 0 || row >= h->dims[mode])
+        return fail(NTC_EINVAL, "row out of range");
+    if (l < 0 || l > 0xFFFF)
+        return fail(NTC_EINVAL, "l out of range");
+    NTC_HIP(ntc::launch_debug_sample(h->md[mode].rowptr, row, h->seed, k, mode, l, h->c, h->dbg + 1, h->dbg,
+                                     h->stream));
+    int32_t cnt = 0;
+    NTC_HIP(hipMemcpyAsync(&cnt, h->dbg, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    NTC_TRY(sync(h));
+    if (cnt > 0) {
+        NTC_HIP(hipMemcpyAsync(pos_out, h->dbg + 1, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        NTC_TRY(sync(h));
+    }
+    *count = cnt;
+    return NTC_OK;
+}
+
+ntc_status ntc_host_sample(uint64_t seed, int64_t k, int32_t mode, int32_t l, int64_t row, int64_t n, double c,
+                           int32_t *pos_out, int64_t *count)
+{
+    if (!count || n < 0 || n >= (int64_t(1) << 31) || !(c > 0.0 && c <= 1.0))
+        return fail(NTC_EINVAL, "invalid argument");
+    const int64_t b = ntc::minibatch_size(c, n);
+    if (b > 0 && !pos_out)
+        return fail(NTC_EINVAL, "pos_out is null");
+    if (b > 0) {
+        const ntc::Prp prp = ntc::make_prp(static_cast<uint32_t>(n), ntc::sample_keys(seed, k, mode, l, row));
+        for (int64_t j = 0; j < b; ++j)
+            pos_out[j] = static_cast<int32_t>(ntc::prp_index(prp, static_cast<uint32_t>(j)));
+    }
+    *count = b;
+    return NTC_OK;
+}
+
+ntc_status ntc_host_csr(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords, int32_t mode,
+                        int64_t *rowptr_out, int64_t *perm_out)
+{
+    if (nmodes < 2 || nmodes > ntc::kMaxModes || !dims || mode < 0 || mode >= nmodes || nnz < 0 ||
+        (nnz > 0 && !coords) || !rowptr_out)
+        return fail(NTC_EINVAL, "invalid argument");
+    for (int64_t e = 0; e < nnz; ++e)
+        for (int m = 0; m < nmodes; ++m)
+            if (coords[e * nmodes + m] < 0 || coords[e * nmodes + m] >= dims[m])
+                return fail(NTC_EINVAL, "coordinate out of range");
+    std::vector<int64_t> rp;
+    csr_build(nmodes, dims, nnz, coords, nullptr, mode, record_words(nmodes), rp, nullptr, perm_out);
+    std::memcpy(rowptr_out, rp.data(), rp.size() * sizeof(int64_t));
+    return NTC_OK;
+}
+
+ntc_status ntc_release(ntc_handle h)
+{
+    delete h;
+    return NTC_OK;
+}
+
+const char *ntc_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char *ntc_version(void)
+{
+    return "libntc 0.1 (gfx950)";
+}
+
+}  // extern "C"

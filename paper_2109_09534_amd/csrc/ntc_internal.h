@@ -1,0 +1,86 @@
+// Internal types of libntc shared by the host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ntc {
+
+constexpr int kMaxModes = 8;
+constexpr int kMaxRank = 64;
+
+// One unit of row work: samples [j0, j1) of the row's minibatch.  slot < 0:
+// the item covers the whole minibatch and finishes the row itself; slot >= 0:
+// it writes its partial (g, H) to partial slot `slot` and a finalize pass
+// combines the row's slots in slot order.
+struct Item {
+    int32_t row;
+    int32_t j0;
+    int32_t j1;
+    int32_t slot;
+};
+
+// A row whose minibatch is split over `nslots` consecutive partial slots.
+struct SplitRow {
+    int32_t row;
+    int32_t slot0;
+    int32_t nslots;
+    int32_t pad;
+};
+
+// Arguments of the row kernels for one (mode, inner step).
+struct RowArgs {
+    const int64_t *rowptr;        // [I+1] CSR of this mode
+    const uint32_t *records;      // [nnz][rec_words]: other-mode coords (increasing mode), value bits
+    const Item *items;
+    const SplitRow *split;
+    const float *gath[kMaxModes - 1];     // other modes' FP32 factors, increasing mode order
+    const uint16_t *gath16[kMaxModes - 1];// their BF16 shadows (precision form)
+    float *A;                     // this mode's factor (A_l in, A_{l+1} out, in place)
+    float *Y;                     // extrapolated iterate buffer (MAX_INNER > 1)
+    uint16_t *A16;                // this mode's BF16 shadow (or null)
+    double *partials;             // [slots][RP + RP*RP]
+    uint64_t seed;
+    int64_t k;
+    double lambda;
+    int32_t mode;
+    int32_t l;
+    int32_t nmodes;
+    int32_t rec_words;
+    int32_t R;
+    int32_t max_inner;
+    int32_t power_iters;
+    int32_t n_items;
+    int32_t n_split;
+};
+
+struct LossArgs {
+    const int64_t *rowptr0;       // CSR of mode 0
+    const uint32_t *records0;
+    int64_t nnz;
+    int64_t I0;
+    const int32_t *test_coords;
+    const float *test_values;
+    int64_t n_test;
+    const float *U[kMaxModes];
+    int64_t dims[kMaxModes];
+    int32_t nmodes;
+    int32_t rec_words;
+    int32_t R;
+    double *part;                 // [4][kLossBlocks]: train SSE, test SSE, test sum x^2, sum U^2
+    double *out;                  // [4]
+};
+
+constexpr int kLossBlocks = 512;
+constexpr int kLossThreads = 256;
+
+hipError_t launch_row_items(const RowArgs &a, int rp, bool bf16, hipStream_t s);
+hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t s);
+hipError_t launch_loss(const LossArgs &a, hipStream_t s);
+hipError_t launch_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale,
+                              hipStream_t s);
+hipError_t launch_to_bf16(const float *U, uint16_t *U16, int64_t count, hipStream_t s);
+hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed, int64_t k, int32_t mode,
+                               int32_t l, double c, int32_t *pos_out, int32_t *count_out, hipStream_t s);
+
+}  // namespace ntc

@@ -1,0 +1,256 @@
+"""GPU parity of libntc against the FP64 oracle, through the C ABI.
+
+Inputs are seeded synthetic tensors shaped like the paper's workloads; both
+sides start from the same FP32 factors.  Bars: sampled positions bit-exact;
+one sweep from identical iterates within 1e-5 relative (Frobenius, per mode)
+and element-wise within 1e-5 relative to the factor scale; final test RMSE
+within 1e-3 of the oracle's.
+"""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2109_09534_amd as ntc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    O.build(force=False)
+    O.set_threads(8)
+    ntc.lib()
+
+
+def _pair(p, R, *, init_seed=1, scale=None, **kw):
+    """(gpu problem, oracle) on identical FP32 init."""
+    if scale is None:
+        scale = synth.init_scale(p.values, R, len(p.dims))
+    init = synth.uniform_init(p.dims, R, init_seed, scale)
+    g = ntc.Problem(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
+                    init=init, stream=0, **kw)
+    okw = {k: v for k, v in kw.items() if k != "gather_bf16"}
+    o = O.Oracle(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
+                 init=init, **okw)
+    return g, o, init
+
+
+def _assert_factor_close(gpu, ora, tag, rel=1e-5):
+    err = np.linalg.norm(gpu - ora) / max(np.linalg.norm(ora), 1e-300)
+    scale = np.sqrt(np.mean(ora ** 2)) + 1e-300
+    worst = np.max(np.abs(gpu - ora) / (np.abs(ora) + scale))
+    _say(f"  {tag}: rel Frobenius {err:.3e}, worst element {worst:.3e}")
+    assert err <= rel, (tag, err)
+    assert worst <= rel, (tag, worst)
+
+
+# ------------------------------------------------------------------ sampler
+def test_device_sampler_is_bit_exact():
+    p = synth.c1_small(seed=3)
+    g = ntc.Problem(p.dims, p.coords, p.values, 16, c=0.1, seed=77, stream=0)
+    o = O.Oracle(p.dims, p.coords, p.values, 16, c=0.1, seed=77)
+    rng = np.random.default_rng(0)
+    checked = 0
+    for mode in range(3):
+        rp, _ = o.csr(mode)
+        n = np.diff(rp)
+        rows = np.concatenate([np.argsort(-n)[:5], rng.integers(0, p.dims[mode], 30)])
+        for row in rows:
+            for k, l in [(0, 0), (5, 1), (2**31 + 3, 0)]:
+                dev = g.debug_sample(k, mode, l, int(row), int(n.max()))
+                ref = O.sample_positions(77, k, mode, l, int(row), int(n[row]), 0.1)
+                assert np.array_equal(dev, ref), (mode, row, k, l)
+                checked += dev.shape[0]
+    _say(f"  {checked} sampled positions identical")
+    assert checked > 100000
+
+
+# ---------------------------------------------------------- one-sweep parity
+CASES = {
+    "cpu_sized_r8": lambda: (synth.c0(seed=0), 8, dict(c=0.1)),
+    "cpu_sized_r8_inner2": lambda: (synth.c0(seed=0), 8, dict(c=0.1, max_inner=2)),
+    "zipf_r16_split_rows": lambda: (synth.c1_small(seed=0), 16, dict(c=0.1)),
+    "zipf_r16_c05": lambda: (synth.c1_small(seed=1), 16, dict(c=0.5)),
+    "r32": lambda: (synth.make_problem((300, 200, 100), 200_000, 32, noise_var=0.05, value_model="clip0",
+                                       seed=4, zipf_s=1.05, test_frac=0.05), 32, dict(c=0.1)),
+    "r50_4way": lambda: (synth.make_problem((183, 24, 114, 171), 150_000, 10, seed=5, test_frac=0.05), 50,
+                         dict(c=0.5)),
+    "r10_5way_generic": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=6), 10, dict(c=0.3)),
+    "r12_matrix": lambda: (synth.make_problem((400, 300), 40_000, 6, seed=7), 12, dict(c=0.2)),
+    "full_batch_inner3": lambda: (synth.make_problem((60, 50, 40), 30_000, 6, seed=8), 6,
+                                  dict(c=1.0, max_inner=3, lam=0.01)),
+    "lambda0_inner5": lambda: (synth.make_problem((80, 60, 50), 40_000, 4, seed=9, noise_var=0.01), 4,
+                               dict(c=0.25, lam=0.0, max_inner=5)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_one_sweep_matches_oracle(case):
+    p, R, kw = CASES[case]()
+    _say(f"case {case}: dims {p.dims} nnz {p.nnz} R {R} {kw}")
+    g, o, init = _pair(p, R, **kw)
+    upd, rows = g.work()
+    assert upd > 0
+    g.sweep(1)
+    o.sweep(1)
+    for m in range(len(p.dims)):
+        gm = g.factors(m).astype(np.float64)
+        assert np.all(gm >= 0.0)
+        _assert_factor_close(gm, o.factors(m), f"mode {m}")
+    assert g.sweep_count == 1
+
+
+def test_each_mode_update_matches_oracle_from_the_same_factors():
+    """Mode by mode from shared FP32 factors (no Gauss-Seidel drift)."""
+    p = synth.c1_small(seed=2)
+    g, o, init = _pair(p, 16, c=0.1)
+    for m in range(3):
+        g.update_mode(m)
+        o.update_mode(m)
+        gm = g.factors(m)
+        _assert_factor_close(gm.astype(np.float64), o.factors(m), f"mode {m}")
+        o.set_factors(m, gm.astype(np.float64))   # continue both from the GPU's FP32 values
+
+
+# ----------------------------------------------------------- multi-sweep
+def test_final_test_rmse_within_1e3_of_oracle():
+    p = synth.c0(seed=0)
+    g, o, init = _pair(p, 8, c=0.1)
+    g.sweep(20)
+    o.sweep(20)
+    lg, lo = g.loss(), o.loss()
+    _say(f"  GPU loss {lg}, oracle {lo}")
+    assert abs(lg[2] - lo[2]) <= 1e-3
+    for m in range(3):
+        assert np.all(g.factors(m) >= 0)
+
+
+def test_bf16_gathers_final_rmse_within_1e3_of_oracle():
+    p = synth.c0(seed=0)
+    g, o, init = _pair(p, 8, c=0.1, gather_bf16=True)
+    g.sweep(1)
+    o.sweep(1)
+    errs = [np.linalg.norm(g.factors(m) - o.factors(m)) / np.linalg.norm(o.factors(m)) for m in range(3)]
+    _say(f"  BF16 one-sweep error vs FP64 oracle per mode: {errs}")
+    assert max(errs) < 2e-2
+    g.sweep(19)
+    o.sweep(19)
+    lg, lo = g.loss(), o.loss()
+    _say(f"  BF16 GPU loss {lg}, oracle {lo}")
+    assert abs(lg[2] - lo[2]) <= 1e-3
+
+
+def test_loss_matches_oracle_on_identical_factors():
+    p = synth.c1_small(seed=4)
+    g, o, init = _pair(p, 16)
+    lg, lo = g.loss(), o.loss()
+    np.testing.assert_allclose(lg, lo, rtol=1e-11)
+
+
+def test_fixed_point_is_bit_exact_on_gpu():
+    p = synth.make_problem((40, 30, 20), 5000, 4, grid_factors=16, seed=2)
+    U0 = [u.astype(np.float32) for u in p.planted]
+    g = ntc.Problem(p.dims, p.coords, p.values, 4, c=0.5, lam=0.0, max_inner=2, init=U0, stream=0)
+    g.sweep(2)
+    for m in range(3):
+        assert np.array_equal(g.factors(m), U0[m])
+
+
+def test_runs_are_bit_identical_and_resumable():
+    p = synth.c1_small(seed=5)
+    init = synth.uniform_init(p.dims, 16, 3, synth.init_scale(p.values, 16, 3))
+    a = ntc.Problem(p.dims, p.coords, p.values, 16, init=init, stream=0)
+    b = ntc.Problem(p.dims, p.coords, p.values, 16, init=init, stream=0)
+    a.sweep(4)
+    b.sweep(2)
+    mid = b.all_factors()
+    c = ntc.Problem(p.dims, p.coords, p.values, 16, init=mid, stream=0)
+    c.sweep_count = b.sweep_count
+    c.sweep(2)
+    b.sweep(2)
+    for m in range(3):
+        fa = a.factors(m)
+        assert np.array_equal(fa, b.factors(m))
+        assert np.array_equal(fa, c.factors(m))
+
+
+def test_default_init_matches_oracle_bit_exactly():
+    p = synth.c0(seed=1)
+    g = ntc.Problem(p.dims, p.coords, p.values, 8, seed=99, stream=0)
+    o = O.Oracle(p.dims, p.coords, p.values, 8, seed=99)
+    for m in range(3):
+        assert np.array_equal(g.factors(m).astype(np.float64), o.factors(m))
+
+
+# ---------------------------------------------------------------- edges
+def test_empty_and_degenerate_problems():
+    # no observed entries: nothing moves, loss is the regulariser
+    dims = [5, 4, 3]
+    init = synth.uniform_init(dims, 3, 0)
+    g = ntc.Problem(dims, np.zeros((0, 3), np.int32), np.zeros(0, np.float32), 3, init=init, stream=0)
+    g.sweep(2)
+    for m in range(3):
+        assert np.array_equal(g.factors(m), init[m])
+    lg = g.loss()
+    assert lg[1] == 0.0 and lg[0] == pytest.approx(0.5e-3 * sum(float(np.sum(u.astype(np.float64) ** 2)) for u in init))
+    # every row below 1/c entries: all rows skipped
+    p = synth.tiny(seed=4, dims=(30, 30, 30), nnz=200, rank=2)
+    init = synth.uniform_init(p.dims, 2, 0)
+    g = ntc.Problem(p.dims, p.coords, p.values, 2, c=0.02, init=init, stream=0)
+    assert g.work() == (0, 0)
+    g.sweep(1)
+    assert all(np.array_equal(g.factors(m), init[m]) for m in range(3))
+    # a mode of size one, rank one
+    p = synth.make_problem((1, 50, 40), 1500, 1, seed=3)
+    g, o, _ = _pair(p, 1, c=0.5)
+    g.sweep(1)
+    o.sweep(1)
+    for m in range(3):
+        _assert_factor_close(g.factors(m).astype(np.float64), o.factors(m), f"mode {m}")
+
+
+_INTEROP = """
+import torch                       # first, so libntc binds to torch's HIP runtime
+import numpy as np
+import paper_2109_09534_amd as ntc
+import synth
+assert torch.cuda.is_available()
+ntc.lib()
+assert len(ntc.hip_runtimes()) == 1, ntc.hip_runtimes()
+p = synth.c0(seed=2)
+init = synth.uniform_init(p.dims, 8, 5, 1.0)
+a = ntc.Problem(p.dims, p.coords, p.values, 8, init=init, stream=0)
+s = torch.cuda.Stream()
+with torch.cuda.stream(s):
+    b = ntc.Problem(p.dims, p.coords, p.values, 8, init=init, stream=s, torch_allocator=True)
+    b.sweep(3)
+    dev = torch.empty(p.dims[0] * 8, dtype=torch.float32, device="cuda")
+    b.factors_into(0, dev)
+s.synchronize()
+a.sweep(3)
+assert np.array_equal(a.factors(0), b.factors(0))
+assert np.array_equal(a.factors(0).reshape(-1), dev.cpu().numpy())
+b.close()
+print("interop ok", flush=True)
+"""
+
+
+@pytest.mark.timeout(400)
+def test_torch_stream_and_allocator_interop_in_a_fresh_process():
+    """torch's stream and caching allocator drive the same kernels and give
+    bit-identical results (child process: torch must load the runtime first)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _INTEROP], cwd=root, capture_output=True, text=True, timeout=380,
+                       env=dict(os.environ, PYTHONPATH=root))
+    _say(r.stdout[-2000:], r.stderr[-2000:])
+    assert r.returncode == 0 and "interop ok" in r.stdout

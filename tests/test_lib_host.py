@@ -1,0 +1,97 @@
+"""CPU checks of libntc: it loads, exports every entry point of include/ntc.h,
+and its host-side parts (sampler copy, CSR build, argument checks) agree
+with the oracle bit for bit.  No compute call touches a device here."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2109_09534_amd as ntc
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(ntc_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_entry_point():
+    L = ntc.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", ntc.library_path()], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ntc_[a-z_0-9]+)$", out, flags=re.M))
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(L, name)
+    # the binding wraps every declared entry point
+    wrapped = {n for n, _, _ in ntc._SIGNATURES}
+    assert set(declared) <= wrapped, set(declared) - wrapped
+    assert b"gfx950" in L.ntc_version()
+
+
+def test_host_sampler_is_bit_identical_to_the_oracle_sampler():
+    rng = np.random.default_rng(0)
+    for _ in range(400):
+        n = int(rng.choice([1, 2, 3, 5, 9, 16, 17, 100, 1023, 1024, 1025, 70000, 2_000_001]))
+        c = float(rng.choice([0.02, 0.1, 0.5, 0.57, 1.0]))
+        args = dict(seed=int(rng.integers(0, 2**63)), k=int(rng.integers(0, 2**31)), mode=int(rng.integers(0, 8)),
+                    l=int(rng.integers(0, 5)), row=int(rng.integers(0, 2**31 - 1)))
+        if n * c > 300000:
+            c = 0.02
+        a = ntc.host_sample(n=n, c=c, **args)
+        b = O.sample_positions(n=n, c=c, **args)
+        assert np.array_equal(a, b), (n, c, args)
+
+
+def test_host_csr_is_bit_identical_to_the_oracle_csr():
+    for seed, dims, nnz in [(0, (30, 20, 10), 3000), (1, (7, 1, 9, 4), 200), (2, (1000, 50, 3), 120000)]:
+        p = synth.make_problem(dims, nnz, 2, seed=seed, zipf_s=1.1 if nnz > 10000 else None)
+        o = O.Oracle(p.dims, p.coords, p.values, 2)
+        for m in range(len(dims)):
+            rp, perm = ntc.host_csr(p.dims, p.coords, m)
+            orp, operm = o.csr(m)
+            assert np.array_equal(rp, orp)
+            assert np.array_equal(perm, operm)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(rank=0), "rank"), (dict(rank=65), "rank"), (dict(c=0.0), "c must"), (dict(c=1.5), "c must"),
+    (dict(lam=-1.0), "lambda"), (dict(max_inner=0), "max_inner"), (dict(power_iters=-1), "power_iters"),
+])
+def test_create_rejects_invalid_parameters_before_touching_a_device(kw, msg):
+    p = synth.tiny(seed=0)
+    args = dict(rank=3)
+    args.update(kw)
+    rank = args.pop("rank")
+    with pytest.raises(ntc.NtcError) as e:
+        ntc.Problem(p.dims, p.coords, p.values, rank, stream=0, **args)
+    assert e.value.status == ntc.NTC_EINVAL and msg in str(e.value)
+
+
+def test_create_rejects_bad_data():
+    p = synth.tiny(seed=0)
+    bad = p.coords.copy()
+    bad[3, 1] = p.dims[1]
+    with pytest.raises(ntc.NtcError, match="coordinate out of range"):
+        ntc.Problem(p.dims, bad, p.values, 3, stream=0)
+    v = p.values.copy()
+    v[0] = np.nan
+    with pytest.raises(ntc.NtcError, match="non-finite"):
+        ntc.Problem(p.dims, p.coords, v, 3, stream=0)
+    init = synth.uniform_init(p.dims, 3, 0)
+    init[1][0, 0] = -1.0
+    with pytest.raises(ntc.NtcError, match="negative"):
+        ntc.Problem(p.dims, p.coords, p.values, 3, init=init, stream=0)
+    with pytest.raises(ntc.NtcError, match="nmodes"):
+        ntc.Problem([5], np.zeros((0, 1), np.int32), np.zeros(0, np.float32), 3, stream=0)

@@ -151,6 +151,31 @@ ntc_status ntc_host_sample(uint64_t seed, int64_t k, int32_t mode, int32_t l, in
 ntc_status ntc_host_csr(int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords,
                         int32_t mode, int64_t *rowptr_out, int64_t *perm_out);
 
+/* Block until all work enqueued on h's stream has finished. */
+ntc_status ntc_synchronize(ntc_handle h);
+
+/* Enqueue `nsweeps` sweeps (as ntc_sweep) between two HIP events recorded on
+ * h's stream, synchronise, and return the elapsed device time in *ms. */
+ntc_status ntc_time_sweeps(ntc_handle h, int32_t nsweeps, double *ms);
+
+/* One launch of a sweep as seen by ntc_profile_sweep. */
+typedef struct ntc_launch_record {
+    int32_t kernel;  /* 0: row items (sample, gather, gradient, Hessian, and the
+                        power method + step for rows held by one item);
+                        1: finalize of rows split over several items */
+    int32_t mode;    /* mode being updated */
+    int32_t inner;   /* inner step l of Alg. 1 */
+    int32_t blocks;  /* workgroups launched */
+    int64_t samples; /* sampled entries the launch consumes */
+    int64_t rows;    /* rows whose step (L_p, projection, extrapolation) it performs */
+    double ms;       /* duration between HIP events around the launch */
+} ntc_launch_record;
+
+/* Run ONE sweep exactly as ntc_sweep does (k advances), recording HIP
+ * events around every kernel launch; writes up to `cap` records in launch
+ * order and the number of launches to *count.  Synchronising. */
+ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, int32_t *count);
+
 /* Release all device and host memory of h (NULL is accepted). */
 ntc_status ntc_release(ntc_handle h);
 

@@ -68,6 +68,12 @@ class _Params(ctypes.Structure):
     ]
 
 
+class LaunchRecord(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("mode", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("blocks", ctypes.c_int32), ("samples", ctypes.c_int64), ("rows", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point of include/ntc.h
@@ -89,6 +95,10 @@ _SIGNATURES = [
     ("ntc_host_sample", ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _i32p, _i64p]),
     ("ntc_host_csr", ctypes.c_int, [ctypes.c_int32, _i64p, ctypes.c_int64, _i32p, ctypes.c_int32, _i64p, _i64p]),
+    ("ntc_synchronize", ctypes.c_int, [ctypes.c_void_p]),
+    ("ntc_time_sweeps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p]),
+    ("ntc_profile_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(LaunchRecord), ctypes.c_int32,
+                                         _i32p]),
     ("ntc_release", ctypes.c_int, [ctypes.c_void_p]),
     ("ntc_last_error", ctypes.c_char_p, []),
     ("ntc_version", ctypes.c_char_p, []),
@@ -268,6 +278,24 @@ class Problem:
     # ---------------------------------------------------------------- method
     def sweep(self, n: int = 1):
         _check(lib().ntc_sweep(self._h, n))
+
+    def synchronize(self):
+        _check(lib().ntc_synchronize(self._h))
+
+    def time_sweeps(self, n: int) -> float:
+        """Device milliseconds of `n` sweeps between HIP events on the handle's stream."""
+        ms = ctypes.c_double(0.0)
+        _check(lib().ntc_time_sweeps(self._h, n, ctypes.byref(ms)))
+        return ms.value
+
+    def profile_sweep(self):
+        """One sweep with HIP events around every launch: list of dicts."""
+        cap = 4096
+        buf = (LaunchRecord * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().ntc_profile_sweep(self._h, buf, cap, ctypes.byref(cnt)))
+        return [dict(kernel=("row_items", "row_finalize")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
+                     samples=r.samples, rows=r.rows, ms=r.ms) for r in buf[: min(cnt.value, cap)]]
 
     def update_mode(self, mode: int):
         _check(lib().ntc_update_mode(self._h, mode))

@@ -154,6 +154,7 @@ struct ModeState {
     int32_t n_slots = 0;
     int64_t samples = 0;
     int64_t active_rows = 0;
+    int64_t fused_rows = 0;
     std::vector<int64_t> h_rowptr;
 };
 
@@ -273,12 +274,44 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     return a;
 }
 
-ntc_status enqueue_mode(ntc_problem *h, int mode)
+// Optional per-launch event timing (ntc_profile_sweep).
+struct LaunchProbe {
+    std::vector<ntc_launch_record> rec;
+    std::vector<hipEvent_t> ev;  // two per launch
+};
+
+ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
 {
+    const ModeState &md = h->md[mode];
     for (int l = 0; l < h->max_inner; ++l) {
         const ntc::RowArgs a = row_args(h, mode, l);
-        NTC_HIP(ntc::launch_row_items(a, h->RP, h->bf16, h->stream));
-        NTC_HIP(ntc::launch_row_finalize(a, h->RP, h->bf16, h->stream));
+        for (int kern = 0; kern < 2; ++kern) {
+            if ((kern == 0 ? md.n_items : md.n_split) <= 0)
+                continue;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (probe) {
+                NTC_HIP(hipEventCreate(&e0));
+                NTC_HIP(hipEventCreate(&e1));
+                probe->ev.push_back(e0);
+                probe->ev.push_back(e1);
+                NTC_HIP(hipEventRecord(e0, h->stream));
+            }
+            if (kern == 0)
+                NTC_HIP(ntc::launch_row_items(a, h->RP, h->bf16, h->stream));
+            else
+                NTC_HIP(ntc::launch_row_finalize(a, h->RP, h->bf16, h->stream));
+            if (probe) {
+                NTC_HIP(hipEventRecord(e1, h->stream));
+                ntc_launch_record r{};
+                r.kernel = kern;
+                r.mode = mode;
+                r.inner = l;
+                r.blocks = kern == 0 ? md.n_items : md.n_split;
+                r.samples = kern == 0 ? md.samples : 0;
+                r.rows = kern == 0 ? md.fused_rows : md.n_split;
+                probe->rec.push_back(r);
+            }
+        }
     }
     return NTC_OK;
 }
@@ -421,6 +454,7 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
             md.samples += b;
             md.active_rows += 1;
             if (b <= smax) {
+                md.fused_rows += 1;
                 items.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
             } else {
                 const int32_t s0 = slot;
@@ -699,6 +733,61 @@ ntc_status ntc_host_csr(int32_t nmodes, const int64_t *dims, int64_t nnz, const 
     std::vector<int64_t> rp;
     csr_build(nmodes, dims, nnz, coords, nullptr, mode, record_words(nmodes), rp, nullptr, perm_out);
     std::memcpy(rowptr_out, rp.data(), rp.size() * sizeof(int64_t));
+    return NTC_OK;
+}
+
+ntc_status ntc_synchronize(ntc_handle h)
+{
+    if (!h)
+        return fail(NTC_EINVAL, "null handle");
+    return sync(h);
+}
+
+ntc_status ntc_time_sweeps(ntc_handle h, int32_t nsweeps, double *ms)
+{
+    if (!h || !ms)
+        return fail(NTC_EINVAL, "null argument");
+    hipEvent_t e0, e1;
+    NTC_HIP(hipEventCreate(&e0));
+    NTC_HIP(hipEventCreate(&e1));
+    NTC_HIP(hipEventRecord(e0, h->stream));
+    ntc_status s = ntc_sweep(h, nsweeps);
+    if (s != NTC_OK)
+        return s;
+    NTC_HIP(hipEventRecord(e1, h->stream));
+    NTC_HIP(hipEventSynchronize(e1));
+    float t = 0.0f;
+    NTC_HIP(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t;
+    return NTC_OK;
+}
+
+ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, int32_t *count)
+{
+    if (!h || !count || (cap > 0 && !out))
+        return fail(NTC_EINVAL, "null argument");
+    LaunchProbe probe;
+    ntc_status s = NTC_OK;
+    for (int m = 0; m < h->N && s == NTC_OK; ++m)
+        s = enqueue_mode(h, m, &probe);
+    if (s == NTC_OK)
+        h->k += 1;
+    const hipError_t se = hipStreamSynchronize(h->stream);
+    for (size_t i = 0; i < probe.rec.size(); ++i) {
+        float t = 0.0f;
+        if (se == hipSuccess && hipEventElapsedTime(&t, probe.ev[2 * i], probe.ev[2 * i + 1]) == hipSuccess)
+            probe.rec[i].ms = t;
+        if (static_cast<int32_t>(i) < cap)
+            out[i] = probe.rec[i];
+    }
+    for (hipEvent_t e : probe.ev)
+        (void)hipEventDestroy(e);
+    if (s != NTC_OK)
+        return s;
+    NTC_HIP(se);
+    *count = static_cast<int32_t>(probe.rec.size());
     return NTC_OK;
 }
 

@@ -19,6 +19,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -48,6 +50,18 @@ class Problem:
 
 
 # ---------------------------------------------------------------- index sets
+_CHUNK = 1 << 22          # draws per child generator (fixed: results do not depend on thread count)
+_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _pmap(fn, items):
+    items = list(items)
+    if _THREADS == 1 or len(items) == 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(_THREADS) as ex:
+        return list(ex.map(fn, items))
+
+
 def _zipf_cdf(n: int, s: float) -> np.ndarray:
     w = np.arange(1, n + 1, dtype=np.float64) ** (-s)
     c = np.cumsum(w)
@@ -55,14 +69,43 @@ def _zipf_cdf(n: int, s: float) -> np.ndarray:
     return c
 
 
-def _draw_mode(rng, n: int, count: int, zipf_s: Optional[float], relabel: np.ndarray,
-               cdf: Optional[np.ndarray]) -> np.ndarray:
-    if zipf_s is None:
-        return rng.integers(0, n, size=count, dtype=np.int64)
-    u = rng.random(count)
-    rank = np.searchsorted(cdf, u, side="right")        # 0-based rank, P(r) ~ (r+1)^-s
-    np.minimum(rank, n - 1, out=rank)
-    return relabel[rank]
+def _draw_keys(seed_seq, dims, strides, count, zipf_s, cdfs, relabels) -> np.ndarray:
+    """`count` linearised cell keys, i.i.d. per mode, in fixed-size chunks."""
+    nchunks = (count + _CHUNK - 1) // _CHUNK
+    children = seed_seq.spawn(nchunks)
+
+    def chunk(ci):
+        rng = np.random.default_rng(children[ci])
+        cnt = min(_CHUNK, count - ci * _CHUNK)
+        key = np.zeros(cnt, dtype=np.int64)
+        for m, d in enumerate(dims):
+            if zipf_s is None:
+                ix = rng.integers(0, d, size=cnt, dtype=np.int64)
+            else:
+                rank = np.searchsorted(cdfs[m], rng.random(cnt), side="right")
+                np.minimum(rank, d - 1, out=rank)
+                ix = relabels[m][rank]
+            key += ix * strides[m]
+        return key
+
+    return np.concatenate(_pmap(chunk, range(nchunks))) if nchunks else np.zeros(0, np.int64)
+
+
+_NB = 64   # hash buckets of the de-duplication (duplicates always share a bucket)
+
+
+def _buckets(keys: np.ndarray):
+    h = ((keys.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(58)).astype(np.uint8)
+    order = np.argsort(h, kind="stable")          # radix sort on 8-bit ids
+    ks = keys[order]
+    bounds = np.concatenate([[0], np.cumsum(np.bincount(h, minlength=_NB))])
+    return [ks[bounds[b]:bounds[b + 1]] for b in range(_NB)]
+
+
+def _merge_unique(state, keys: np.ndarray):
+    """state: _NB sorted arrays of distinct keys; returns state with `keys` added."""
+    new = _buckets(keys)
+    return _pmap(lambda b: np.union1d(state[b], new[b]), range(_NB))
 
 
 def distinct_cells(rng, dims: Sequence[int], nnz: int, zipf_s: Optional[float] = None) -> np.ndarray:
@@ -96,14 +139,18 @@ def distinct_cells(rng, dims: Sequence[int], nnz: int, zipf_s: Optional[float] =
         # dense fraction: a random subset of the grid directly
         keys = rng.choice(total, size=nnz, replace=False).astype(np.int64)
     else:
-        keys = np.empty(0, dtype=np.int64)
-        while keys.shape[0] < nnz:
-            deficit = nnz - keys.shape[0]
-            draw = int(deficit * 1.2) + 1024
-            new = np.zeros(draw, dtype=np.int64)
-            for m, d in enumerate(dims):
-                new += _draw_mode(rng, d, draw, zipf_s, relabels[m], cdfs[m]) * strides[m]
-            keys = np.unique(np.concatenate([keys, new]))
+        seq = np.random.SeedSequence(int(rng.integers(0, 2 ** 63)))
+        state = [np.zeros(0, np.int64)] * _NB
+        have, yield_rate = 0, 1.0
+        while have < nnz:
+            deficit = nnz - have
+            draw = int(deficit / max(yield_rate, 0.02) * 1.1) + 1024
+            state = _merge_unique(state, _draw_keys(seq.spawn(1)[0], dims, strides, draw, zipf_s, cdfs,
+                                                    relabels))
+            now = sum(x.shape[0] for x in state)
+            yield_rate = (now - have) / draw
+            have = now
+        keys = np.concatenate(state)        # deterministic order: bucket, then key
         keys = keys[rng.permutation(keys.shape[0])[:nnz]]
     coords = np.empty((nnz, len(dims)), dtype=np.int32)
     rem = keys
@@ -119,16 +166,33 @@ def planted_factors(rng, dims: Sequence[int], rank: int) -> List[np.ndarray]:
     return [rng.random((int(d), rank)) for d in dims]
 
 
-def planted_values(factors: Sequence[np.ndarray], coords: np.ndarray, chunk: int = 1 << 21) -> np.ndarray:
+def planted_values(factors: Sequence[np.ndarray], coords: np.ndarray, chunk: int = 1 << 20) -> np.ndarray:
     """FP64 entries of the planted CPD at ``coords`` (eq. Xo_densef)."""
     nnz = coords.shape[0]
     out = np.empty(nnz, dtype=np.float64)
-    for s in range(0, nnz, chunk):
+
+    def part(s):
         e = min(nnz, s + chunk)
-        acc = factors[0][coords[s:e, 0]].copy()
+        acc = factors[0][coords[s:e, 0]]
         for m in range(1, len(factors)):
-            acc *= factors[m][coords[s:e, m]]
+            acc = acc * factors[m][coords[s:e, m]]
         out[s:e] = acc.sum(axis=1)
+
+    _pmap(part, range(0, nnz, chunk))
+    return out
+
+
+def _normal(seed_seq, n: int, sigma: float) -> np.ndarray:
+    nchunks = (n + _CHUNK - 1) // _CHUNK
+    children = seed_seq.spawn(max(nchunks, 1))
+    out = np.empty(n, dtype=np.float64)
+
+    def part(ci):
+        s = ci * _CHUNK
+        e = min(n, s + _CHUNK)
+        out[s:e] = np.random.default_rng(children[ci]).normal(0.0, sigma, size=e - s)
+
+    _pmap(part, range(nchunks))
     return out
 
 
@@ -165,7 +229,8 @@ def make_problem(dims: Sequence[int], nnz: int, planted_rank: int, *, rank: Opti
     if value_model == "ratings":
         lo, hi = float(xo.min()), float(xo.max())
         xo = 1.0 + 4.0 * (xo - lo) / (hi - lo if hi > lo else 1.0)
-    noise = rng.normal(0.0, math.sqrt(noise_var), size=nnz) if noise_var > 0 else np.zeros(nnz)
+    noise = (_normal(np.random.SeedSequence(int(rng.integers(0, 2 ** 63))), nnz, math.sqrt(noise_var))
+             if noise_var > 0 else np.zeros(nnz))
     x = xo + noise
     if value_model == "ratings":
         x = np.clip(np.rint(x), 1.0, 5.0)

@@ -400,7 +400,7 @@ def test_planted_recovery_on_the_cpu_sized_workload():
     o = O.Oracle(p.dims, p.coords, p.values, 8, c=0.5, lam=1e-3, seed=0,
                  test_coords=p.test_coords, test_values=p.test_values)
     before = o.loss()[3]
-    o.sweep(500)
+    o.sweep(1000)
     after = o.loss()[3]
     assert after < before
     assert after <= 1e-2, after

@@ -128,7 +128,7 @@ def main():
     k1_bytes = k1_ms = 0.0
     sweep_bytes = 0
     for rec in launches:
-        if rec["kernel"] == "row_items":
+        if rec["kernel"] in ("row_items", "row_tiny"):
             per_upd, b_upd, b_rows = algorithmic_bytes(p.nmodes, R, rec["samples"], rec["rows"], max_inner,
                                                        args.bf16)
             k1_bytes += b_upd + b_rows

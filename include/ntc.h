@@ -62,7 +62,8 @@ typedef struct ntc_params {
     uint64_t seed;        /* Philox key of the minibatch sampler and the default init */
     int32_t gather_bf16;  /* 1: gather other-mode factor rows from a BF16 shadow copy
                              (FP32 master factors, FP32 accumulation) */
-    int32_t reserved0;
+    int32_t tiny_max;     /* schedule: rows with 1 <= B_p <= tiny_max run one row per lane
+                             (R <= 16 only); -1 = default (4), 0 = off, at most 4 */
     int64_t n_test;             /* optional held-out entries for ntc_loss (0 = none) */
     const int32_t *test_coords; /* [n_test][nmodes], host, copied */
     const float *test_values;   /* [n_test], host, copied */
@@ -72,11 +73,17 @@ typedef struct ntc_params {
     ntc_alloc_fn dev_alloc;     /* optional; NULL = hipMalloc */
     ntc_free_fn dev_free;
     void *alloc_ctx;
+    int32_t item_samples;       /* schedule: sampled entries per work item; longer minibatches
+                                   are split over several items (0 = default) */
+    int32_t overlap;            /* schedule: 1 = run the one-row-per-lane launch on a second
+                                   stream concurrently with the other rows (default), 0 = serial */
 } ntc_params;
 
 /* Fill *p with defaults: c = 0.1, lambda = 1e-3, max_inner = 1,
  * power_iters = 20, seed = 0, FP32 gathers, no test set, default init,
- * null stream, hipMalloc. */
+ * null stream, hipMalloc, default schedule (tiny_max = -1, item_samples = 0,
+ * overlap = 1).  The schedule changes the order of floating-point sums
+ * only, never the sampled entries. */
 void ntc_params_default(ntc_params *p);
 
 /* Create a problem from the observed entries (Section II: X on Omega).
@@ -162,7 +169,8 @@ ntc_status ntc_time_sweeps(ntc_handle h, int32_t nsweeps, double *ms);
 typedef struct ntc_launch_record {
     int32_t kernel;  /* 0: row items (sample, gather, gradient, Hessian, and the
                         power method + step for rows held by one item);
-                        1: finalize of rows split over several items */
+                        1: finalize of rows split over several items;
+                        2: rows with at most 4 sampled entries, one per lane */
     int32_t mode;    /* mode being updated */
     int32_t inner;   /* inner step l of Alg. 1 */
     int32_t blocks;  /* workgroups launched */

@@ -69,7 +69,9 @@ def lib():
         L.ora_feistel_rounds.restype = ctypes.c_int
         L.ora_feistel_rounds.argtypes = [ctypes.c_int]
         L.ora_feistel_net.restype = ctypes.c_uint32
-        L.ora_feistel_net.argtypes = [ctypes.c_uint32, ctypes.c_int, _u32p]
+        L.ora_feistel_net.argtypes = [ctypes.c_uint32, ctypes.c_int64, _u32p]
+        L.ora_feistel_domain.restype = ctypes.c_int64
+        L.ora_feistel_domain.argtypes = [ctypes.c_int64]
         L.ora_feistel_pos.restype = ctypes.c_uint32
         L.ora_feistel_pos.argtypes = [ctypes.c_uint32, ctypes.c_int64, _u32p]
         L.ora_sample_size.restype = ctypes.c_int64
@@ -113,9 +115,14 @@ def feistel_rounds(w: int) -> int:
     return int(lib().ora_feistel_rounds(w))
 
 
-def feistel_net(x: int, w: int, keys) -> int:
+def feistel_net(x: int, n: int, keys) -> int:
+    """One pass of the network for a row of length n (x < feistel_domain(n))."""
     k = np.ascontiguousarray(keys, dtype=np.uint32)
-    return int(lib().ora_feistel_net(x, w, _p(k, _u32p)))
+    return int(lib().ora_feistel_net(x, n, _p(k, _u32p)))
+
+
+def feistel_domain(n: int) -> int:
+    return int(lib().ora_feistel_domain(n))
 
 
 def feistel_pos(j: int, n: int, keys) -> int:

@@ -35,10 +35,11 @@
  *   - the CSR of mode m is a stable sort of the COO entries by i_m.
  *
  * Philox4x32-10 follows Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
- * as easy as 1, 2, 3" (SC'11).  The Feistel network is an unbalanced
- * Luby-Rackoff construction (8 rounds, 24 on domains of at most 16 words)
- * restricted to [0, n) by cycle walking (Black and Rogaway, "Ciphers with
- * arbitrary finite domains", 2002).
+ * as easy as 1, 2, 3" (SC'11).  The permutation of [0, n) is a Feistel
+ * network over a mixed-radix domain Z_A x Z_B with modular addition (the
+ * FFX construction of Bellare, Rogaway and Spies, 2010; 8 rounds, 24 on
+ * domains of at most 16 words), restricted to [0, n) by cycle walking
+ * (Black and Rogaway, "Ciphers with arbitrary finite domains", 2002).
  */
 #include <math.h>
 #include <stdint.h>
@@ -121,19 +122,20 @@ void ora_sample_keys(uint64_t seed, int64_t k, int32_t mode, int32_t l, int64_t 
 }
 
 /* ----------------------------------------------------------------- Feistel */
-/* Round function: key-xor then a multiply/xor-shift finaliser on 32 bits. */
+/* Round function on 32 bits: key xor, then two rounds of xor-shift and a
+ * multiply of the low 24 bits by a 24-bit odd constant (low 32 bits kept). */
 static uint32_t feistel_f(uint32_t x, uint32_t key)
 {
     uint32_t h = x ^ key;
     h ^= h >> 16;
-    h *= 0x7FEB352Du;
-    h ^= h >> 15;
-    h *= 0x846CA68Bu;
+    h = (h & 0xFFFFFFu) * 0x9E3779u;
+    h ^= h >> 13;
+    h = (h & 0xFFFFFFu) * 0xC2B2AEu;
     h ^= h >> 16;
     return h;
 }
 
-/* Width of the permuted domain: the smallest w >= 2 with 2^w >= n. */
+/* w = the smallest integer >= 2 with 2^w >= n. */
 int ora_feistel_width(int64_t n)
 {
     int w = 2;
@@ -142,41 +144,55 @@ int ora_feistel_width(int64_t n)
     return w;
 }
 
-/* Number of rounds of the network on w-bit words: 24 when w <= 4 (tiny
- * domains need many rounds before every subset is about equally likely),
- * 8 otherwise. */
+/* Number of rounds: 24 when w <= 4 (tiny domains need many rounds before
+ * every subset is about equally likely), 8 otherwise. */
 int ora_feistel_rounds(int w) { return w <= 4 ? 24 : 8; }
 
-/* One pass of the unbalanced network on w-bit words: the high part has
- * ceil(w/2) bits, the low part floor(w/2).  Even rounds xor the high part
- * with F(low, kappa_r), odd rounds xor the low part with F(high, kappa_r),
- * where kappa_r = K[r mod 4] ^ (r * 0x9E3779B9).  Each round is a bijection,
- * so the network is a permutation of [0, 2^w). */
-uint32_t ora_feistel_net(uint32_t x, int w, const uint32_t keys[4])
+/* One pass of the Feistel network over the mixed-radix domain Z_A x Z_B,
+ * A = 2^ceil(w/2), B = ceil(n / A), the word x = lo * A + hi with hi in Z_A,
+ * lo in Z_B (FFX-style rounds with modular addition, Bellare, Rogaway and
+ * Spies 2010).  Round r uses kappa_r = K[r mod 4] ^ (r * 0x9E3779B9); even
+ * rounds set hi = (hi + F(lo, kappa_r)) mod A, odd rounds set
+ * lo = (lo + ((F(hi, kappa_r) mod 2^16) * B) div 2^16) mod B.  Each round is a
+ * bijection of Z_A x Z_B, so the pass permutes [0, A*B), and A*B - n < A. */
+uint32_t ora_feistel_net(uint32_t x, int64_t n, const uint32_t keys[4])
 {
-    int bh = (w + 1) / 2, bl = w / 2;
-    uint32_t mh = (1u << bh) - 1u;
-    uint32_t ml = (1u << bl) - 1u;
-    uint32_t hi = x >> bl, lo = x & ml;
+    int w = ora_feistel_width(n);
+    int a = (w + 1) / 2;
+    uint32_t A = 1u << a;
+    uint32_t B = (uint32_t)((n + A - 1) / A);
+    uint32_t hi = x & (A - 1u), lo = x >> a;
     int rounds = ora_feistel_rounds(w);
     for (int r = 0; r < rounds; ++r) {
         uint32_t kappa = keys[r & 3] ^ (uint32_t)((uint32_t)r * 0x9E3779B9u);
-        if ((r & 1) == 0)
-            hi ^= feistel_f(lo, kappa) & mh;
-        else
-            lo ^= feistel_f(hi, kappa) & ml;
+        if ((r & 1) == 0) {
+            hi = (hi + feistel_f(lo, kappa)) & (A - 1u);
+        } else {
+            uint32_t t = ((feistel_f(hi, kappa) & 0xFFFFu) * B) >> 16;
+            lo = lo + t;
+            if (lo >= B)
+                lo -= B;
+        }
     }
-    return (hi << bl) | lo;
+    return (lo << a) | hi;
 }
 
-/* pi(j): the network applied to j, re-applied while the image is >= n. */
+/* pi(j): the network applied to j, re-applied while the image is >= n
+ * (cycle walking, Black and Rogaway 2002). */
 uint32_t ora_feistel_pos(uint32_t j, int64_t n, const uint32_t keys[4])
 {
-    int w = ora_feistel_width(n);
-    uint32_t x = ora_feistel_net(j, w, keys);
+    uint32_t x = ora_feistel_net(j, n, keys);
     while ((int64_t)x >= n)
-        x = ora_feistel_net(x, w, keys);
+        x = ora_feistel_net(x, n, keys);
     return x;
+}
+
+/* Size A*B of the permuted word domain for a row of length n. */
+int64_t ora_feistel_domain(int64_t n)
+{
+    int w = ora_feistel_width(n);
+    int64_t A = (int64_t)1 << ((w + 1) / 2);
+    return A * ((n + A - 1) / A);
 }
 
 /* B_{l,p} = floor(c * n): one binary64 multiply, then floor. */

@@ -56,7 +56,7 @@ class _Params(ctypes.Structure):
         ("power_iters", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("gather_bf16", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("tiny_max", ctypes.c_int32),
         ("n_test", ctypes.c_int64),
         ("test_coords", _i32p),
         ("test_values", _f32p),
@@ -65,6 +65,8 @@ class _Params(ctypes.Structure):
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),
         ("alloc_ctx", ctypes.c_void_p),
+        ("item_samples", ctypes.c_int32),
+        ("overlap", ctypes.c_int32),
     ]
 
 
@@ -205,7 +207,7 @@ class Problem:
                  c: float = 0.1, lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
                  gather_bf16: bool = False, test_coords: Optional[np.ndarray] = None,
                  test_values: Optional[np.ndarray] = None, init: Optional[Sequence[np.ndarray]] = None,
-                 stream=None, torch_allocator: bool = False):
+                 stream=None, torch_allocator: bool = False, schedule: Optional[dict] = None):
         L = lib()
         self.dims = [int(d) for d in dims]
         self.N = len(self.dims)
@@ -219,6 +221,10 @@ class Problem:
         L.ntc_params_default(ctypes.byref(prm))
         prm.c, prm.lam, prm.max_inner, prm.power_iters, prm.seed = c, lam, max_inner, power_iters, seed
         prm.gather_bf16 = 1 if gather_bf16 else 0
+        for key, val in (schedule or {}).items():
+            if key not in ("tiny_max", "item_samples", "overlap"):
+                raise ValueError(f"unknown schedule field {key}")
+            setattr(prm, key, int(val))
         keep = [d, co, va]
         if test_coords is not None:
             tc = np.ascontiguousarray(test_coords, dtype=np.int32)
@@ -294,7 +300,7 @@ class Problem:
         buf = (LaunchRecord * cap)()
         cnt = ctypes.c_int32(0)
         _check(lib().ntc_profile_sweep(self._h, buf, cap, ctypes.byref(cnt)))
-        return [dict(kernel=("row_items", "row_finalize")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
+        return [dict(kernel=("row_items", "row_finalize", "row_tiny")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
                      samples=r.samples, rows=r.rows, ms=r.ms) for r in buf[: min(cnt.value, cap)]]
 
     def update_mode(self, mode: int):

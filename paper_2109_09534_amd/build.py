@@ -21,8 +21,8 @@ ARCH = "gfx950"
 SOURCES = ["ntc_host.cpp", "ntc_kernels.hip"]
 
 
-def build(verbose: bool = False) -> str:
-    out = LIB + ".tmp"
+def build(verbose: bool = False, out_path: str = LIB, defines=()) -> str:
+    out = out_path + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function",
@@ -31,6 +31,7 @@ def build(verbose: bool = False) -> str:
     for s in SOURCES:
         p = os.path.join(CSRC, s)
         srcs += (["-x", "hip", p] if s.endswith(".cpp") else [p])
+    cmd += [f"-D{d}" for d in defines]
     cmd += srcs
     cmd += ["-lpthread"]
     if verbose:
@@ -39,8 +40,8 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libntc.so")
-    os.replace(out, LIB)
-    return LIB
+    os.replace(out, out_path)
+    return out_path
 
 
 if __name__ == "__main__":

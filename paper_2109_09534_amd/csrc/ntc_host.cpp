@@ -34,9 +34,11 @@ ntc_status fail(ntc_status s, const std::string &msg)
             return fail(NTC_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_));         \
     } while (0)
 
+// Lanes per rank group: R <= 16 runs the group-per-item kernels (a 16-lane
+// DPP row per item); larger ranks the wave-per-item kernels.
 int padded_rank(int R)
 {
-    return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+    return R <= 16 ? 16 : R <= 32 ? 32 : 64;
 }
 
 int record_words(int nmodes)
@@ -48,7 +50,7 @@ int record_words(int nmodes)
 // 64/RP samples per step).
 int item_samples(int rp)
 {
-    return 512 * (64 / rp);
+    return rp == 16 ? 1024 : 512 * (64 / rp);
 }
 
 unsigned host_threads()
@@ -149,7 +151,11 @@ struct ModeState {
     uint32_t *records = nullptr;
     Item *items = nullptr;
     SplitRow *split = nullptr;
+    int32_t *tiny = nullptr;
+    int32_t n_tiny = 0;
+    int64_t tiny_samples = 0;
     int32_t n_items = 0;
+    int32_t n_partial = 0;
     int32_t n_split = 0;
     int32_t n_slots = 0;
     int64_t samples = 0;
@@ -170,6 +176,10 @@ struct ntc_problem {
     bool bf16 = false;
     int64_t k = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;   // second stream for the one-row-per-lane launches
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int tiny_max = ntc::kTinyB;
+    int item_samples = 0;
     int device = 0;
     ntc_alloc_fn alloc = nullptr;
     ntc_free_fn dfree = nullptr;
@@ -218,6 +228,14 @@ struct ntc_problem {
             else
                 (void)hipFree(p);
         }
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
+        if (ev_fork)
+            (void)hipEventDestroy(ev_fork);
+        if (ev_join)
+            (void)hipEventDestroy(ev_join);
     }
 };
 
@@ -247,6 +265,9 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.records = m.records;
     a.items = m.items;
     a.split = m.split;
+    a.tiny = m.tiny;
+    a.n_tiny = m.n_tiny;
+    a.c = h->c;
     int w = 0;
     for (int mm = 0; mm < h->N; ++mm) {
         if (mm == mode)
@@ -270,6 +291,7 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.max_inner = h->max_inner;
     a.power_iters = h->power_iters;
     a.n_items = m.n_items;
+    a.n_partial = m.n_partial;
     a.n_split = m.n_split;
     return a;
 }
@@ -285,32 +307,48 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
     const ModeState &md = h->md[mode];
     for (int l = 0; l < h->max_inner; ++l) {
         const ntc::RowArgs a = row_args(h, mode, l);
-        for (int kern = 0; kern < 2; ++kern) {
-            if ((kern == 0 ? md.n_items : md.n_split) <= 0)
+        // the one-row-per-lane rows are disjoint from the other rows: with a
+        // side stream they run concurrently (fork/join through events)
+        const bool fork = h->side && md.n_tiny > 0 && (md.n_items > 0 || md.n_split > 0);
+        if (fork) {
+            NTC_HIP(hipEventRecord(h->ev_fork, h->stream));
+            NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        }
+        for (int kern : {2, 0, 1}) {
+            const int32_t count = kern == 0 ? md.n_items : kern == 1 ? md.n_split : md.n_tiny;
+            if (count <= 0)
                 continue;
+            hipStream_t st = (kern == 2 && fork) ? h->side : h->stream;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (probe) {
                 NTC_HIP(hipEventCreate(&e0));
                 NTC_HIP(hipEventCreate(&e1));
                 probe->ev.push_back(e0);
                 probe->ev.push_back(e1);
-                NTC_HIP(hipEventRecord(e0, h->stream));
+                NTC_HIP(hipEventRecord(e0, st));
             }
             if (kern == 0)
-                NTC_HIP(ntc::launch_row_items(a, h->RP, h->bf16, h->stream));
+                NTC_HIP(ntc::launch_row_items(a, h->RP, h->bf16, st));
+            else if (kern == 1)
+                NTC_HIP(ntc::launch_row_finalize(a, h->RP, h->bf16, st));
             else
-                NTC_HIP(ntc::launch_row_finalize(a, h->RP, h->bf16, h->stream));
+                NTC_HIP(ntc::launch_row_tiny(a, h->bf16, st));
             if (probe) {
-                NTC_HIP(hipEventRecord(e1, h->stream));
+                NTC_HIP(hipEventRecord(e1, st));
                 ntc_launch_record r{};
                 r.kernel = kern;
                 r.mode = mode;
                 r.inner = l;
-                r.blocks = kern == 0 ? md.n_items : md.n_split;
-                r.samples = kern == 0 ? md.samples : 0;
-                r.rows = kern == 0 ? md.fused_rows : md.n_split;
+                r.blocks = kern == 0 ? (h->RP == 16 ? (md.n_items + 3) / 4 : md.n_items)
+                                     : kern == 1 ? md.n_split : (md.n_tiny + 255) / 256;
+                r.samples = kern == 0 ? md.samples - md.tiny_samples : kern == 1 ? 0 : md.tiny_samples;
+                r.rows = kern == 0 ? md.fused_rows : kern == 1 ? md.n_split : md.n_tiny;
                 probe->rec.push_back(r);
             }
+        }
+        if (fork) {
+            NTC_HIP(hipEventRecord(h->ev_join, h->side));
+            NTC_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
         }
     }
     return NTC_OK;
@@ -361,6 +399,10 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
         return fail(NTC_EINVAL, "max_inner must be in [1, 65535]");
     if (p.power_iters < 0)
         return fail(NTC_EINVAL, "power_iters must be >= 0");
+    if (p.tiny_max < -1 || p.tiny_max > ntc::kTinyB)
+        return fail(NTC_EINVAL, "tiny_max must be -1 or in [0, 4]");
+    if (p.item_samples < 0 || (p.item_samples > 0 && p.item_samples < 16))
+        return fail(NTC_EINVAL, "item_samples must be 0 or >= 16");
     if (p.n_test < 0 || (p.n_test > 0 && (!p.test_coords || !p.test_values)))
         return fail(NTC_EINVAL, "test set pointers are null");
     for (int m = 0; m < N; ++m)
@@ -406,7 +448,14 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
     h->alloc = p.dev_alloc;
     h->dfree = p.dev_free;
     h->actx = p.alloc_ctx;
+    h->tiny_max = p.tiny_max < 0 ? ntc::kTinyB : p.tiny_max;
+    h->item_samples = p.item_samples;
     NTC_HIP(hipGetDevice(&h->device));
+    if (p.overlap) {
+        NTC_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        NTC_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        NTC_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
     for (int m = 0; m < N; ++m)
         h->dims[m] = dims[m];
 
@@ -425,7 +474,7 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
     // CSR per mode and the static schedule
     std::vector<uint32_t> rec(static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw);
     const int rp = h->RP;
-    const int smax = item_samples(rp);
+    const int smax = h->item_samples > 0 ? h->item_samples : item_samples(rp);
     int32_t max_slots = 0;
     for (int m = 0; m < N; ++m) {
         ModeState &md = h->md[m];
@@ -446,16 +495,20 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
                 rows.push_back(static_cast<int32_t>(r));
         }
         std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return bsz[a] > bsz[b]; });
-        std::vector<Item> items;
+        std::vector<Item> items, whole;
         std::vector<SplitRow> split;
+        std::vector<int32_t> tiny;
         int32_t slot = 0;
         for (int32_t r : rows) {
             const int64_t b = bsz[r];
             md.samples += b;
             md.active_rows += 1;
-            if (b <= smax) {
+            if (rp == 16 && b <= h->tiny_max) {
+                tiny.push_back(r);
+                md.tiny_samples += b;
+            } else if (b <= smax) {
                 md.fused_rows += 1;
-                items.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
+                whole.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
             } else {
                 const int32_t s0 = slot;
                 for (int64_t j0 = 0; j0 < b; j0 += smax)
@@ -464,6 +517,12 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
                 split.push_back(SplitRow{r, s0, slot - s0, 0});
             }
         }
+        md.n_partial = static_cast<int32_t>(items.size());
+        items.insert(items.end(), whole.begin(), whole.end());
+        md.n_tiny = static_cast<int32_t>(tiny.size());
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.tiny), tiny.size() * sizeof(int32_t), "tiny rows"));
+        if (!tiny.empty())
+            NTC_HIP(hipMemcpy(md.tiny, tiny.data(), tiny.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         md.n_items = static_cast<int32_t>(items.size());
         md.n_split = static_cast<int32_t>(split.size());
         md.n_slots = slot;
@@ -531,6 +590,8 @@ void ntc_params_default(ntc_params *p)
     p->lambda = 1e-3;
     p->max_inner = 1;
     p->power_iters = 20;
+    p->tiny_max = -1;
+    p->overlap = 1;
 }
 
 ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords,
@@ -774,7 +835,9 @@ ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, 
         s = enqueue_mode(h, m, &probe);
     if (s == NTC_OK)
         h->k += 1;
-    const hipError_t se = hipStreamSynchronize(h->stream);
+    hipError_t se = hipStreamSynchronize(h->stream);
+    if (se == hipSuccess && h->side)
+        se = hipStreamSynchronize(h->side);
     for (size_t i = 0; i < probe.rec.size(); ++i) {
         float t = 0.0f;
         if (se == hipSuccess && hipEventElapsedTime(&t, probe.ev[2 * i], probe.ev[2 * i + 1]) == hipSuccess)

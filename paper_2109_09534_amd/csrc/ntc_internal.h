@@ -34,6 +34,7 @@ struct RowArgs {
     const uint32_t *records;      // [nnz][rec_words]: other-mode coords (increasing mode), value bits
     const Item *items;
     const SplitRow *split;
+    const int32_t *tiny;          // rows whose minibatch has 1..kTinyB samples (R <= 16 kernels)
     const float *gath[kMaxModes - 1];     // other modes' FP32 factors, increasing mode order
     const uint16_t *gath16[kMaxModes - 1];// their BF16 shadows (precision form)
     float *A;                     // this mode's factor (A_l in, A_{l+1} out, in place)
@@ -43,6 +44,7 @@ struct RowArgs {
     uint64_t seed;
     int64_t k;
     double lambda;
+    double c;
     int32_t mode;
     int32_t l;
     int32_t nmodes;
@@ -51,8 +53,13 @@ struct RowArgs {
     int32_t max_inner;
     int32_t power_iters;
     int32_t n_items;
+    int32_t n_partial;            // the first n_partial items write partial slots (split rows)
     int32_t n_split;
+    int32_t n_tiny;
 };
+
+// Rows whose minibatch has at most this many samples run one row per lane.
+constexpr int kTinyB = 4;
 
 struct LossArgs {
     const int64_t *rowptr0;       // CSR of mode 0
@@ -76,6 +83,7 @@ constexpr int kLossThreads = 256;
 
 hipError_t launch_row_items(const RowArgs &a, int rp, bool bf16, hipStream_t s);
 hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t s);
+hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s);
 hipError_t launch_loss(const LossArgs &a, hipStream_t s);
 hipError_t launch_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale,
                               hipStream_t s);

@@ -18,6 +18,16 @@
 #include "ntc_internal.h"
 #include "ntc_rng.h"
 
+#ifndef NTC_HACC_LDS
+#define NTC_HACC_LDS 1
+#endif
+#ifndef NTC_SPLIT_LAUNCH
+#define NTC_SPLIT_LAUNCH 0
+#endif
+#ifndef NTC_WAVES3
+#define NTC_WAVES3 4
+#endif
+
 namespace ntc {
 namespace {
 
@@ -271,6 +281,632 @@ __global__ __launch_bounds__(64) void k_row_finalize(const RowArgs a)
     finish_row<RP, BF16>(a, sr.row, lane, g, h, y, s_v);
 }
 
+// ------------------------------------------------- group-per-item (R <= 16)
+//
+// For R <= 16 every work item is owned by one 16-lane group (one DPP row),
+// so a wave advances four rows at once.  Inside a row: k.y by a four-step
+// DPP butterfly; the row Hessian k k^T by one v_mfma_f32_16x16x1f32 per step,
+// whose four 16x16 output blocks are the four groups' rank-1 updates (FP32
+// over a batch of 16 samples, then added into FP64); the power method in a
+// skewed layout (lane r keeps H[r][sigma_s(r)] for the 16 row rotations
+// sigma_s, so H v is 16 FMAs against row-rotated copies of v).  A batch of
+// 16 samples per group is mapped one sample per lane for the sampler and the
+// record fetch, staged in LDS, and all factor gathers of the batch are
+// issued before any arithmetic.
+
+// DPP controls (gfx9): quad permutations, half-row and row mirrors, row rotations.
+constexpr int kDppXor1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+constexpr int kDppRor = 0x120;       // + s: row_ror:s
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 16 lanes of a DPP row; every lane gets the same bits (each
+// step pairs lanes symmetrically).
+__device__ __forceinline__ float row_sum_f32(float x)
+{
+    x += dpp_f32<kDppXor1>(x);
+    x += dpp_f32<kDppXor2>(x);
+    x += dpp_f32<kDppHalfMirror>(x);
+    x += dpp_f32<kDppMirror>(x);
+    return x;
+}
+
+__device__ __forceinline__ double row_sum_f64(double x)
+{
+    x += dpp_f64<kDppXor1>(x);
+    x += dpp_f64<kDppXor2>(x);
+    x += dpp_f64<kDppHalfMirror>(x);
+    x += dpp_f64<kDppMirror>(x);
+    return x;
+}
+
+// w += sum_{s>=1} hd[s] * v[sigma_s(lane)]
+template <int S>
+__device__ __forceinline__ void skew_matvec(const double (&hd)[16], double v, double &w)
+{
+    w = fma(hd[S], dpp_f64<kDppRor + S>(v), w);
+    if constexpr (S + 1 < 16)
+        skew_matvec<S + 1>(hd, v, w);
+}
+
+// Power method, step, projection and extrapolation for the row owned by
+// this 16-lane group.  Lane r holds g[r] (sampled gradient without ridge)
+// and hd[s] = H[r][sigma_s(r)] (sampled Hessian without ridge); lanes r >= R
+// hold zeros.  No cross-group communication.
+template <bool BF16>
+__device__ void finish_row16(const RowArgs &a, int row, int r, double g, double (&hd)[16], float y)
+{
+    const int R = a.R;
+    const bool live = r < R;
+    if (live) {
+        g += a.lambda * static_cast<double>(y);
+        hd[0] += a.lambda;  // sigma_0 is the identity: the diagonal
+    }
+    double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
+    bool vanished = false;
+    for (int t = 0; t < a.power_iters; ++t) {
+        double w = hd[0] * v;
+        skew_matvec<1>(hd, v, w);
+        const double n2 = row_sum_f64(w * w);
+        if (!(n2 > 0.0)) {
+            vanished = true;
+            break;
+        }
+        v = w / sqrt(n2);
+    }
+    double L = 0.0;
+    if (!vanished) {
+        double w = hd[0] * v;
+        skew_matvec<1>(hd, v, w);
+        L = row_sum_f64(v * w);
+    }
+    if (!live)
+        return;
+    const int64_t off = static_cast<int64_t>(row) * R + r;
+    const float a_prev = (a.l == 0) ? y : a.A[off];
+    const bool more = a.l + 1 < a.max_inner;
+    if (L > 0.0) {
+        double an = static_cast<double>(y) - g / L;
+        an = an > 0.0 ? an : 0.0;
+        const double sl = sqrt(L), sm = sqrt(a.lambda);
+        const double beta = (sl - sm) / (sl + sm);
+        const float af = static_cast<float>(an);
+        a.A[off] = af;
+        if (BF16)
+            a.A16[off] = f32_to_bf16(af);
+        if (more)
+            a.Y[off] = static_cast<float>(an + beta * (an - static_cast<double>(a_prev)));
+    } else if (more && a.l == 0) {
+        a.Y[off] = y;  // row skipped: Y_1 = Y_0
+    }
+}
+
+constexpr int kSlot16 = 16 + 16 * 16;  // doubles per partial slot: g[16], row-major H[16][16]
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Lane index within the DPP row that row_ror:s reads for this lane, for
+// s = 0..15: the skewed Hessian layout uses exactly the hardware rotation.
+__device__ __forceinline__ void ror_sources(int r, int (&sig)[16])
+{
+    sig[0] = r;
+#define NTC_SIG(S) sig[S] = __builtin_amdgcn_update_dpp(0, r, kDppRor + S, 0xF, 0xF, true)
+    NTC_SIG(1); NTC_SIG(2); NTC_SIG(3); NTC_SIG(4); NTC_SIG(5); NTC_SIG(6); NTC_SIG(7); NTC_SIG(8);
+    NTC_SIG(9); NTC_SIG(10); NTC_SIG(11); NTC_SIG(12); NTC_SIG(13); NTC_SIG(14); NTC_SIG(15);
+#undef NTC_SIG
+}
+
+// Per-group state of one work item of the group kernels.
+struct GroupItem {
+    Item it;
+    bool has;
+    int len;
+    int64_t base;
+    Prp prp;
+};
+
+__device__ __forceinline__ GroupItem load_group_item(const RowArgs &a, int id)
+{
+    GroupItem g;
+    g.has = id < a.n_items;
+    g.it = Item{0, 0, 0, -1};
+    if (g.has)
+        g.it = a.items[id];
+    g.base = 0;
+    int64_t n = 1;
+    if (g.has) {
+        g.base = a.rowptr[g.it.row];
+        n = a.rowptr[g.it.row + 1] - g.base;
+    }
+    g.len = g.it.j1 - g.it.j0;
+    g.prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.k, a.mode, a.l, g.it.row));
+    return g;
+}
+
+// Record of sample jb + r of the item (zeros past its end).
+template <int RW>
+__device__ __forceinline__ void fetch_record(const RowArgs &a, const GroupItem &g, int jb, int r, uint4 &w0,
+                                             uint4 &w1)
+{
+    w0 = make_uint4(0u, 0u, 0u, 0u);
+    w1 = make_uint4(0u, 0u, 0u, 0u);
+    if (jb + r < g.len) {
+        const uint32_t q = prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r));
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.records + (g.base + q) * RW);
+        w0 = src[0];
+        if (RW == 8)
+            w1 = src[1];
+    }
+}
+
+// LDS accesses of one wave are performed in order, so staging needs only a
+// compiler barrier, not a fence (a fence would also wait for the gathers in
+// flight).
+template <int RW>
+__device__ __forceinline__ void stage_record(uint4 *buf, int lane, const uint4 &w0, const uint4 &w1)
+{
+    buf[lane * (RW / 4)] = w0;
+    if (RW == 8)
+        buf[lane * (RW / 4) + 1] = w1;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Issue the factor gathers of one batch: f[mm][t] = U_mm[idx(t, mm), r].
+// Branch-free: every lane loads from an in-bounds address (a missing sample
+// has index 0 in LDS, a lane r >= R reads column 0) and the compute masks the
+// value, so all loads of the batch issue back to back.
+template <int NM, int RW, bool BF16>
+__device__ __forceinline__ void gather_batch(const RowArgs &a, const uint32_t *srec, int rr, float (&f)[NM - 1][16])
+{
+    const uint32_t R = static_cast<uint32_t>(a.R);
+#pragma unroll
+    for (int mm = 0; mm < NM - 1; ++mm) {
+        // 32-bit byte offsets from a wave-uniform base (factors are < 4 GiB)
+        const char *base = BF16 ? reinterpret_cast<const char *>(a.gath16[mm])
+                                : reinterpret_cast<const char *>(a.gath[mm]);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const uint32_t e = srec[t * RW + mm] * R + static_cast<uint32_t>(rr);
+            if (BF16)
+                f[mm][t] = bf16_to_f32(*reinterpret_cast<const uint16_t *>(base + e * 2u));
+            else
+                f[mm][t] = *reinterpret_cast<const float *>(base + e * 4u);
+        }
+    }
+}
+
+// Items of the group kernels with a compile-time mode count N <= 4.  The
+// batch loop is software-pipelined: while batch b is reduced, the factor
+// gathers of batch b+1 and the record fetches of batch b+2 are in flight
+// (records double-buffered in LDS, gathered values held raw until used).
+template <int NM, int RW, bool BF16, int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NTC_WAVES3 : 2))) void k_rows16(const RowArgs a)
+{
+    __shared__ uint4 s_rec[2][64 * (RW / 4)];
+    // FP64 sum of the MFMA blocks: register v of lane l at s_h[v * 64 + l]
+    __shared__ double s_h[16 * 64];
+#if !NTC_HACC_LDS
+    double hd[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+        hd[v] = 0.0;
+#endif
+    const int lane = threadIdx.x;
+    const int r = lane & 15;
+    const int grp = lane >> 4;
+    // partial items (slots) come first in the item list, whole rows after
+    const int first = KIND == 1 ? a.n_partial : 0;
+    const int last = KIND == 0 ? a.n_partial : a.n_items;
+    const int id = first + blockIdx.x * 4 + grp;
+    const GroupItem g = load_group_item(a, id < last ? id : a.n_items);
+    const int R = a.R;
+    const bool rlive = r < R;
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const float y = (g.has && rlive) ? ysrc[static_cast<int64_t>(g.it.row) * R + r] : 0.0f;
+
+    // the MFMA below reads all 64 lanes: the batch loop runs the same number
+    // of times in every group (the longest item of the wave); missing
+    // samples enter as k = 0
+    const int maxlen = max(max(__builtin_amdgcn_readlane(g.len, 0), __builtin_amdgcn_readlane(g.len, 16)),
+                           max(__builtin_amdgcn_readlane(g.len, 32), __builtin_amdgcn_readlane(g.len, 48)));
+    const int nb = (maxlen + 15) / 16;
+
+    double gd = 0.0;
+#if NTC_HACC_LDS
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+        s_h[v * 64 + lane] = 0.0;
+#endif
+
+    const int rr = rlive ? r : 0;
+    uint4 w0, w1;
+    float f[NM - 1][16];  // gathered factor values of the next batch to reduce
+    if (nb > 0) {
+        fetch_record<RW>(a, g, 0, r, w0, w1);
+        stage_record<RW>(s_rec[0], lane, w0, w1);
+        if (nb > 1) {
+            fetch_record<RW>(a, g, 16, r, w0, w1);
+            stage_record<RW>(s_rec[1], lane, w0, w1);
+        }
+        gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(s_rec[0]) + grp * 16 * RW, rr, f);
+    }
+    for (int bi = 0; bi < nb; ++bi) {
+        const int jb = bi * 16;
+        const int cnt = min(16, max(0, g.len - jb));
+        const int tmax = min(16, maxlen - jb);
+        // Khatri-Rao rows of this batch; this frees f for the next gathers
+        float kc[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            float k = f[0][t];
+#pragma unroll
+            for (int mm = 1; mm < NM - 1; ++mm)
+                k *= f[mm][t];
+            kc[t] = (t < cnt && rlive) ? k : 0.0f;
+        }
+        // issue order: records of batch b+2, then gathers of batch b+1, so
+        // that staging the records later waits only for the record loads
+        if (bi + 2 < nb)
+            fetch_record<RW>(a, g, jb + 32, r, w0, w1);
+        if (bi + 1 < nb)
+            gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(s_rec[(bi + 1) & 1]) + grp * 16 * RW,
+                                       rr, f);
+        const uint32_t *srec = reinterpret_cast<const uint32_t *>(s_rec[bi & 1]) + grp * 16 * RW;
+        float gf = 0.0f;
+        f32x16 acc = {0.0f};
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            if (t < tmax) {  // wave-uniform
+                const float k = kc[t];
+                const float x = __uint_as_float(srec[t * RW + NM - 1]);  // 0 for a missing sample
+                const float pred = row_sum_f32(k * y);
+                gf = fmaf(pred - x, k, gf);
+                // four independent rank-1 updates, one per group: block b += k_b k_b^T
+                acc = __builtin_amdgcn_mfma_f32_16x16x1f32(k, k, acc, 0, 0, 0);
+            }
+        }
+        gd += static_cast<double>(gf);
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+#if NTC_HACC_LDS
+            s_h[v * 64 + lane] += static_cast<double>(acc[v]);
+#else
+            hd[v] += static_cast<double>(acc[v]);
+#endif
+        __builtin_amdgcn_wave_barrier();  // the compute above read s_rec[bi & 1]
+        if (bi + 2 < nb)
+            stage_record<RW>(s_rec[bi & 1], lane, w0, w1);
+    }
+
+    // register v of lane l holds block v/4, row 4*(l/16) + v%4, column l%16:
+    // row r of this group's block is at v = 4*grp + r%4, lanes 16*(r/4) + q
+#if !NTC_HACC_LDS
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+        s_h[v * 64 + lane] = hd[v];
+#endif
+    __builtin_amdgcn_wave_barrier();
+    if (!g.has)
+        return;
+    const double *hrow = s_h + (4 * grp + (r & 3)) * 64 + 16 * (r >> 2);
+    if (KIND == 0 || (KIND == 2 && g.it.slot >= 0)) {
+        double *P = a.partials + static_cast<int64_t>(g.it.slot) * kSlot16;
+        P[r] = gd;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            P[16 + r * 16 + q] = hrow[q];
+        return;
+    } else {
+        int sig[16];
+        ror_sources(r, sig);
+        double hs[16];
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2)
+            hs[s2] = hrow[sig[s2]];
+        finish_row16<BF16>(a, g.it.row, r, gd, hs, y);
+    }
+}
+
+// Items of the group kernels for 5 <= N <= 8 (32-byte records): the same
+// computation without the software pipeline; the Khatri-Rao product is
+// accumulated over a runtime mode loop.
+template <bool BF16>
+__global__ __launch_bounds__(64) void k_rows16_nm(const RowArgs a)
+{
+    __shared__ uint4 s_rec[64 * 2];
+    __shared__ double s_h[4 * 256];
+    const int lane = threadIdx.x;
+    const int r = lane & 15;
+    const int grp = lane >> 4;
+    const int nm = a.nmodes;
+    const GroupItem g = load_group_item(a, blockIdx.x * 4 + grp);
+    const int R = a.R;
+    const bool rlive = r < R;
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const float y = (g.has && rlive) ? ysrc[static_cast<int64_t>(g.it.row) * R + r] : 0.0f;
+    const int maxlen = max(max(__builtin_amdgcn_readlane(g.len, 0), __builtin_amdgcn_readlane(g.len, 16)),
+                           max(__builtin_amdgcn_readlane(g.len, 32), __builtin_amdgcn_readlane(g.len, 48)));
+    double gd = 0.0;
+    double hd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        hd[q] = 0.0;
+    for (int jb = 0; jb < maxlen; jb += 16) {
+        const int cnt = min(16, max(0, g.len - jb));
+        const int tmax = min(16, maxlen - jb);
+        uint4 w0, w1;
+        fetch_record<8>(a, g, jb, r, w0, w1);
+        stage_record<8>(s_rec, lane, w0, w1);
+        const uint32_t *srec = reinterpret_cast<const uint32_t *>(s_rec) + grp * 16 * 8;
+        float kp[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            kp[t] = (t < cnt && rlive) ? 1.0f : 0.0f;
+        for (int mm = 0; mm < nm - 1; ++mm) {
+            float f[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                f[t] = 0.0f;
+                if (t < cnt && rlive) {
+                    const int64_t idx = srec[t * 8 + mm];
+                    f[t] = BF16 ? bf16_to_f32(a.gath16[mm][idx * R + r]) : a.gath[mm][idx * R + r];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                kp[t] *= f[t];
+        }
+        float gf = 0.0f;
+        f32x16 acc = {0.0f};
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            if (t < tmax) {
+                const float k = kp[t];
+                const float x = __uint_as_float(srec[t * 8 + nm - 1]);
+                const float pred = row_sum_f32(k * y);
+                gf = fmaf(pred - x, k, gf);
+                acc = __builtin_amdgcn_mfma_f32_16x16x1f32(k, k, acc, 0, 0, 0);
+            }
+        }
+        gd += static_cast<double>(gf);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            hd[q] += static_cast<double>(acc[q]);
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+        s_h[(v >> 2) * 256 + (4 * grp + (v & 3)) * 16 + r] = hd[v];
+    __builtin_amdgcn_wave_barrier();
+    if (!g.has)
+        return;
+    const double *hrow = s_h + grp * 256 + r * 16;
+    if (g.it.slot >= 0) {
+        double *P = a.partials + static_cast<int64_t>(g.it.slot) * kSlot16;
+        P[r] = gd;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            P[16 + r * 16 + q] = hrow[q];
+        return;
+    }
+    int sig[16];
+    ror_sources(r, sig);
+    double hs[16];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2)
+        hs[s2] = hrow[sig[s2]];
+    finish_row16<BF16>(a, g.it.row, r, gd, hs, y);
+}
+
+// Rows whose minibatch has at most kTinyB samples (R <= 16): one row per
+// lane, no cross-lane traffic.  The lane keeps the b sampled Khatri-Rao rows
+// k_j and applies the row Hessian as H v = sum_j k_j (k_j . v) + lambda v,
+// the same matrix as B^T diag(M_hat(p,:)) B + lambda I applied through its
+// rank-b factors, so each power-method product costs O(bR) instead of O(R^2).
+template <int NM, int RW, bool BF16>
+__global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= a.n_tiny)
+        return;
+    const int nm = (NM > 0) ? NM : a.nmodes;
+    const int R = a.R;
+    const int row = a.tiny[id];
+    const int64_t base = a.rowptr[row];
+    const int64_t n = a.rowptr[row + 1] - base;
+    const int b = static_cast<int>(minibatch_size(a.c, n));  // 1 .. kTinyB
+    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.k, a.mode, a.l, row));
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const int64_t roff = static_cast<int64_t>(row) * R;
+    float y[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        y[r] = r < R ? ysrc[roff + r] : 0.0f;
+
+    float kk[kTinyB][16];
+    float gf[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        gf[r] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kTinyB; ++j) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            kk[j][r] = 0.0f;
+        if (j < b) {
+            const uint32_t q = prp_index(prp, static_cast<uint32_t>(j));
+            const uint32_t *rec = a.records + (base + q) * RW;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                kk[j][r] = r < R ? 1.0f : 0.0f;
+            for (int mm = 0; mm < nm - 1; ++mm) {
+                const int64_t o = static_cast<int64_t>(rec[mm]) * R;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (r < R)
+                        kk[j][r] *= BF16 ? bf16_to_f32(a.gath16[mm][o + r]) : a.gath[mm][o + r];
+            }
+            const float x = __uint_as_float(rec[nm - 1]);
+            float pred = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                pred = fmaf(kk[j][r], y[r], pred);
+            const float res = pred - x;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                gf[r] = fmaf(res, kk[j][r], gf[r]);
+        }
+    }
+
+    // power method on H = sum_j k_j k_j^T + lambda I
+    const double lam = a.lambda;
+    double v[16];
+    const double v0 = 1.0 / sqrt(static_cast<double>(R));
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        v[r] = r < R ? v0 : 0.0;
+    auto apply_h = [&](const double (&x)[16], double (&out)[16]) {
+        double u[kTinyB];
+#pragma unroll
+        for (int j = 0; j < kTinyB; ++j) {
+            u[j] = 0.0;
+            if (j < b) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    u[j] = fma(static_cast<double>(kk[j][r]), x[r], u[j]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double o = lam * x[r];
+#pragma unroll
+            for (int j = 0; j < kTinyB; ++j)
+                if (j < b)
+                    o = fma(static_cast<double>(kk[j][r]), u[j], o);
+            out[r] = o;
+        }
+    };
+    double w[16];
+    bool vanished = false;
+    for (int t = 0; t < a.power_iters; ++t) {
+        apply_h(v, w);
+        double n2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            n2 = fma(w[r], w[r], n2);
+        if (!(n2 > 0.0)) {
+            vanished = true;
+            break;
+        }
+        const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = w[r] * inv;
+    }
+    double L = 0.0;
+    if (!vanished) {
+        apply_h(v, w);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            L = fma(v[r], w[r], L);
+    }
+    const bool more = a.l + 1 < a.max_inner;
+    if (L > 0.0) {
+        const double sl = sqrt(L), sm = sqrt(lam);
+        const double beta = (sl - sm) / (sl + sm);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r < R) {
+                const double g = static_cast<double>(gf[r]) + lam * static_cast<double>(y[r]);
+                double an = static_cast<double>(y[r]) - g / L;
+                an = an > 0.0 ? an : 0.0;
+                const float a_prev = (a.l == 0) ? y[r] : a.A[roff + r];
+                const float af = static_cast<float>(an);
+                a.A[roff + r] = af;
+                if (BF16)
+                    a.A16[roff + r] = f32_to_bf16(af);
+                if (more)
+                    a.Y[roff + r] = static_cast<float>(an + beta * (an - static_cast<double>(a_prev)));
+            }
+        }
+    } else if (more && a.l == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (r < R)
+                a.Y[roff + r] = y[r];
+    }
+}
+
+// Rows split over several items: one 256-thread block per row; its 16
+// groups sum the row's slots with a fixed stride, a fixed-order tree in LDS
+// combines them, and the first group finishes the row.
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_finalize16(const RowArgs a)
+{
+    __shared__ double s_part[16 * 16 * 17];
+    const SplitRow sr = a.split[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int r = tid & 15;
+    const int grp = tid >> 4;
+    double g = 0.0;
+    double hd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        hd[q] = 0.0;
+    int sig[16];
+    ror_sources(r, sig);
+    for (int s = grp; s < sr.nslots; s += 16) {
+        const double *P = a.partials + static_cast<int64_t>(sr.slot0 + s) * kSlot16;
+        g += P[r];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            hd[q] += P[16 + r * 16 + sig[q]];
+    }
+    double *mine = s_part + (grp * 16 + r) * 17;
+    mine[0] = g;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        mine[1 + q] = hd[q];
+    __syncthreads();
+    for (int st = 8; st > 0; st >>= 1) {
+        if (grp < st) {
+            const double *other = s_part + ((grp + st) * 16 + r) * 17;
+#pragma unroll
+            for (int q = 0; q < 17; ++q)
+                mine[q] += other[q];
+        }
+        __syncthreads();
+    }
+    if (grp != 0)
+        return;
+    g = mine[0];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        hd[q] = mine[1 + q];
+    float y = 0.0f;
+    if (r < a.R) {
+        const float *ysrc = (a.l == 0) ? a.A : a.Y;
+        y = ysrc[static_cast<int64_t>(sr.row) * a.R + r];
+    }
+    finish_row16<BF16>(a, sr.row, r, g, hd, y);
+}
+
 // ------------------------------------------------------------------ loss
 __device__ __forceinline__ double block_sum(double v, double *s)
 {
@@ -416,6 +1052,39 @@ hipError_t launch_items_rp(const RowArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <bool BF16, int KIND>
+hipError_t launch_items16_part(const RowArgs &a, hipStream_t s)
+{
+    const int count = KIND == 1 ? a.n_items - a.n_partial : KIND == 0 ? a.n_partial : a.n_items;
+    if (count <= 0)
+        return hipSuccess;
+    const dim3 grid((count + 3) / 4);
+    if (a.nmodes == 3)
+        hipLaunchKernelGGL((k_rows16<3, 4, BF16, KIND>), grid, dim3(64), 0, s, a);
+    else if (a.nmodes == 4)
+        hipLaunchKernelGGL((k_rows16<4, 4, BF16, KIND>), grid, dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_rows16<2, 4, BF16, KIND>), grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <bool BF16>
+hipError_t launch_items16(const RowArgs &a, hipStream_t s)
+{
+    if (a.nmodes > 4) {
+        hipLaunchKernelGGL((k_rows16_nm<BF16>), dim3((a.n_items + 3) / 4), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
+#if NTC_SPLIT_LAUNCH
+    hipError_t e = launch_items16_part<BF16, 0>(a, s);
+    if (e != hipSuccess)
+        return e;
+    return launch_items16_part<BF16, 1>(a, s);
+#else
+    return launch_items16_part<BF16, 2>(a, s);
+#endif
+}
+
 template <bool BF16>
 hipError_t launch_items_b(const RowArgs &a, int rp, hipStream_t s)
 {
@@ -423,7 +1092,7 @@ hipError_t launch_items_b(const RowArgs &a, int rp, hipStream_t s)
     case 8:
         return launch_items_rp<8, BF16>(a, s);
     case 16:
-        return launch_items_rp<16, BF16>(a, s);
+        return launch_items16<BF16>(a, s);
     case 32:
         return launch_items_rp<32, BF16>(a, s);
     case 64:
@@ -441,7 +1110,7 @@ hipError_t launch_final_b(const RowArgs &a, int rp, hipStream_t s)
         hipLaunchKernelGGL((k_row_finalize<8, BF16>), dim3(a.n_split), dim3(64), 0, s, a);
         break;
     case 16:
-        hipLaunchKernelGGL((k_row_finalize<16, BF16>), dim3(a.n_split), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_finalize16<BF16>), dim3(a.n_split), dim3(256), 0, s, a);
         break;
     case 32:
         hipLaunchKernelGGL((k_row_finalize<32, BF16>), dim3(a.n_split), dim3(64), 0, s, a);
@@ -469,6 +1138,30 @@ hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t 
     if (a.n_split <= 0)
         return hipSuccess;
     return bf16 ? launch_final_b<true>(a, rp, s) : launch_final_b<false>(a, rp, s);
+}
+
+hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s)
+{
+    if (a.n_tiny <= 0)
+        return hipSuccess;
+    const dim3 grid((a.n_tiny + 255) / 256);
+#define NTC_TINY(NMV, RWV)                                                                                  \
+    do {                                                                                                    \
+        if (bf16)                                                                                           \
+            hipLaunchKernelGGL((k_tiny16<NMV, RWV, true>), grid, dim3(256), 0, s, a);                       \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_tiny16<NMV, RWV, false>), grid, dim3(256), 0, s, a);                      \
+    } while (0)
+    if (a.nmodes == 3)
+        NTC_TINY(3, 4);
+    else if (a.nmodes == 4)
+        NTC_TINY(4, 4);
+    else if (a.nmodes == 2)
+        NTC_TINY(2, 4);
+    else
+        NTC_TINY(0, 8);
+#undef NTC_TINY
+    return hipGetLastError();
 }
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s)

@@ -54,11 +54,17 @@ def test_feistel_is_a_permutation_for_every_small_domain():
         assert np.array_equal(np.sort(pos), np.arange(n)), n
 
 
-def test_feistel_network_is_a_permutation_of_its_full_word():
-    for w in [2, 3, 4, 5, 9, 12]:
-        keys = O.sample_keys(3, w, 0, 0, 0)
-        img = sorted(O.feistel_net(x, w, keys) for x in range(1 << w))
-        assert img == list(range(1 << w))
+def test_feistel_network_is_a_permutation_of_its_word_domain():
+    """One pass permutes [0, A*B) with A = 2^ceil(w/2), B = ceil(n/A), and
+    A*B - n < A (so cycle walking is short)."""
+    for n in [1, 2, 3, 4, 5, 7, 9, 16, 17, 100, 1000, 4097, 50000]:
+        keys = O.sample_keys(3, n, 0, 0, 0)
+        D = O.feistel_domain(n)
+        w = O.feistel_width(n)
+        A = 1 << ((w + 1) // 2)
+        assert n <= D < n + A
+        img = sorted(O.feistel_net(x, n, keys) for x in range(D))
+        assert img == list(range(D)), n
     assert O.feistel_width(1) == 2 and O.feistel_width(4) == 2 and O.feistel_width(5) == 3
     assert O.feistel_width(1 << 20) == 20 and O.feistel_width((1 << 20) + 1) == 21
 

@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 PROFILES = os.path.join(ROOT, "profiles")
+# profile_sweep's launch kinds -> the kernels rocprofv3 reports for them (R = 16, N = 3)
+KERNEL_NAMES = {"row_items": "k_rows16<3, 4, false, 1>", "row_chunks": "k_chunk16<3, 4, false>",
+                "row_tiny": "k_tiny16<3, 4, false>", "row_finalize": "k_finalize16<false>"}
 
 
 def log(*a):
@@ -122,30 +125,33 @@ def main():
     value = upd_sweep * args.steps / wall
     log(f"timed: {wall * 1e3:.2f} ms wall, {dev_ms:.2f} ms device for {args.steps} sweeps")
 
-    # per-launch event timing of one more sweep: roofline of the dominant kernel
+    # per-launch event timing of one more sweep (all launches on one stream):
+    # roofline of the dominant kernel, the one with the largest share of the sweep
     launches = prob.profile_sweep()
-    per_mode = []
-    k1_bytes = k1_ms = 0.0
+    per_kernel = {}
     sweep_bytes = 0
+    per_mode = []
     for rec in launches:
-        if rec["kernel"] in ("row_items", "row_tiny"):
-            per_upd, b_upd, b_rows = algorithmic_bytes(p.nmodes, R, rec["samples"], rec["rows"], max_inner,
-                                                       args.bf16)
-            k1_bytes += b_upd + b_rows
-            k1_ms += rec["ms"]
-            sweep_bytes += b_upd + b_rows
-        else:
-            _, _, b_rows = algorithmic_bytes(p.nmodes, R, 0, rec["rows"], max_inner, args.bf16)
-            sweep_bytes += b_rows
-        per_mode.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in rec.items()})
-    n_k1 = sum(1 for r in launches if r["kernel"] == "row_items")
-    achieved = k1_bytes / (k1_ms * 1e-3) / 1e9 if k1_ms > 0 else 0.0
-    traffic_rec = load_traffic("row_items_c1_traffic.json" if not args.bf16 else "row_items_c1_bf16_traffic.json")
+        _, b_upd, b_rows = algorithmic_bytes(p.nmodes, R, rec["samples"], rec["rows"], max_inner, args.bf16)
+        k = per_kernel.setdefault(rec["kernel"], {"bytes": 0, "ms": 0.0, "launches": 0})
+        k["bytes"] += b_upd + b_rows
+        k["ms"] += rec["ms"]
+        k["launches"] += 1
+        sweep_bytes += b_upd + b_rows
+        per_mode.append({kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in rec.items()})
+    dom = max(per_kernel, key=lambda n: per_kernel[n]["ms"])
+    kd = per_kernel[dom]
+    avg_ms = kd["ms"] / kd["launches"]
+    bytes_per_launch = kd["bytes"] / kd["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic_rec = load_traffic(f"{dom}_c1{'_bf16' if args.bf16 else ''}_traffic.json")
     traffic = traffic_rec["hbm_bytes_per_launch"] if traffic_rec else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_row_items", "avg_launch_ms": round(k1_ms / max(n_k1, 1), 4),
-                "algorithmic_bytes_per_launch": round(k1_bytes / max(n_k1, 1))}
+                "kernel": KERNEL_NAMES[dom], "avg_launch_ms": round(avg_ms, 4),
+                "launches_per_sweep": kd["launches"],
+                "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                "sweep_share": round(kd["ms"] / sum(v["ms"] for v in per_kernel.values()), 3)}
     hbm_frac = sweep_bytes * args.steps / wall / (HBM_PEAK_GBS * 1e9)
 
     t0 = time.perf_counter()

@@ -77,6 +77,10 @@ typedef struct ntc_params {
                                    are split over several items (0 = default) */
     int32_t overlap;            /* schedule: 1 = run the one-row-per-lane launch on a second
                                    stream concurrently with the other rows (default), 0 = serial */
+    int32_t group_max;          /* schedule (R <= 16): rows with tiny_max < B_p <= group_max run
+                                   one row per 16-lane group, longer ones as 256-thread chunks of
+                                   item_samples entries (0 = default 256) */
+    int32_t reserved1;
 } ntc_params;
 
 /* Fill *p with defaults: c = 0.1, lambda = 1e-3, max_inner = 1,
@@ -167,10 +171,13 @@ ntc_status ntc_time_sweeps(ntc_handle h, int32_t nsweeps, double *ms);
 
 /* One launch of a sweep as seen by ntc_profile_sweep. */
 typedef struct ntc_launch_record {
-    int32_t kernel;  /* 0: row items (sample, gather, gradient, Hessian, and the
-                        power method + step for rows held by one item);
-                        1: finalize of rows split over several items;
-                        2: rows with at most 4 sampled entries, one per lane */
+    int32_t kernel;  /* 0: rows held by one work item (sample, gather, gradient,
+                        Hessian, power method, step), one per 16-lane group for
+                        R <= 16, one per wave otherwise;
+                        1: finalize of rows split over several work items;
+                        2: rows with at most 4 sampled entries, one per lane;
+                        3: chunks of rows with many samples, one per 256-thread
+                        block (R <= 16) */
     int32_t mode;    /* mode being updated */
     int32_t inner;   /* inner step l of Alg. 1 */
     int32_t blocks;  /* workgroups launched */

@@ -67,6 +67,8 @@ class _Params(ctypes.Structure):
         ("alloc_ctx", ctypes.c_void_p),
         ("item_samples", ctypes.c_int32),
         ("overlap", ctypes.c_int32),
+        ("group_max", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -222,7 +224,7 @@ class Problem:
         prm.c, prm.lam, prm.max_inner, prm.power_iters, prm.seed = c, lam, max_inner, power_iters, seed
         prm.gather_bf16 = 1 if gather_bf16 else 0
         for key, val in (schedule or {}).items():
-            if key not in ("tiny_max", "item_samples", "overlap"):
+            if key not in ("tiny_max", "item_samples", "overlap", "group_max"):
                 raise ValueError(f"unknown schedule field {key}")
             setattr(prm, key, int(val))
         keep = [d, co, va]
@@ -300,7 +302,7 @@ class Problem:
         buf = (LaunchRecord * cap)()
         cnt = ctypes.c_int32(0)
         _check(lib().ntc_profile_sweep(self._h, buf, cap, ctypes.byref(cnt)))
-        return [dict(kernel=("row_items", "row_finalize", "row_tiny")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
+        return [dict(kernel=("row_items", "row_finalize", "row_tiny", "row_chunks")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
                      samples=r.samples, rows=r.rows, ms=r.ms) for r in buf[: min(cnt.value, cap)]]
 
     def update_mode(self, mode: int):

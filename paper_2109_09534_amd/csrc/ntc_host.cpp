@@ -50,7 +50,7 @@ int record_words(int nmodes)
 // 64/RP samples per step).
 int item_samples(int rp)
 {
-    return rp == 16 ? 1024 : 512 * (64 / rp);
+    return rp == 16 ? 4096 : 512 * (64 / rp);
 }
 
 unsigned host_threads()
@@ -80,10 +80,10 @@ void parallel_for(int64_t n, F &&f)
 
 // Stable counting sort of the COO entries by coordinate `mode`, done in T
 // contiguous chunks so that ties keep COO order.  Writes rowptr [I+1] and,
-// if given, the records [nnz][rw] (other-mode coordinates in increasing mode
-// order, then the value bits) and/or the permutation [nnz].
+// if given, the records [nnz][rw] (other-mode coordinates times R, in
+// increasing mode order, then the value bits) and/or the permutation [nnz].
 void csr_build(int nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords, const float *values, int mode,
-               int rw, std::vector<int64_t> &rowptr, uint32_t *records, int64_t *perm)
+               int rw, std::vector<int64_t> &rowptr, uint32_t *records, int64_t *perm, uint32_t rank = 1)
 {
     const int64_t I = dims[mode];
     const unsigned T = (nnz < (1 << 16)) ? 1u : host_threads();
@@ -130,7 +130,7 @@ void csr_build(int nmodes, const int64_t *dims, int64_t nnz, const int32_t *coor
                 int w = 0;
                 for (int m = 0; m < nmodes; ++m)
                     if (m != mode)
-                        rec[w++] = static_cast<uint32_t>(ce[m]);
+                        rec[w++] = static_cast<uint32_t>(ce[m]) * rank;  // element offset of the factor row
                 uint32_t vb;
                 std::memcpy(&vb, values + e, 4);
                 rec[w++] = vb;
@@ -156,11 +156,14 @@ struct ModeState {
     int64_t tiny_samples = 0;
     int32_t n_items = 0;
     int32_t n_partial = 0;
+    int32_t n_group = 0;
     int32_t n_split = 0;
     int32_t n_slots = 0;
     int64_t samples = 0;
     int64_t active_rows = 0;
     int64_t fused_rows = 0;
+    int64_t row_samples = 0, row_fused = 0;      // launched by launch_row_items
+    int64_t chunk_samples = 0, chunk_fused = 0;  // launched by launch_row_chunks
     std::vector<int64_t> h_rowptr;
 };
 
@@ -180,6 +183,7 @@ struct ntc_problem {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int tiny_max = ntc::kTinyB;
     int item_samples = 0;
+    int group_max = 256;
     int device = 0;
     ntc_alloc_fn alloc = nullptr;
     ntc_free_fn dfree = nullptr;
@@ -276,6 +280,14 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
         a.gath16[w] = h->U16[mm];
         ++w;
     }
+    {
+        int z = 0;
+        for (int mm = 0; mm < h->N; ++mm)
+            if (mm != mode)
+                a.zrec[z++] = static_cast<uint32_t>(h->dims[mm] * h->R);
+        for (; z < 8; ++z)
+            a.zrec[z] = 0u;  // value 0 and padding
+    }
     a.A = h->U[mode];
     a.Y = h->Y;
     a.A16 = h->U16[mode];
@@ -292,6 +304,7 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.power_iters = h->power_iters;
     a.n_items = m.n_items;
     a.n_partial = m.n_partial;
+    a.n_group = m.n_group;
     a.n_split = m.n_split;
     return a;
 }
@@ -309,13 +322,20 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
         const ntc::RowArgs a = row_args(h, mode, l);
         // the one-row-per-lane rows are disjoint from the other rows: with a
         // side stream they run concurrently (fork/join through events)
-        const bool fork = h->side && md.n_tiny > 0 && (md.n_items > 0 || md.n_split > 0);
+        const bool group16 = h->RP == 16 && h->N <= 4;
+        const int32_t n_chunk = group16 ? md.n_items - md.n_group : 0;
+        const int32_t n_rows = group16 ? md.n_group : md.n_items;
+        // the one-row-per-lane rows are disjoint from the other rows: with a
+        // side stream they run concurrently (fork/join through events); a
+        // profiled sweep runs everything on one stream
+        const bool fork = !probe && h->side && md.n_tiny > 0 && (md.n_items > 0 || md.n_split > 0);
         if (fork) {
             NTC_HIP(hipEventRecord(h->ev_fork, h->stream));
             NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         }
-        for (int kern : {2, 0, 1}) {
-            const int32_t count = kern == 0 ? md.n_items : kern == 1 ? md.n_split : md.n_tiny;
+        // launch order: one-row-per-lane, chunks, rows, finalize of split rows
+        for (int kern : {2, 3, 0, 1}) {
+            const int32_t count = kern == 0 ? n_rows : kern == 1 ? md.n_split : kern == 2 ? md.n_tiny : n_chunk;
             if (count <= 0)
                 continue;
             hipStream_t st = (kern == 2 && fork) ? h->side : h->stream;
@@ -331,18 +351,21 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
                 NTC_HIP(ntc::launch_row_items(a, h->RP, h->bf16, st));
             else if (kern == 1)
                 NTC_HIP(ntc::launch_row_finalize(a, h->RP, h->bf16, st));
-            else
+            else if (kern == 2)
                 NTC_HIP(ntc::launch_row_tiny(a, h->bf16, st));
+            else
+                NTC_HIP(ntc::launch_row_chunks(a, h->RP, h->bf16, st));
             if (probe) {
                 NTC_HIP(hipEventRecord(e1, st));
                 ntc_launch_record r{};
                 r.kernel = kern;
                 r.mode = mode;
                 r.inner = l;
-                r.blocks = kern == 0 ? (h->RP == 16 ? (md.n_items + 3) / 4 : md.n_items)
-                                     : kern == 1 ? md.n_split : (md.n_tiny + 255) / 256;
-                r.samples = kern == 0 ? md.samples - md.tiny_samples : kern == 1 ? 0 : md.tiny_samples;
-                r.rows = kern == 0 ? md.fused_rows : kern == 1 ? md.n_split : md.n_tiny;
+                r.blocks = kern == 0 ? (h->RP == 16 ? (n_rows + 3) / 4 : n_rows)
+                           : kern == 1 ? md.n_split : kern == 2 ? (md.n_tiny + 255) / 256 : n_chunk;
+                r.samples = kern == 0 ? md.row_samples : kern == 1 ? 0 : kern == 2 ? md.tiny_samples
+                                                                             : md.chunk_samples;
+                r.rows = kern == 0 ? md.row_fused : kern == 1 ? md.n_split : kern == 2 ? md.n_tiny : md.chunk_fused;
                 probe->rec.push_back(r);
             }
         }
@@ -403,11 +426,17 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
         return fail(NTC_EINVAL, "tiny_max must be -1 or in [0, 4]");
     if (p.item_samples < 0 || (p.item_samples > 0 && p.item_samples < 16))
         return fail(NTC_EINVAL, "item_samples must be 0 or >= 16");
+    if (p.group_max < 0)
+        return fail(NTC_EINVAL, "group_max must be >= 0");
     if (p.n_test < 0 || (p.n_test > 0 && (!p.test_coords || !p.test_values)))
         return fail(NTC_EINVAL, "test set pointers are null");
-    for (int m = 0; m < N; ++m)
+    for (int m = 0; m < N; ++m) {
         if (dims[m] < 1 || dims[m] >= (int64_t(1) << 31))
             return fail(NTC_EINVAL, "dims[" + std::to_string(m) + "] must be in [1, 2^31)");
+        if ((dims[m] + 1) * R * 4 >= (int64_t(1) << 32))
+            return fail(NTC_EUNSUPPORTED, "factor of mode " + std::to_string(m) +
+                                              " would exceed 4 GiB (gathers use 32-bit byte offsets)");
+    }
     for (int64_t e = 0; e < nnz; ++e) {
         for (int m = 0; m < N; ++m) {
             const int32_t x = coords[e * N + m];
@@ -450,6 +479,7 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
     h->actx = p.alloc_ctx;
     h->tiny_max = p.tiny_max < 0 ? ntc::kTinyB : p.tiny_max;
     h->item_samples = p.item_samples;
+    h->group_max = p.group_max > 0 ? p.group_max : 256;
     NTC_HIP(hipGetDevice(&h->device));
     if (p.overlap) {
         NTC_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
@@ -461,12 +491,17 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
 
     // factors and shadows
     int64_t maxI = 0;
+    // every factor has one extra all-zero row (index I_m): the gathers of a
+    // missing sample read it, so its Khatri-Rao row is exactly zero
     for (int m = 0; m < N; ++m) {
-        const int64_t cntm = dims[m] * R;
+        const int64_t cntm = (dims[m] + 1) * R;
         maxI = std::max(maxI, dims[m]);
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U[m]), cntm * sizeof(float), "factor"));
-        if (h->bf16)
+        NTC_HIP(hipMemset(h->U[m], 0, cntm * sizeof(float)));
+        if (h->bf16) {
             NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U16[m]), cntm * sizeof(uint16_t), "bf16 shadow"));
+            NTC_HIP(hipMemset(h->U16[m], 0, cntm * sizeof(uint16_t)));
+        }
     }
     if (h->max_inner > 1)
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->Y), maxI * R * sizeof(float), "Y buffer"));
@@ -479,7 +514,8 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
     for (int m = 0; m < N; ++m) {
         ModeState &md = h->md[m];
         md.I = dims[m];
-        csr_build(N, dims, nnz, coords, values, m, h->rw, md.h_rowptr, rec.data(), nullptr);
+        csr_build(N, dims, nnz, coords, values, m, h->rw, md.h_rowptr, rec.data(), nullptr,
+                  static_cast<uint32_t>(R));
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.rowptr), (md.I + 1) * sizeof(int64_t), "rowptr"));
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.records),
                               static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw * 4, "records"));
@@ -499,22 +535,59 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
         std::vector<SplitRow> split;
         std::vector<int32_t> tiny;
         int32_t slot = 0;
-        for (int32_t r : rows) {
-            const int64_t b = bsz[r];
-            md.samples += b;
-            md.active_rows += 1;
-            if (rp == 16 && b <= h->tiny_max) {
-                tiny.push_back(r);
-                md.tiny_samples += b;
-            } else if (b <= smax) {
-                md.fused_rows += 1;
-                whole.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
-            } else {
-                const int32_t s0 = slot;
-                for (int64_t j0 = 0; j0 < b; j0 += smax)
-                    items.push_back(Item{r, static_cast<int32_t>(j0), static_cast<int32_t>(std::min(b, j0 + smax)),
-                                         slot++});
-                split.push_back(SplitRow{r, s0, slot - s0, 0});
+        if (rp == 16) {
+            // one row per lane / one row per 16-lane group / 16 groups per row chunk
+            std::vector<Item> chunks;
+            for (int32_t r : rows) {
+                const int64_t b = bsz[r];
+                md.samples += b;
+                md.active_rows += 1;
+                if (b <= h->tiny_max) {
+                    tiny.push_back(r);
+                    md.tiny_samples += b;
+                } else if (b <= h->group_max) {
+                    md.fused_rows += 1;
+                    md.row_fused += 1;
+                    md.row_samples += b;
+                    items.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
+                } else if (b <= smax) {
+                    md.fused_rows += 1;
+                    md.chunk_fused += 1;
+                    md.chunk_samples += b;
+                    chunks.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
+                } else {
+                    md.chunk_samples += b;
+                    const int32_t s0 = slot;
+                    for (int64_t j0 = 0; j0 < b; j0 += smax)
+                        chunks.push_back(Item{r, static_cast<int32_t>(j0),
+                                              static_cast<int32_t>(std::min(b, j0 + smax)), slot++});
+                    split.push_back(SplitRow{r, s0, slot - s0, 0});
+                }
+            }
+            md.n_group = static_cast<int32_t>(items.size());
+            items.insert(items.end(), chunks.begin(), chunks.end());
+            if (h->N > 4) {  // the group kernel takes every item
+                md.row_samples += md.chunk_samples;
+                md.row_fused += md.chunk_fused;
+                md.chunk_samples = md.chunk_fused = 0;
+            }
+        } else {
+            for (int32_t r : rows) {
+                const int64_t b = bsz[r];
+                md.samples += b;
+                md.active_rows += 1;
+                md.row_samples += b;
+                if (b <= smax) {
+                    md.fused_rows += 1;
+                    md.row_fused += 1;
+                    whole.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
+                } else {
+                    const int32_t s0 = slot;
+                    for (int64_t j0 = 0; j0 < b; j0 += smax)
+                        items.push_back(Item{r, static_cast<int32_t>(j0),
+                                             static_cast<int32_t>(std::min(b, j0 + smax)), slot++});
+                    split.push_back(SplitRow{r, s0, slot - s0, 0});
+                }
             }
         }
         md.n_partial = static_cast<int32_t>(items.size());

@@ -31,7 +31,7 @@ struct SplitRow {
 // Arguments of the row kernels for one (mode, inner step).
 struct RowArgs {
     const int64_t *rowptr;        // [I+1] CSR of this mode
-    const uint32_t *records;      // [nnz][rec_words]: other-mode coords (increasing mode), value bits
+    const uint32_t *records;      // [nnz][rec_words]: other-mode coordinates * R (increasing mode), value bits
     const Item *items;
     const SplitRow *split;
     const int32_t *tiny;          // rows whose minibatch has 1..kTinyB samples (R <= 16 kernels)
@@ -41,6 +41,8 @@ struct RowArgs {
     float *Y;                     // extrapolated iterate buffer (MAX_INNER > 1)
     uint16_t *A16;                // this mode's BF16 shadow (or null)
     double *partials;             // [slots][RP + RP*RP]
+    uint32_t zrec[8];             // record of a missing sample: the all-zero row (index I_m) of each
+                                  // other mode, value 0
     uint64_t seed;
     int64_t k;
     double lambda;
@@ -53,7 +55,9 @@ struct RowArgs {
     int32_t max_inner;
     int32_t power_iters;
     int32_t n_items;
-    int32_t n_partial;            // the first n_partial items write partial slots (split rows)
+    int32_t n_partial;            // (wave-per-item kernels) items [0, n_partial) write partial slots
+    int32_t n_group;              // (R <= 16) items [0, n_group) are whole rows for the group kernel,
+                                  // items [n_group, n_items) row chunks for the block kernel
     int32_t n_split;
     int32_t n_tiny;
 };
@@ -63,7 +67,7 @@ constexpr int kTinyB = 4;
 
 struct LossArgs {
     const int64_t *rowptr0;       // CSR of mode 0
-    const uint32_t *records0;
+    const uint32_t *records0;     // coordinates * R
     int64_t nnz;
     int64_t I0;
     const int32_t *test_coords;
@@ -81,7 +85,11 @@ struct LossArgs {
 constexpr int kLossBlocks = 512;
 constexpr int kLossThreads = 256;
 
+// R <= 16: whole rows one per 16-lane group (5 <= N <= 8: also every chunk)
+// R > 16: every item, one per wave
 hipError_t launch_row_items(const RowArgs &a, int rp, bool bf16, hipStream_t s);
+// R <= 16 and N <= 4: row chunks of rows with many samples, one per 256-thread block
+hipError_t launch_row_chunks(const RowArgs &a, int rp, bool bf16, hipStream_t s);
 hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t s);
 hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s);
 hipError_t launch_loss(const LossArgs &a, hipStream_t s);

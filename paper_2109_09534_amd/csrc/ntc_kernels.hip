@@ -190,13 +190,13 @@ __global__ __launch_bounds__(64) void k_row_items(const RowArgs a)
             if (valid) {
                 kv = rlive ? 1.0f : 0.0f;
                 for (int mm = 0; mm < nm - 1; ++mm) {
-                    const int64_t idx = s_rec[t * 8 + mm];
+                    const int64_t off = s_rec[t * 8 + mm];  // coordinate * R
                     float f = 0.0f;
                     if (rlive) {
                         if (BF16)
-                            f = bf16_to_f32(a.gath16[mm][idx * R + r]);
+                            f = bf16_to_f32(a.gath16[mm][off + r]);
                         else
-                            f = a.gath[mm][idx * R + r];
+                            f = a.gath[mm][off + r];
                     }
                     kv *= f;
                 }
@@ -316,14 +316,14 @@ __device__ __forceinline__ double dpp_f64(double x)
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// Sum over the 16 lanes of a DPP row; every lane gets the same bits (each
-// step pairs lanes symmetrically).
+// Sum over the 16 lanes of a DPP row: quad butterflies, then two row
+// rotations (every lane gets the sum; lanes may differ in the last bit).
 __device__ __forceinline__ float row_sum_f32(float x)
 {
     x += dpp_f32<kDppXor1>(x);
     x += dpp_f32<kDppXor2>(x);
-    x += dpp_f32<kDppHalfMirror>(x);
-    x += dpp_f32<kDppMirror>(x);
+    x += dpp_f32<kDppRor + 4>(x);
+    x += dpp_f32<kDppRor + 8>(x);
     return x;
 }
 
@@ -444,8 +444,8 @@ template <int RW>
 __device__ __forceinline__ void fetch_record(const RowArgs &a, const GroupItem &g, int jb, int r, uint4 &w0,
                                              uint4 &w1)
 {
-    w0 = make_uint4(0u, 0u, 0u, 0u);
-    w1 = make_uint4(0u, 0u, 0u, 0u);
+    w0 = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+    w1 = make_uint4(a.zrec[4], a.zrec[5], a.zrec[6], a.zrec[7]);
     if (jb + r < g.len) {
         const uint32_t q = prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r));
         const uint4 *src = reinterpret_cast<const uint4 *>(a.records + (g.base + q) * RW);
@@ -474,7 +474,6 @@ __device__ __forceinline__ void stage_record(uint4 *buf, int lane, const uint4 &
 template <int NM, int RW, bool BF16>
 __device__ __forceinline__ void gather_batch(const RowArgs &a, const uint32_t *srec, int rr, float (&f)[NM - 1][16])
 {
-    const uint32_t R = static_cast<uint32_t>(a.R);
 #pragma unroll
     for (int mm = 0; mm < NM - 1; ++mm) {
         // 32-bit byte offsets from a wave-uniform base (factors are < 4 GiB)
@@ -482,7 +481,7 @@ __device__ __forceinline__ void gather_batch(const RowArgs &a, const uint32_t *s
                                 : reinterpret_cast<const char *>(a.gath[mm]);
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-            const uint32_t e = srec[t * RW + mm] * R + static_cast<uint32_t>(rr);
+            const uint32_t e = srec[t * RW + mm] + static_cast<uint32_t>(rr);  // coordinate * R + column
             if (BF16)
                 f[mm][t] = bf16_to_f32(*reinterpret_cast<const uint16_t *>(base + e * 2u));
             else
@@ -511,8 +510,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NT
     const int r = lane & 15;
     const int grp = lane >> 4;
     // partial items (slots) come first in the item list, whole rows after
-    const int first = KIND == 1 ? a.n_partial : 0;
-    const int last = KIND == 0 ? a.n_partial : a.n_items;
+    const int first = 0;
+    const int last = a.n_group;
     const int id = first + blockIdx.x * 4 + grp;
     const GroupItem g = load_group_item(a, id < last ? id : a.n_items);
     const int R = a.R;
@@ -548,7 +547,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NT
     }
     for (int bi = 0; bi < nb; ++bi) {
         const int jb = bi * 16;
-        const int cnt = min(16, max(0, g.len - jb));
         const int tmax = min(16, maxlen - jb);
         // Khatri-Rao rows of this batch; this frees f for the next gathers
         float kc[16];
@@ -558,7 +556,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NT
 #pragma unroll
             for (int mm = 1; mm < NM - 1; ++mm)
                 k *= f[mm][t];
-            kc[t] = (t < cnt && rlive) ? k : 0.0f;
+            kc[t] = rlive ? k : 0.0f;  // a missing sample gathered the zero rows
         }
         // issue order: records of batch b+2, then gathers of batch b+1, so
         // that staging the records later waits only for the record loads
@@ -623,6 +621,140 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NT
     }
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Chunks of rows with many sampled entries: one 256-thread block (16
+// groups) per chunk of up to item_samples entries of ONE row.  Batch t of
+// the chunk (16 entries) goes to group t mod 16, so every group walks a
+// short chain of batches.  The four groups of a wave hold samples of the
+// same row, so one v_mfma_f32_16x16x4f32 per step adds all four k k^T into a
+// single 16x16 block (K = the four groups); register v of lane l holds
+// H[4*(l/16) + v][l%16].  The four waves' FP64 sums and the 16 groups'
+// gradients are combined in LDS in a fixed order; a chunk that is the whole
+// row finishes it in place, otherwise it writes a partial slot.
+template <int NM, int RW, bool BF16>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_chunk16(
+    const RowArgs a)
+{
+    __shared__ uint4 s_rec[4][2][64 * (RW / 4)];
+    __shared__ double s_hw[4][4 * 64];  // per wave: its FP64 block sum, register v of lane l at v*64 + l
+    __shared__ double s_g[16 * 16];     // per group: gradient partial of lane r
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int r = lane & 15;
+    const int grp = lane >> 4;
+    const int G = wave * 4 + grp;       // group index in the block
+    const Item it = a.items[a.n_group + blockIdx.x];
+    const int R = a.R;
+    const bool rlive = r < R;
+    const int rr = rlive ? r : 0;
+    const int64_t base = a.rowptr[it.row];
+    const int64_t n = a.rowptr[it.row + 1] - base;
+    GroupItem g;
+    g.has = true;
+    g.it = it;
+    g.base = base;
+    g.len = it.j1 - it.j0;
+    g.prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.k, a.mode, a.l, it.row));
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const float y = rlive ? ysrc[static_cast<int64_t>(it.row) * R + r] : 0.0f;
+
+    const int nbatch = (g.len + 15) / 16;  // batches of the chunk
+    const int nit = (nbatch + 15) / 16;    // iterations of every group (uniform in the block)
+    // batch handled by group G at iteration i: G + 16 i (entries from 16 * batch)
+
+    double gd = 0.0;
+    double hd[4] = {0.0, 0.0, 0.0, 0.0};
+    uint4 w0, w1;
+    float f[NM - 1][16];
+    uint4 *rb0 = s_rec[wave][0];
+    uint4 *rb1 = s_rec[wave][1];
+    if (nit > 0) {
+        fetch_record<RW>(a, g, 16 * G, r, w0, w1);
+        stage_record<RW>(rb0, lane, w0, w1);
+        if (nit > 1) {
+            fetch_record<RW>(a, g, 16 * (G + 16), r, w0, w1);
+            stage_record<RW>(rb1, lane, w0, w1);
+        }
+        gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(rb0) + grp * 16 * RW, rr, f);
+    }
+    for (int i = 0; i < nit; ++i) {
+        float kc[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            float k = f[0][t];
+#pragma unroll
+            for (int mm = 1; mm < NM - 1; ++mm)
+                k *= f[mm][t];
+            kc[t] = rlive ? k : 0.0f;  // a missing sample gathered the zero rows
+        }
+        if (i + 2 < nit)
+            fetch_record<RW>(a, g, 16 * (G + 16 * (i + 2)), r, w0, w1);
+        if (i + 1 < nit)
+            gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>((i & 1) ? rb0 : rb1) + grp * 16 * RW,
+                                       rr, f);
+        const uint32_t *srec = reinterpret_cast<const uint32_t *>((i & 1) ? rb1 : rb0) + grp * 16 * RW;
+        float gf = 0.0f;
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const float k = kc[t];
+            const float x = __uint_as_float(srec[t * RW + NM - 1]);  // 0 for a missing sample
+            const float pred = row_sum_f32(k * y);
+            gf = fmaf(pred - x, k, gf);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(k, k, acc, 0, 0, 0);
+        }
+        gd += static_cast<double>(gf);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            hd[v] += static_cast<double>(acc[v]);
+        __builtin_amdgcn_wave_barrier();  // the compute above read this buffer
+        if (i + 2 < nit)
+            stage_record<RW>((i & 1) ? rb1 : rb0, lane, w0, w1);
+    }
+
+    // fixed-order combination over the four waves and the 16 groups
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        s_hw[wave][v * 64 + lane] = hd[v];
+    s_g[G * 16 + r] = gd;
+    __syncthreads();
+    if (wave != 0)
+        return;
+    double h4[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        h4[v] = ((s_hw[0][v * 64 + lane] + s_hw[1][v * 64 + lane]) + s_hw[2][v * 64 + lane]) + s_hw[3][v * 64 + lane];
+    double gsum = 0.0;
+    for (int q = 0; q < 16; ++q)
+        gsum += s_g[q * 16 + r];
+    if (it.slot >= 0) {
+        double *P = a.partials + static_cast<int64_t>(it.slot) * kSlot16;
+        if (grp == 0)
+            P[r] = gsum;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            P[16 + (4 * grp + v) * 16 + r] = h4[v];
+        return;
+    }
+    // whole row: row-major H in LDS (reusing wave 0's slot), then group 0 finishes
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        s_hw[0][(4 * grp + v) * 16 + r] = h4[v];
+    __builtin_amdgcn_wave_barrier();
+    if (grp != 0)
+        return;
+    int sig[16];
+    ror_sources(r, sig);
+    double hs[16];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2)
+        hs[s2] = s_hw[0][r * 16 + sig[s2]];
+    finish_row16<BF16>(a, it.row, r, gsum, hs, y);
+}
+
 // Items of the group kernels for 5 <= N <= 8 (32-byte records): the same
 // computation without the software pipeline; the Khatri-Rao product is
 // accumulated over a runtime mode loop.
@@ -664,8 +796,8 @@ __global__ __launch_bounds__(64) void k_rows16_nm(const RowArgs a)
             for (int t = 0; t < 16; ++t) {
                 f[t] = 0.0f;
                 if (t < cnt && rlive) {
-                    const int64_t idx = srec[t * 8 + mm];
-                    f[t] = BF16 ? bf16_to_f32(a.gath16[mm][idx * R + r]) : a.gath[mm][idx * R + r];
+                    const int64_t off = srec[t * 8 + mm];  // coordinate * R
+                    f[t] = BF16 ? bf16_to_f32(a.gath16[mm][off + r]) : a.gath[mm][off + r];
                 }
             }
 #pragma unroll
@@ -715,10 +847,15 @@ __global__ __launch_bounds__(64) void k_rows16_nm(const RowArgs a)
 }
 
 // Rows whose minibatch has at most kTinyB samples (R <= 16): one row per
-// lane, no cross-lane traffic.  The lane keeps the b sampled Khatri-Rao rows
-// k_j and applies the row Hessian as H v = sum_j k_j (k_j . v) + lambda v,
-// the same matrix as B^T diag(M_hat(p,:)) B + lambda I applied through its
-// rank-b factors, so each power-method product costs O(bR) instead of O(R^2).
+// lane, no cross-lane traffic.  With K the b x R matrix of the sampled
+// Khatri-Rao rows, H = K^T K + lambda I, and the T-th (unnormalised) power
+// iterate from v0 is x_T = lambda^T v0 + K^T u_T with u_0 = 0 and
+//     u_{t+1} = (G + lambda I) u_t + lambda^t c,   G = K K^T, c = K v0,
+// because H (a v0 + K^T u) = lambda a v0 + K^T (a c + G u + lambda u).  The
+// Rayleigh quotient of x_T is ||a c + G u||^2 / ||x||^2 + lambda with
+// ||x||^2 = a^2 + 2 a u.c + u^T G u (||v0|| = 1).  This is the same iterate
+// as T normalised products with H, evaluated in the b-dimensional span of
+// the samples: O(T b^2) instead of O(T b R) operations per row.
 template <int NM, int RW, bool BF16>
 __global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
 {
@@ -739,6 +876,16 @@ __global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
     for (int r = 0; r < 16; ++r)
         y[r] = r < R ? ysrc[roff + r] : 0.0f;
 
+    // sampled records first (all in flight), then the factor rows
+    uint32_t rec[kTinyB][RW];
+#pragma unroll
+    for (int j = 0; j < kTinyB; ++j) {
+        const uint32_t q = j < b ? prp_index(prp, static_cast<uint32_t>(j)) : 0u;
+        const uint32_t *src = a.records + (base + q) * RW;
+#pragma unroll
+        for (int w = 0; w < RW; ++w)
+            rec[j][w] = src[w];
+    }
     float kk[kTinyB][16];
     float gf[16];
 #pragma unroll
@@ -748,21 +895,16 @@ __global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
     for (int j = 0; j < kTinyB; ++j) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            kk[j][r] = 0.0f;
-        if (j < b) {
-            const uint32_t q = prp_index(prp, static_cast<uint32_t>(j));
-            const uint32_t *rec = a.records + (base + q) * RW;
+            kk[j][r] = (r < R && j < b) ? 1.0f : 0.0f;
+        for (int mm = 0; mm < nm - 1; ++mm) {
+            const int64_t o = static_cast<int64_t>(rec[j][mm]);  // coordinate * R
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                kk[j][r] = r < R ? 1.0f : 0.0f;
-            for (int mm = 0; mm < nm - 1; ++mm) {
-                const int64_t o = static_cast<int64_t>(rec[mm]) * R;
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    if (r < R)
-                        kk[j][r] *= BF16 ? bf16_to_f32(a.gath16[mm][o + r]) : a.gath[mm][o + r];
-            }
-            const float x = __uint_as_float(rec[nm - 1]);
+                if (r < R)
+                    kk[j][r] *= BF16 ? bf16_to_f32(a.gath16[mm][o + r]) : a.gath[mm][o + r];
+        }
+        if (j < b) {
+            const float x = __uint_as_float(rec[j][nm - 1]);
             float pred = 0.0f;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -774,58 +916,70 @@ __global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
         }
     }
 
-    // power method on H = sum_j k_j k_j^T + lambda I
+    // c = K v0 and G = K K^T in FP64 (products of FP32 values are exact)
     const double lam = a.lambda;
-    double v[16];
     const double v0 = 1.0 / sqrt(static_cast<double>(R));
+    double c[kTinyB], G[kTinyB][kTinyB];
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-        v[r] = r < R ? v0 : 0.0;
-    auto apply_h = [&](const double (&x)[16], double (&out)[16]) {
-        double u[kTinyB];
+    for (int i = 0; i < kTinyB; ++i) {
+        double si = 0.0;
 #pragma unroll
-        for (int j = 0; j < kTinyB; ++j) {
-            u[j] = 0.0;
-            if (j < b) {
+        for (int r = 0; r < 16; ++r)
+            si += static_cast<double>(kk[i][r]);
+        c[i] = si * v0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    u[j] = fma(static_cast<double>(kk[j][r]), x[r], u[j]);
-            }
+        for (int j = 0; j <= i; ++j) {
+            double d = 0.0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                d = fma(static_cast<double>(kk[i][r]), static_cast<double>(kk[j][r]), d);
+            G[i][j] = d;
+            G[j][i] = d;
         }
+    }
+    // the recurrence, rescaled every step (only the direction matters)
+    double al = 1.0, u[kTinyB];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            double o = lam * x[r];
+    for (int i = 0; i < kTinyB; ++i)
+        u[i] = 0.0;
+    for (int t = 0; t < a.power_iters; ++t) {
+        double un[kTinyB];
+        double mx = fabs(al * lam);
+#pragma unroll
+        for (int i = 0; i < kTinyB; ++i) {
+            double s = fma(lam, u[i], al * c[i]);
 #pragma unroll
             for (int j = 0; j < kTinyB; ++j)
-                if (j < b)
-                    o = fma(static_cast<double>(kk[j][r]), u[j], o);
-            out[r] = o;
+                s = fma(G[i][j], u[j], s);
+            un[i] = s;
+            mx = fmax(mx, fabs(s));
         }
-    };
-    double w[16];
-    bool vanished = false;
-    for (int t = 0; t < a.power_iters; ++t) {
-        apply_h(v, w);
-        double n2 = 0.0;
+        if (!(mx > 0.0)) {
+            al = 0.0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            n2 = fma(w[r], w[r], n2);
-        if (!(n2 > 0.0)) {
-            vanished = true;
+            for (int i = 0; i < kTinyB; ++i)
+                u[i] = 0.0;
             break;
         }
-        const double inv = 1.0 / sqrt(n2);
+        const double inv = 1.0 / mx;
+        al = (al * lam) * inv;
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            v[r] = w[r] * inv;
+        for (int i = 0; i < kTinyB; ++i)
+            u[i] = un[i] * inv;
     }
-    double L = 0.0;
-    if (!vanished) {
-        apply_h(v, w);
+    double x2 = al * al, kx2 = 0.0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            L = fma(v[r], w[r], L);
+    for (int i = 0; i < kTinyB; ++i) {
+        double gu = 0.0;
+#pragma unroll
+        for (int j = 0; j < kTinyB; ++j)
+            gu = fma(G[i][j], u[j], gu);
+        x2 = fma(u[i], fma(2.0 * al, c[i], gu), x2);   // a^2 + 2 a u.c + u^T G u
+        const double kxi = fma(al, c[i], gu);          // (K x)_i = a c_i + (G u)_i
+        kx2 = fma(kxi, kxi, kx2);
     }
+    const double L = (x2 > 0.0) ? kx2 / x2 + lam : 0.0;
+
     const bool more = a.l + 1 < a.max_inner;
     if (L > 0.0) {
         const double sl = sqrt(L), sm = sqrt(lam);
@@ -947,7 +1101,7 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_partials(const LossArgs a
         for (int r = 0; r < R; ++r) {
             double prod = static_cast<double>(a.U[0][lo * R + r]);
             for (int m = 1; m < nm; ++m)
-                prod *= static_cast<double>(a.U[m][static_cast<int64_t>(rec[m - 1]) * R + r]);
+                prod *= static_cast<double>(a.U[m][static_cast<int64_t>(rec[m - 1]) + r]);  // coordinate * R
             pred += prod;
         }
         const double res = static_cast<double>(__uint_as_float(rec[nm - 1])) - pred;
@@ -1055,7 +1209,7 @@ hipError_t launch_items_rp(const RowArgs &a, hipStream_t s)
 template <bool BF16, int KIND>
 hipError_t launch_items16_part(const RowArgs &a, hipStream_t s)
 {
-    const int count = KIND == 1 ? a.n_items - a.n_partial : KIND == 0 ? a.n_partial : a.n_items;
+    const int count = a.n_group;
     if (count <= 0)
         return hipSuccess;
     const dim3 grid((count + 3) / 4);
@@ -1069,20 +1223,30 @@ hipError_t launch_items16_part(const RowArgs &a, hipStream_t s)
 }
 
 template <bool BF16>
+hipError_t launch_chunks16(const RowArgs &a, hipStream_t s)
+{
+    const int nchunk = a.n_items - a.n_group;
+    if (nchunk <= 0 || a.nmodes > 4)
+        return hipSuccess;
+    if (a.nmodes == 3)
+        hipLaunchKernelGGL((k_chunk16<3, 4, BF16>), dim3(nchunk), dim3(256), 0, s, a);
+    else if (a.nmodes == 4)
+        hipLaunchKernelGGL((k_chunk16<4, 4, BF16>), dim3(nchunk), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_chunk16<2, 4, BF16>), dim3(nchunk), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <bool BF16>
 hipError_t launch_items16(const RowArgs &a, hipStream_t s)
 {
     if (a.nmodes > 4) {
-        hipLaunchKernelGGL((k_rows16_nm<BF16>), dim3((a.n_items + 3) / 4), dim3(64), 0, s, a);
+        // 5 <= N <= 8: every item (whole rows and chunks) in the group kernel
+        if (a.n_items > 0)
+            hipLaunchKernelGGL((k_rows16_nm<BF16>), dim3((a.n_items + 3) / 4), dim3(64), 0, s, a);
         return hipGetLastError();
     }
-#if NTC_SPLIT_LAUNCH
-    hipError_t e = launch_items16_part<BF16, 0>(a, s);
-    if (e != hipSuccess)
-        return e;
     return launch_items16_part<BF16, 1>(a, s);
-#else
-    return launch_items16_part<BF16, 2>(a, s);
-#endif
 }
 
 template <bool BF16>
@@ -1138,6 +1302,13 @@ hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t 
     if (a.n_split <= 0)
         return hipSuccess;
     return bf16 ? launch_final_b<true>(a, rp, s) : launch_final_b<false>(a, rp, s);
+}
+
+hipError_t launch_row_chunks(const RowArgs &a, int rp, bool bf16, hipStream_t s)
+{
+    if (rp != 16)
+        return hipSuccess;
+    return bf16 ? launch_chunks16<true>(a, s) : launch_chunks16<false>(a, s);
 }
 
 hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s)

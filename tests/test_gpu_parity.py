@@ -91,6 +91,11 @@ CASES = {
                                   dict(c=1.0, max_inner=3, lam=0.01)),
     "lambda0_inner5": lambda: (synth.make_problem((80, 60, 50), 40_000, 4, seed=9, noise_var=0.01), 4,
                                dict(c=0.25, lam=0.0, max_inner=5)),
+    # unconverged power method: every kernel must reproduce the oracle's T-th iterate, not lambda_max
+    "zipf_power0": lambda: (synth.c1_small(seed=6), 16, dict(c=0.1, power_iters=0)),
+    "zipf_power1": lambda: (synth.c1_small(seed=6), 16, dict(c=0.1, power_iters=1)),
+    "zipf_power3_inner2": lambda: (synth.c1_small(seed=7), 16, dict(c=0.1, power_iters=3, max_inner=2)),
+    "r8_power2_lam0": lambda: (synth.c0(seed=3), 8, dict(c=0.3, power_iters=2, lam=0.0)),
 }
 
 

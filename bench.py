@@ -18,7 +18,6 @@ Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 2] [--scale 1.0]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -50,14 +49,6 @@ def algorithmic_bytes(nmodes: int, R: int, samples: int, rows: int, max_inner: i
     return per_upd, samples * per_upd, rows * 16 + rows * 4 * R * 2 + (rows * 2 * R if bf16 else 0)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for fn in ["ntc_kernels.hip", "ntc_rng.h", "ntc_internal.h"]:
-        with open(os.path.join(ROOT, "paper_2109_09534_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(name: str):
     """Measured HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 --pmc summary, if it was taken on the current kernel source."""
@@ -69,7 +60,8 @@ def load_traffic(name: str):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    from paper_2109_09534_amd.profiling import source_hash
+    if d.get("kernel_source_hash") != source_hash():
         return None
     return d
 
@@ -144,7 +136,8 @@ def main():
     avg_ms = kd["ms"] / kd["launches"]
     bytes_per_launch = kd["bytes"] / kd["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic_rec = load_traffic(f"{dom}_c1{'_bf16' if args.bf16 else ''}_traffic.json")
+    kfile = KERNEL_NAMES[dom].split("<")[0]
+    traffic_rec = load_traffic(f"{kfile}_c1{'_bf16' if args.bf16 else ''}_traffic.json")
     traffic = traffic_rec["hbm_bytes_per_launch"] if traffic_rec else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

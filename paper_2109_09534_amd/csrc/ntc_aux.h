@@ -1,0 +1,39 @@
+// Device-side interfaces of the auxiliary kernels (loss, init, BF16 refresh,
+// sampler probe).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ntc_internal.h"
+
+namespace ntc {
+
+struct LossArgs {
+    const uint32_t *records0;     // CSR records of mode 0 (coordinates * R)
+    const uint32_t *row0;         // [nnz] row * R of every mode-0 record, or null
+    int32_t row_word;             // record word holding row * R when row0 is null
+    int64_t nnz;
+    const int32_t *test_coords;
+    const float *test_values;
+    int64_t n_test;
+    const float *U[kMaxModes];
+    int64_t dims[kMaxModes];
+    int32_t nmodes;
+    int32_t rec_words;
+    int32_t R;
+    double *part;                 // [4][kLossBlocks]: train SSE, test SSE, test sum x^2, sum U^2
+    double *out;                  // [4]
+};
+
+constexpr int kLossBlocks = 512;
+constexpr int kLossThreads = 256;
+
+hipError_t launch_loss(const LossArgs &a, hipStream_t s);
+hipError_t launch_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale,
+                              hipStream_t s);
+hipError_t launch_to_bf16(const float *U, uint16_t *U16, int64_t count, hipStream_t s);
+hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed, int64_t k, int32_t mode,
+                               int32_t l, double c, int32_t *pos_out, int32_t *count_out, hipStream_t s);
+
+}  // namespace ntc

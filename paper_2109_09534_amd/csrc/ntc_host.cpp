@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ntc.h"
+#include "ntc_aux.h"
 #include "ntc_internal.h"
 #include "ntc_rng.h"
 
@@ -82,8 +83,11 @@ void parallel_for(int64_t n, F &&f)
 // contiguous chunks so that ties keep COO order.  Writes rowptr [I+1] and,
 // if given, the records [nnz][rw] (other-mode coordinates times R, in
 // increasing mode order, then the value bits) and/or the permutation [nnz].
+// own_word >= 0 also stores the entry's own coordinate times R in that
+// (otherwise padding) word of the record, for the loss.
 void csr_build(int nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords, const float *values, int mode,
-               int rw, std::vector<int64_t> &rowptr, uint32_t *records, int64_t *perm, uint32_t rank = 1)
+               int rw, std::vector<int64_t> &rowptr, uint32_t *records, int64_t *perm, uint32_t rank = 1,
+               int own_word = -1)
 {
     const int64_t I = dims[mode];
     const unsigned T = (nnz < (1 << 16)) ? 1u : host_threads();
@@ -136,6 +140,8 @@ void csr_build(int nmodes, const int64_t *dims, int64_t nnz, const int32_t *coor
                 rec[w++] = vb;
                 for (; w < rw; ++w)
                     rec[w] = 0u;
+                if (own_word >= 0)
+                    rec[own_word] = static_cast<uint32_t>(ce[mode]) * rank;
             }
         }
     };
@@ -199,6 +205,8 @@ struct ntc_problem {
     float *test_values = nullptr;
     double *loss_part = nullptr;
     double *loss_out = nullptr;
+    uint32_t *row0 = nullptr;  // row * R per mode-0 record when the record has no spare word
+    int32_t row_word = -1;     // record word of mode 0 holding row * R
     int32_t *dbg = nullptr;  // debug sampler output [max row length + 1]
     int64_t max_row = 0;
 
@@ -514,8 +522,21 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
     for (int m = 0; m < N; ++m) {
         ModeState &md = h->md[m];
         md.I = dims[m];
+        // mode 0's records also carry the row (times R) for the loss: in the
+        // padding word when there is one, else in a separate array
+        const int own = (m == 0 && N < h->rw) ? N : -1;
         csr_build(N, dims, nnz, coords, values, m, h->rw, md.h_rowptr, rec.data(), nullptr,
-                  static_cast<uint32_t>(R));
+                  static_cast<uint32_t>(R), own);
+        if (m == 0 && own < 0 && nnz > 0) {
+            std::vector<uint32_t> rowR(static_cast<size_t>(nnz));
+            for (int64_t r = 0; r < md.I; ++r)
+                for (int64_t e = md.h_rowptr[r]; e < md.h_rowptr[r + 1]; ++e)
+                    rowR[e] = static_cast<uint32_t>(r * R);
+            NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->row0), static_cast<size_t>(nnz) * 4, "loss rows"));
+            NTC_HIP(hipMemcpy(h->row0, rowR.data(), static_cast<size_t>(nnz) * 4, hipMemcpyHostToDevice));
+        }
+        if (m == 0)
+            h->row_word = own;
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.rowptr), (md.I + 1) * sizeof(int64_t), "rowptr"));
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.records),
                               static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw * 4, "records"));
@@ -717,10 +738,10 @@ ntc_status ntc_loss(ntc_handle h, double out[4])
     if (!h || !out)
         return fail(NTC_EINVAL, "null argument");
     ntc::LossArgs a{};
-    a.rowptr0 = h->md[0].rowptr;
     a.records0 = h->md[0].records;
+    a.row0 = h->row0;
+    a.row_word = h->row_word;
     a.nnz = h->nnz;
-    a.I0 = h->dims[0];
     a.test_coords = h->test_coords;
     a.test_values = h->test_values;
     a.n_test = h->n_test;

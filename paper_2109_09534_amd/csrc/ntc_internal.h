@@ -65,25 +65,6 @@ struct RowArgs {
 // Rows whose minibatch has at most this many samples run one row per lane.
 constexpr int kTinyB = 4;
 
-struct LossArgs {
-    const int64_t *rowptr0;       // CSR of mode 0
-    const uint32_t *records0;     // coordinates * R
-    int64_t nnz;
-    int64_t I0;
-    const int32_t *test_coords;
-    const float *test_values;
-    int64_t n_test;
-    const float *U[kMaxModes];
-    int64_t dims[kMaxModes];
-    int32_t nmodes;
-    int32_t rec_words;
-    int32_t R;
-    double *part;                 // [4][kLossBlocks]: train SSE, test SSE, test sum x^2, sum U^2
-    double *out;                  // [4]
-};
-
-constexpr int kLossBlocks = 512;
-constexpr int kLossThreads = 256;
 
 // R <= 16: whole rows one per 16-lane group (5 <= N <= 8: also every chunk)
 // R > 16: every item, one per wave
@@ -92,11 +73,5 @@ hipError_t launch_row_items(const RowArgs &a, int rp, bool bf16, hipStream_t s);
 hipError_t launch_row_chunks(const RowArgs &a, int rp, bool bf16, hipStream_t s);
 hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t s);
 hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s);
-hipError_t launch_loss(const LossArgs &a, hipStream_t s);
-hipError_t launch_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale,
-                              hipStream_t s);
-hipError_t launch_to_bf16(const float *U, uint16_t *U16, int64_t count, hipStream_t s);
-hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed, int64_t k, int32_t mode,
-                               int32_t l, double c, int32_t *pos_out, int32_t *count_out, hipStream_t s);
 
 }  // namespace ntc

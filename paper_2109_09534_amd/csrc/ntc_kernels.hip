@@ -15,6 +15,7 @@
 // (g, H) and the finalize kernel combines the partials in slot order.
 #include <hip/hip_runtime.h>
 
+#include "ntc_bf16.h"
 #include "ntc_internal.h"
 #include "ntc_rng.h"
 
@@ -30,19 +31,6 @@
 
 namespace ntc {
 namespace {
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t b)
-{
-    return __uint_as_float(static_cast<uint32_t>(b) << 16);
-}
-
-// round-to-nearest-even FP32 -> BF16 (inputs are finite)
-__device__ __forceinline__ uint16_t f32_to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
-}
 
 template <int W>
 __device__ __forceinline__ float group_sum(float v)
@@ -1061,139 +1049,6 @@ __global__ __launch_bounds__(256) void k_finalize16(const RowArgs a)
     finish_row16<BF16>(a, sr.row, r, g, hd, y);
 }
 
-// ------------------------------------------------------------------ loss
-__device__ __forceinline__ double block_sum(double v, double *s)
-{
-    // fixed-shape tree: deterministic for a fixed blockDim
-    const int t = threadIdx.x;
-    s[t] = v;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if (t < st)
-            s[t] += s[t + st];
-        __syncthreads();
-    }
-    const double r = s[0];
-    __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(kLossThreads) void k_loss_partials(const LossArgs a)
-{
-    __shared__ double s[kLossThreads];
-    const int R = a.R;
-    const int nm = a.nmodes;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    // training entries, walked through the mode-0 CSR
-    double sse = 0.0;
-    for (int64_t e = tid; e < a.nnz; e += stride) {
-        int64_t lo = 0, hi = a.I0;  // find p with rowptr[p] <= e < rowptr[p+1]
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (a.rowptr0[mid] <= e)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const uint32_t *rec = a.records0 + e * a.rec_words;
-        double pred = 0.0;
-        for (int r = 0; r < R; ++r) {
-            double prod = static_cast<double>(a.U[0][lo * R + r]);
-            for (int m = 1; m < nm; ++m)
-                prod *= static_cast<double>(a.U[m][static_cast<int64_t>(rec[m - 1]) + r]);  // coordinate * R
-            pred += prod;
-        }
-        const double res = static_cast<double>(__uint_as_float(rec[nm - 1])) - pred;
-        sse += res * res;
-    }
-    double tse = 0.0, tsx = 0.0;
-    for (int64_t e = tid; e < a.n_test; e += stride) {
-        const int32_t *cc = a.test_coords + e * nm;
-        double pred = 0.0;
-        for (int r = 0; r < R; ++r) {
-            double prod = 1.0;
-            for (int m = 0; m < nm; ++m)
-                prod *= static_cast<double>(a.U[m][static_cast<int64_t>(cc[m]) * R + r]);
-            pred += prod;
-        }
-        const double x = static_cast<double>(a.test_values[e]);
-        const double res = x - pred;
-        tse += res * res;
-        tsx += x * x;
-    }
-    double reg = 0.0;
-    for (int m = 0; m < nm; ++m) {
-        const int64_t cntm = a.dims[m] * R;
-        for (int64_t t = tid; t < cntm; t += stride) {
-            const double u = static_cast<double>(a.U[m][t]);
-            reg += u * u;
-        }
-    }
-    sse = block_sum(sse, s);
-    tse = block_sum(tse, s);
-    tsx = block_sum(tsx, s);
-    reg = block_sum(reg, s);
-    if (threadIdx.x == 0) {
-        a.part[0 * kLossBlocks + blockIdx.x] = sse;
-        a.part[1 * kLossBlocks + blockIdx.x] = tse;
-        a.part[2 * kLossBlocks + blockIdx.x] = tsx;
-        a.part[3 * kLossBlocks + blockIdx.x] = reg;
-    }
-}
-
-__global__ __launch_bounds__(kLossThreads) void k_loss_final(const LossArgs a)
-{
-    __shared__ double s[kLossThreads];
-    for (int q = 0; q < 4; ++q) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < kLossBlocks; b += blockDim.x)
-            v += a.part[q * kLossBlocks + b];
-        v = block_sum(v, s);
-        if (threadIdx.x == 0)
-            a.out[q] = v;
-    }
-}
-
-// ------------------------------------------------------------- init, bf16
-__global__ void k_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale)
-{
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= count)
-        return;
-    const uint64_t blk = static_cast<uint64_t>(t) >> 2;
-    const U32x4 ctr = {{static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32), static_cast<uint32_t>(mode),
-                        kTagInit}};
-    const U32x4 o = philox4x32_10(ctr, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
-    const float u = static_cast<float>(o.v[t & 3] >> 8) * 5.9604644775390625e-08f;  // 2^-24
-    const float val = u * scale;
-    U[t] = val;
-    if (U16)
-        U16[t] = f32_to_bf16(val);
-}
-
-__global__ void k_to_bf16(const float *U, uint16_t *U16, int64_t count)
-{
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t < count)
-        U16[t] = f32_to_bf16(U[t]);
-}
-
-__global__ void k_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed, int64_t k, int32_t mode,
-                               int32_t l, double c, int32_t *pos, int32_t *count)
-{
-    const int64_t n = rowptr[row + 1] - rowptr[row];
-    const int64_t b = minibatch_size(c, n);
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *count = static_cast<int32_t>(b);
-    if (b <= 0)
-        return;
-    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(seed, k, mode, l, row));
-    for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < b;
-         j += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        pos[j] = static_cast<int32_t>(prp_index(prp, static_cast<uint32_t>(j)));
-}
-
 template <int RP, bool BF16>
 hipError_t launch_items_rp(const RowArgs &a, hipStream_t s)
 {
@@ -1332,41 +1187,6 @@ hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s)
     else
         NTC_TINY(0, 8);
 #undef NTC_TINY
-    return hipGetLastError();
-}
-
-hipError_t launch_loss(const LossArgs &a, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_loss_partials, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale,
-                              hipStream_t s)
-{
-    if (count <= 0)
-        return hipSuccess;
-    const int64_t blocks = (count + 255) / 256;
-    hipLaunchKernelGGL(k_init_factor, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, U, U16, count, mode, seed,
-                       scale);
-    return hipGetLastError();
-}
-
-hipError_t launch_to_bf16(const float *U, uint16_t *U16, int64_t count, hipStream_t s)
-{
-    if (count <= 0)
-        return hipSuccess;
-    const int64_t blocks = (count + 255) / 256;
-    hipLaunchKernelGGL(k_to_bf16, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, U, U16, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed, int64_t k, int32_t mode,
-                               int32_t l, double c, int32_t *pos_out, int32_t *count_out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_debug_sample, dim3(64), dim3(256), 0, s, rowptr, row, seed, k, mode, l, c, pos_out,
-                       count_out);
     return hipGetLastError();
 }
 

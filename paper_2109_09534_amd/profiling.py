@@ -1,0 +1,138 @@
+"""Summaries of rocprofv3 output for the row kernels.
+
+rocprofv3 writes a SQLite database per run.  This module turns one into
+the short text summaries kept beside the code:
+
+* ``trace``   -- per-kernel statistics (``--kernel-trace --stats``) and the
+  dispatch table of the last sweep's row kernels, as Markdown;
+* ``traffic`` -- HBM bytes per launch of one kernel from two ``--pmc`` runs
+  (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+  same counter reads for a plain device copy of known size, as JSON tagged
+  with a hash of the row-kernel sources it was taken on.
+
+Usage:
+  python -m paper_2109_09534_amd.profiling trace DIR --title T --command C [--last 9]
+  python -m paper_2109_09534_amd.profiling traffic --kernel K --fetch DIR --write DIR
+         --copy-fetch DIR --copy-write DIR --copy-bytes B --command C [--out FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROW_KERNEL_SOURCES = ["ntc_kernels.hip", "ntc_rng.h", "ntc_bf16.h", "ntc_internal.h"]
+ROW_KERNELS = ("k_rows16", "k_chunk16", "k_tiny16", "k_finalize16", "k_row_items", "k_row_finalize",
+               "k_rows16_nm")
+
+
+def source_hash() -> str:
+    """Hash of the sources the row kernels are compiled from."""
+    h = hashlib.sha256()
+    for fn in ROW_KERNEL_SOURCES:
+        with open(os.path.join(PKG, "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _db(path: str) -> sqlite3.Connection:
+    dbs = glob.glob(os.path.join(path, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise FileNotFoundError(f"no rocprofv3 database under {path}")
+    return sqlite3.connect(dbs[0])
+
+
+def short_name(name: str) -> str:
+    name = name.replace("ntc::(anonymous namespace)::", "").replace("ntc::", "")
+    return re.sub(r"^void ", "", name).split("(")[0]
+
+
+def trace(path: str, title: str, command: str, last: int = 9) -> str:
+    con = _db(path)
+    out = [f"# {title}", "", "Command (from the repository root; REPO is its absolute path):", "",
+           "```", command, "```", "",
+           "## Kernel statistics (rocprofv3 --stats; durations in microseconds)", "",
+           "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for name, calls, total, avg, pct in con.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels"):
+        out.append(f"| `{short_name(name)}` | {calls} | {total:.1f} | {avg:.1f} | {pct:.2f} |")
+    like = " or ".join(f"name like '%{k}%'" for k in ROW_KERNELS)
+    rows = list(con.execute(f"select name, grid_x, workgroup_x, duration, vgpr_count, accum_vgpr_count, "
+                            f"lds_size, scratch_size from kernels where {like} order by start"))
+    out += ["", f"## Row-kernel dispatches of the last sweep ({min(last, len(rows))} launches, in order)", "",
+            "| kernel | grid (threads) | block | duration us | VGPR | AGPR | LDS B | scratch B |",
+            "|---|---|---|---|---|---|---|---|"]
+    for name, grid, wg, dur, vgpr, agpr, lds, scratch in rows[-last:]:
+        out.append(f"| `{short_name(name)}` | {grid} | {wg} | {dur / 1e3:.1f} | {vgpr} | {agpr} | {lds} | {scratch} |")
+    return "\n".join(out) + "\n"
+
+
+def _per_dispatch(path: str, counter: str):
+    con = _db(path)
+    q = ("select dispatch_id, kernel_name, sum(value) from counters_collection where counter_name = ? "
+         "group by dispatch_id order by dispatch_id")
+    return [(d, short_name(n), v) for d, n, v in con.execute(q, (counter,))]
+
+
+def traffic(kernel: str, fetch: str, write: str, copy_fetch: str, copy_write: str, copy_bytes: int,
+            command: str) -> dict:
+    """HBM bytes per launch of `kernel` (name prefix, e.g. 'k_chunk16<3, 4, false>')."""
+    kib = 1024.0
+    scale = {}
+    for counter, path, expect in (("FETCH_SIZE", copy_fetch, copy_bytes), ("WRITE_SIZE", copy_write, copy_bytes)):
+        copies = [v for _, n, v in _per_dispatch(path, counter) if "copyBuffer" in n]
+        if not copies:
+            raise RuntimeError(f"no copy dispatch in {path}")
+        counted = sum(copies) / len(copies) * kib
+        scale[counter] = expect / counted
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch), ("WRITE_SIZE", write)):
+        vals = [v for _, n, v in _per_dispatch(path, counter) if n.startswith(kernel)]
+        if not vals:
+            raise RuntimeError(f"no dispatch of {kernel} in {path}")
+        per[counter] = vals
+    n = min(len(per["FETCH_SIZE"]), len(per["WRITE_SIZE"]))
+    fetch_b = sum(per["FETCH_SIZE"][:n]) / n * kib * scale["FETCH_SIZE"]
+    write_b = sum(per["WRITE_SIZE"][:n]) / n * kib * scale["WRITE_SIZE"]
+    return {"kernel": kernel, "launches": n, "hbm_bytes_per_launch": round(fetch_b + write_b),
+            "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
+            "fetch_kib_per_dispatch": per["FETCH_SIZE"][:n], "write_kib_per_dispatch": per["WRITE_SIZE"][:n],
+            "copy_bytes": copy_bytes, "scale": {k: round(v, 4) for k, v in scale.items()},
+            "kernel_source_hash": source_hash(), "command": command}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2109_09534_amd.profiling")
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--title", required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--last", type=int, default=9)
+    t.add_argument("--out")
+    f = sub.add_parser("traffic")
+    for k in ("kernel", "fetch", "write", "copy-fetch", "copy-write", "command"):
+        f.add_argument("--" + k, required=True)
+    f.add_argument("--copy-bytes", type=int, required=True)
+    f.add_argument("--out")
+    a = ap.parse_args(argv)
+    if a.what == "trace":
+        text = trace(a.dir, a.title, a.command, a.last)
+    else:
+        text = json.dumps(traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.command),
+                          indent=1) + "\n"
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(text)
+    else:
+        sys.stdout.write(text)
+
+
+if __name__ == "__main__":
+    main()

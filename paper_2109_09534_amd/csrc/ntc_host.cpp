@@ -13,6 +13,7 @@
 #include "ntc.h"
 #include "ntc_aux.h"
 #include "ntc_internal.h"
+#include "ntc_problem.h"
 #include "ntc_rng.h"
 
 using ntc::Item;
@@ -27,6 +28,15 @@ ntc_status fail(ntc_status s, const std::string &msg)
     g_last_error = msg;
     return s;
 }
+
+}  // namespace
+
+ntc_status ntc::set_error(ntc_status s, const std::string &msg)
+{
+    return fail(s, msg);
+}
+
+namespace {
 
 #define NTC_HIP(expr)                                                                                    \
     do {                                                                                                 \
@@ -205,6 +215,10 @@ struct ntc_problem {
     float *test_values = nullptr;
     double *loss_part = nullptr;
     double *loss_out = nullptr;
+    int64_t *kdev = nullptr;            // device copy of the sweep counter k
+    ntc::RowArgs *args_dev = nullptr;  // [N][max_inner] row-kernel arguments (static after create)
+    std::vector<ntc::RowArgs> args_host;  // host copy of args_dev
+    size_t bytes = 0;                   // device bytes held
     uint32_t *row0 = nullptr;  // row * R per mode-0 record when the record has no spare word
     int32_t row_word = -1;     // record word of mode 0 holding row * R
     int32_t *dbg = nullptr;  // debug sampler output [max row length + 1]
@@ -221,8 +235,10 @@ struct ntc_problem {
             (void)hipGetLastError();
             p = nullptr;
         }
-        if (p)
+        if (p) {
             owned.push_back(p);
+            this->bytes += bytes;
+        }
         return p;
     }
 
@@ -269,6 +285,11 @@ ntc_status alloc_or_fail(ntc_problem *h, void **dst, size_t bytes, const char *w
             return s_;                \
     } while (0)
 
+ntc::KernelClass kernel_class(const ntc_problem *h)
+{
+    return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0};
+}
+
 ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
 {
     ntc::RowArgs a{};
@@ -301,7 +322,7 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.A16 = h->U16[mode];
     a.partials = h->partials;
     a.seed = h->seed;
-    a.k = h->k;
+    a.kptr = h->kdev;
     a.lambda = h->lambda;
     a.mode = mode;
     a.l = l;
@@ -326,13 +347,11 @@ struct LaunchProbe {
 ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
 {
     const ModeState &md = h->md[mode];
+    const ntc::KernelClass kc = kernel_class(h);
     for (int l = 0; l < h->max_inner; ++l) {
-        const ntc::RowArgs a = row_args(h, mode, l);
-        // the one-row-per-lane rows are disjoint from the other rows: with a
-        // side stream they run concurrently (fork/join through events)
-        const bool group16 = h->RP == 16 && h->N <= 4;
-        const int32_t n_chunk = group16 ? md.n_items - md.n_group : 0;
-        const int32_t n_rows = group16 ? md.n_group : md.n_items;
+        ntc::Launch L{};
+        L.args = h->args_dev + mode * h->max_inner + l;
+        L.n = 1;
         // the one-row-per-lane rows are disjoint from the other rows: with a
         // side stream they run concurrently (fork/join through events); a
         // profiled sweep runs everything on one stream
@@ -342,11 +361,11 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
             NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         }
         // launch order: one-row-per-lane, chunks, rows, finalize of split rows
-        for (int kern : {2, 3, 0, 1}) {
-            const int32_t count = kern == 0 ? n_rows : kern == 1 ? md.n_split : kern == 2 ? md.n_tiny : n_chunk;
-            if (count <= 0)
+        for (ntc::RowKernel kern : {ntc::kTiny, ntc::kChunks, ntc::kRows, ntc::kFinalize}) {
+            L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny);
+            if (L.blocks <= 0)
                 continue;
-            hipStream_t st = (kern == 2 && fork) ? h->side : h->stream;
+            hipStream_t st = (kern == ntc::kTiny && fork) ? h->side : h->stream;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (probe) {
                 NTC_HIP(hipEventCreate(&e0));
@@ -355,25 +374,18 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
                 probe->ev.push_back(e1);
                 NTC_HIP(hipEventRecord(e0, st));
             }
-            if (kern == 0)
-                NTC_HIP(ntc::launch_row_items(a, h->RP, h->bf16, st));
-            else if (kern == 1)
-                NTC_HIP(ntc::launch_row_finalize(a, h->RP, h->bf16, st));
-            else if (kern == 2)
-                NTC_HIP(ntc::launch_row_tiny(a, h->bf16, st));
-            else
-                NTC_HIP(ntc::launch_row_chunks(a, h->RP, h->bf16, st));
+            NTC_HIP(ntc::launch_row_kernel(kern, kc, L, st));
             if (probe) {
                 NTC_HIP(hipEventRecord(e1, st));
                 ntc_launch_record r{};
                 r.kernel = kern;
                 r.mode = mode;
                 r.inner = l;
-                r.blocks = kern == 0 ? (h->RP == 16 ? (n_rows + 3) / 4 : n_rows)
-                           : kern == 1 ? md.n_split : kern == 2 ? (md.n_tiny + 255) / 256 : n_chunk;
-                r.samples = kern == 0 ? md.row_samples : kern == 1 ? 0 : kern == 2 ? md.tiny_samples
-                                                                             : md.chunk_samples;
-                r.rows = kern == 0 ? md.row_fused : kern == 1 ? md.n_split : kern == 2 ? md.n_tiny : md.chunk_fused;
+                r.blocks = L.blocks;
+                r.samples = kern == ntc::kRows ? md.row_samples : kern == ntc::kFinalize ? 0
+                            : kern == ntc::kTiny ? md.tiny_samples : md.chunk_samples;
+                r.rows = kern == ntc::kRows ? md.row_fused : kern == ntc::kFinalize ? md.n_split
+                         : kern == ntc::kTiny ? md.n_tiny : md.chunk_fused;
                 probe->rec.push_back(r);
             }
         }
@@ -648,6 +660,20 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
     NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->loss_out), 4 * sizeof(double), "loss out"));
     NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->dbg), (h->max_row + 1) * sizeof(int32_t), "debug"));
 
+    // device sweep counter and the row-kernel argument table of every (mode, inner step)
+    NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->kdev), sizeof(int64_t), "sweep counter"));
+    NTC_HIP(hipMemcpy(h->kdev, &h->k, sizeof(int64_t), hipMemcpyHostToDevice));
+    {
+        std::vector<ntc::RowArgs> &tab = h->args_host;
+        tab.clear();
+        for (int m = 0; m < N; ++m)
+            for (int l = 0; l < h->max_inner; ++l)
+                tab.push_back(row_args(h, m, l));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->args_dev), tab.size() * sizeof(ntc::RowArgs),
+                              "row arguments"));
+        NTC_HIP(hipMemcpy(h->args_dev, tab.data(), tab.size() * sizeof(ntc::RowArgs), hipMemcpyHostToDevice));
+    }
+
     // initial factors
     if (p.init_factors) {
         for (int m = 0; m < N; ++m) {
@@ -671,6 +697,40 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
 }
 
 }  // namespace
+
+ntc_status ntc::problem_view(ntc_handle h, ntc::ProblemView *v)
+{
+    if (!h || !v)
+        return fail(NTC_EINVAL, "null argument");
+    v->kc = kernel_class(h);
+    v->nmodes = h->N;
+    v->rank = h->R;
+    v->max_inner = h->max_inner;
+    v->args_host = h->args_host.data();
+    v->kdev = h->kdev;
+    for (int m = 0; m < h->N; ++m) {
+        const ModeState &md = h->md[m];
+        for (int kind = 0; kind < 4; ++kind)
+            v->blocks[m][kind] = ntc::row_kernel_blocks(static_cast<ntc::RowKernel>(kind), v->kc, md.n_items,
+                                                        md.n_group, md.n_split, md.n_tiny);
+        v->U[m] = h->U[m];
+    }
+    v->n_test = h->n_test;
+    v->test_coords = h->test_coords;
+    v->test_values = h->test_values;
+    v->bytes = h->bytes;
+    v->k = h->k;
+    int64_t u = 0;
+    for (int m = 0; m < h->N; ++m)
+        u += h->md[m].samples * h->max_inner;
+    v->updates_per_sweep = u;
+    return NTC_OK;
+}
+
+void ntc::note_sweeps(ntc_handle h, int64_t n)
+{
+    h->k += n;
+}
 
 // ======================================================================= ABI
 extern "C" {
@@ -722,6 +782,7 @@ ntc_status ntc_sweep(ntc_handle h, int32_t nsweeps)
     for (int32_t s = 0; s < nsweeps; ++s) {
         for (int m = 0; m < h->N; ++m)
             NTC_TRY(enqueue_mode(h, m));
+        NTC_HIP(ntc::launch_advance(h->kdev, 1, h->stream));
         h->k += 1;
     }
     return NTC_OK;
@@ -815,6 +876,8 @@ ntc_status ntc_set_sweep(ntc_handle h, int64_t k)
         return fail(NTC_EINVAL, "null handle");
     if (k < 0)
         return fail(NTC_EINVAL, "k must be >= 0");
+    NTC_TRY(sync(h));
+    NTC_HIP(hipMemcpy(h->kdev, &k, sizeof(int64_t), hipMemcpyHostToDevice));
     h->k = k;
     return NTC_OK;
 }
@@ -927,8 +990,11 @@ ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, 
     ntc_status s = NTC_OK;
     for (int m = 0; m < h->N && s == NTC_OK; ++m)
         s = enqueue_mode(h, m, &probe);
-    if (s == NTC_OK)
+    if (s == NTC_OK) {
+        if (ntc::launch_advance(h->kdev, 1, h->stream) != hipSuccess)
+            s = fail(NTC_EDEVICE, "launch of the sweep-counter update failed");
         h->k += 1;
+    }
     hipError_t se = hipStreamSynchronize(h->stream);
     if (se == hipSuccess && h->side)
         se = hipStreamSynchronize(h->side);

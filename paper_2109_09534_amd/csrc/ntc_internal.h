@@ -44,7 +44,7 @@ struct RowArgs {
     uint32_t zrec[8];             // record of a missing sample: the all-zero row (index I_m) of each
                                   // other mode, value 0
     uint64_t seed;
-    int64_t k;
+    const int64_t *kptr;          // sweep counter k of the problem (device)
     double lambda;
     double c;
     int32_t mode;
@@ -66,12 +66,36 @@ struct RowArgs {
 constexpr int kTinyB = 4;
 
 
-// R <= 16: whole rows one per 16-lane group (5 <= N <= 8: also every chunk)
-// R > 16: every item, one per wave
-hipError_t launch_row_items(const RowArgs &a, int rp, bool bf16, hipStream_t s);
-// R <= 16 and N <= 4: row chunks of rows with many samples, one per 256-thread block
-hipError_t launch_row_chunks(const RowArgs &a, int rp, bool bf16, hipStream_t s);
-hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t s);
-hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s);
+// One launch of a row kernel over n entries (problems).  args: [n] device
+// RowArgs.  For n > 1, start: [n] first block of each entry, owner:
+// [blocks] entry of each block (both device); for n == 1 both may be null.
+struct Launch {
+    const RowArgs *args;
+    const int32_t *start;
+    const int32_t *owner;
+    int32_t n;
+    int32_t blocks;
+};
+
+// Kernel family of a problem: padded rank (16, 32, 64), mode count, BF16 gathers.
+struct KernelClass {
+    int32_t rp;
+    int32_t nmodes;
+    int32_t bf16;
+};
+
+// The row kernels.  R <= 16: kRows takes whole rows with B_p <= group_max, one
+// per 16-lane group (for N > 4 also every chunk); kChunks takes row chunks,
+// one per 256-thread block; kTiny rows with B_p <= kTinyB, one per lane;
+// kFinalize combines the partial slots of split rows.  R > 16: kRows takes
+// every work item, one per wave.
+enum RowKernel { kRows = 0, kFinalize = 1, kTiny = 2, kChunks = 3 };
+
+// Grid blocks one problem needs for `kind`.
+int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items, int32_t n_group, int32_t n_split,
+                          int32_t n_tiny);
+hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s);
+// k[t] += 1 for t < n (the sweep counters, once per sweep)
+hipError_t launch_advance(int64_t *k, int32_t n, hipStream_t s);
 
 }  // namespace ntc

@@ -19,18 +19,28 @@
 #include "ntc_internal.h"
 #include "ntc_rng.h"
 
-#ifndef NTC_HACC_LDS
-#define NTC_HACC_LDS 1
-#endif
-#ifndef NTC_SPLIT_LAUNCH
-#define NTC_SPLIT_LAUNCH 0
-#endif
-#ifndef NTC_WAVES3
-#define NTC_WAVES3 4
-#endif
 
 namespace ntc {
 namespace {
+
+// Every row kernel runs one launch over one or many problems (a Launch):
+// block b belongs to entry owner[b] (entry 0 when there is one entry) and is
+// that entry's local block b - start[entry].  The entry's RowArgs are read
+// through the constant address space: they never change during a launch, so
+// every field is a scalar load that the compiler may repeat at any point
+// instead of holding it in registers.
+typedef const __attribute__((address_space(4))) RowArgs CRowArgs;
+#define NTC_ROW_PARAMS                                                                                       \
+    const RowArgs *__restrict__ args_, const int32_t *__restrict__ start_, const int32_t *__restrict__ owner_, \
+        const int32_t nent_
+#define NTC_ROW_RESOLVE(a, blk)                              \
+    int blk = static_cast<int>(blockIdx.x);                  \
+    int ent_ = 0;                                            \
+    if (nent_ > 1) {                                         \
+        ent_ = owner_[blockIdx.x];                           \
+        blk -= start_[ent_];                                 \
+    }                                                        \
+    CRowArgs &a = ((CRowArgs *)args_)[ent_]
 
 template <int W>
 __device__ __forceinline__ float group_sum(float v)
@@ -53,8 +63,8 @@ __device__ __forceinline__ double wave_sum(double v)
 // L_p, A_{l+1}, beta, Y_{l+1}).  Called by all 64 lanes; lanes r < RP of the
 // first group hold g[r] (sampled gradient without ridge) and row r of the
 // sampled H (without ridge); all other lanes pass zeros.
-template <int RP, bool BF16>
-__device__ void finish_row(const RowArgs &a, int row, int lane, double g, double (&h)[RP], float y, double *s_v)
+template <int RP, bool BF16, class Args>
+__device__ void finish_row(const Args &a, int row, int lane, double g, double (&h)[RP], float y, double *s_v)
 {
     const int R = a.R;
     const bool live = lane < RP && lane < R;
@@ -121,8 +131,9 @@ __device__ void finish_row(const RowArgs &a, int row, int lane, double g, double
 }
 
 template <int RP, int NM, bool BF16>
-__global__ __launch_bounds__(64) void k_row_items(const RowArgs a)
+__global__ __launch_bounds__(64) void k_row_items(NTC_ROW_PARAMS)
 {
+    NTC_ROW_RESOLVE(a, blk_);
     constexpr int G = 64 / RP;
     constexpr int RED = (G > 1) ? 64 * RP : 1;
     __shared__ uint32_t s_rec[64 * 8];
@@ -133,7 +144,7 @@ __global__ __launch_bounds__(64) void k_row_items(const RowArgs a)
 
     const int nm = (NM > 0) ? NM : a.nmodes;
     const int rw = (NM > 0) ? ((NM <= 4) ? 4 : 8) : a.rec_words;
-    const Item it = a.items[blockIdx.x];
+    const Item it = a.items[blk_];
     const int lane = threadIdx.x;
     const int r = lane % RP;
     const int grp = lane / RP;
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(64) void k_row_items(const RowArgs a)
 
     const int64_t base = a.rowptr[it.row];
     const int64_t n = a.rowptr[it.row + 1] - base;
-    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.k, a.mode, a.l, it.row));
+    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, it.row));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const float y = rlive ? ysrc[static_cast<int64_t>(it.row) * R + r] : 0.0f;
 
@@ -241,10 +252,11 @@ __global__ __launch_bounds__(64) void k_row_items(const RowArgs a)
 }
 
 template <int RP, bool BF16>
-__global__ __launch_bounds__(64) void k_row_finalize(const RowArgs a)
+__global__ __launch_bounds__(64) void k_row_finalize(NTC_ROW_PARAMS)
 {
+    NTC_ROW_RESOLVE(a, blk_);
     __shared__ double s_v[RP];
-    const SplitRow sr = a.split[blockIdx.x];
+    const SplitRow sr = a.split[blk_];
     const int lane = threadIdx.x;
     const int R = a.R;
     double g = 0.0;
@@ -337,8 +349,8 @@ __device__ __forceinline__ void skew_matvec(const double (&hd)[16], double v, do
 // this 16-lane group.  Lane r holds g[r] (sampled gradient without ridge)
 // and hd[s] = H[r][sigma_s(r)] (sampled Hessian without ridge); lanes r >= R
 // hold zeros.  No cross-group communication.
-template <bool BF16>
-__device__ void finish_row16(const RowArgs &a, int row, int r, double g, double (&hd)[16], float y)
+template <bool BF16, class Args>
+__device__ void finish_row16(const Args &a, int row, int r, double g, double (&hd)[16], float y)
 {
     const int R = a.R;
     const bool live = r < R;
@@ -409,7 +421,8 @@ struct GroupItem {
     Prp prp;
 };
 
-__device__ __forceinline__ GroupItem load_group_item(const RowArgs &a, int id)
+template <class Args>
+__device__ __forceinline__ GroupItem load_group_item(const Args &a, int id)
 {
     GroupItem g;
     g.has = id < a.n_items;
@@ -423,13 +436,13 @@ __device__ __forceinline__ GroupItem load_group_item(const RowArgs &a, int id)
         n = a.rowptr[g.it.row + 1] - g.base;
     }
     g.len = g.it.j1 - g.it.j0;
-    g.prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.k, a.mode, a.l, g.it.row));
+    g.prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, g.it.row));
     return g;
 }
 
 // Record of sample jb + r of the item (zeros past its end).
-template <int RW>
-__device__ __forceinline__ void fetch_record(const RowArgs &a, const GroupItem &g, int jb, int r, uint4 &w0,
+template <int RW, class Args>
+__device__ __forceinline__ void fetch_record(const Args &a, const GroupItem &g, int jb, int r, uint4 &w0,
                                              uint4 &w1)
 {
     w0 = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
@@ -459,8 +472,8 @@ __device__ __forceinline__ void stage_record(uint4 *buf, int lane, const uint4 &
 // Branch-free: every lane loads from an in-bounds address (a missing sample
 // has index 0 in LDS, a lane r >= R reads column 0) and the compute masks the
 // value, so all loads of the batch issue back to back.
-template <int NM, int RW, bool BF16>
-__device__ __forceinline__ void gather_batch(const RowArgs &a, const uint32_t *srec, int rr, float (&f)[NM - 1][16])
+template <int NM, int RW, bool BF16, class Args>
+__device__ __forceinline__ void gather_batch(const Args &a, const uint32_t *srec, int rr, float (&f)[NM - 1][16])
 {
 #pragma unroll
     for (int mm = 0; mm < NM - 1; ++mm) {
@@ -482,26 +495,19 @@ __device__ __forceinline__ void gather_batch(const RowArgs &a, const uint32_t *s
 // batch loop is software-pipelined: while batch b is reduced, the factor
 // gathers of batch b+1 and the record fetches of batch b+2 are in flight
 // (records double-buffered in LDS, gathered values held raw until used).
-template <int NM, int RW, bool BF16, int KIND>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NTC_WAVES3 : 2))) void k_rows16(const RowArgs a)
+template <int NM, int RW, bool BF16>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_rows16(NTC_ROW_PARAMS)
 {
+    NTC_ROW_RESOLVE(a, blk_);
     __shared__ uint4 s_rec[2][64 * (RW / 4)];
     // FP64 sum of the MFMA blocks: register v of lane l at s_h[v * 64 + l]
     __shared__ double s_h[16 * 64];
-#if !NTC_HACC_LDS
-    double hd[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v)
-        hd[v] = 0.0;
-#endif
     const int lane = threadIdx.x;
     const int r = lane & 15;
     const int grp = lane >> 4;
-    // partial items (slots) come first in the item list, whole rows after
-    const int first = 0;
-    const int last = a.n_group;
-    const int id = first + blockIdx.x * 4 + grp;
-    const GroupItem g = load_group_item(a, id < last ? id : a.n_items);
+    // whole rows: items [0, n_group), four per wave
+    const int id = blk_ * 4 + grp;
+    const GroupItem g = load_group_item(a, id < a.n_group ? id : a.n_items);
     const int R = a.R;
     const bool rlive = r < R;
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
@@ -515,11 +521,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NT
     const int nb = (maxlen + 15) / 16;
 
     double gd = 0.0;
-#if NTC_HACC_LDS
 #pragma unroll
     for (int v = 0; v < 16; ++v)
         s_h[v * 64 + lane] = 0.0;
-#endif
 
     const int rr = rlive ? r : 0;
     uint4 w0, w1;
@@ -570,11 +574,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NT
         gd += static_cast<double>(gf);
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-#if NTC_HACC_LDS
             s_h[v * 64 + lane] += static_cast<double>(acc[v]);
-#else
-            hd[v] += static_cast<double>(acc[v]);
-#endif
         __builtin_amdgcn_wave_barrier();  // the compute above read s_rec[bi & 1]
         if (bi + 2 < nb)
             stage_record<RW>(s_rec[bi & 1], lane, w0, w1);
@@ -582,31 +582,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? NT
 
     // register v of lane l holds block v/4, row 4*(l/16) + v%4, column l%16:
     // row r of this group's block is at v = 4*grp + r%4, lanes 16*(r/4) + q
-#if !NTC_HACC_LDS
-#pragma unroll
-    for (int v = 0; v < 16; ++v)
-        s_h[v * 64 + lane] = hd[v];
-#endif
     __builtin_amdgcn_wave_barrier();
     if (!g.has)
         return;
     const double *hrow = s_h + (4 * grp + (r & 3)) * 64 + 16 * (r >> 2);
-    if (KIND == 0 || (KIND == 2 && g.it.slot >= 0)) {
-        double *P = a.partials + static_cast<int64_t>(g.it.slot) * kSlot16;
-        P[r] = gd;
+    int sig[16];
+    ror_sources(r, sig);
+    double hs[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            P[16 + r * 16 + q] = hrow[q];
-        return;
-    } else {
-        int sig[16];
-        ror_sources(r, sig);
-        double hs[16];
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2)
-            hs[s2] = hrow[sig[s2]];
-        finish_row16<BF16>(a, g.it.row, r, gd, hs, y);
-    }
+    for (int s2 = 0; s2 < 16; ++s2)
+        hs[s2] = hrow[sig[s2]];
+    finish_row16<BF16>(a, g.it.row, r, gd, hs, y);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -621,9 +607,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // gradients are combined in LDS in a fixed order; a chunk that is the whole
 // row finishes it in place, otherwise it writes a partial slot.
 template <int NM, int RW, bool BF16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_chunk16(
-    const RowArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_chunk16(NTC_ROW_PARAMS)
 {
+    NTC_ROW_RESOLVE(a, blk_);
     __shared__ uint4 s_rec[4][2][64 * (RW / 4)];
     __shared__ double s_hw[4][4 * 64];  // per wave: its FP64 block sum, register v of lane l at v*64 + l
     __shared__ double s_g[16 * 16];     // per group: gradient partial of lane r
@@ -633,7 +619,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
     const int r = lane & 15;
     const int grp = lane >> 4;
     const int G = wave * 4 + grp;       // group index in the block
-    const Item it = a.items[a.n_group + blockIdx.x];
+    const Item it = a.items[a.n_group + blk_];
     const int R = a.R;
     const bool rlive = r < R;
     const int rr = rlive ? r : 0;
@@ -644,7 +630,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
     g.it = it;
     g.base = base;
     g.len = it.j1 - it.j0;
-    g.prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.k, a.mode, a.l, it.row));
+    g.prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, it.row));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const float y = rlive ? ysrc[static_cast<int64_t>(it.row) * R + r] : 0.0f;
 
@@ -747,15 +733,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
 // computation without the software pipeline; the Khatri-Rao product is
 // accumulated over a runtime mode loop.
 template <bool BF16>
-__global__ __launch_bounds__(64) void k_rows16_nm(const RowArgs a)
+__global__ __launch_bounds__(64) void k_rows16_nm(NTC_ROW_PARAMS)
 {
+    NTC_ROW_RESOLVE(a, blk_);
     __shared__ uint4 s_rec[64 * 2];
     __shared__ double s_h[4 * 256];
     const int lane = threadIdx.x;
     const int r = lane & 15;
     const int grp = lane >> 4;
     const int nm = a.nmodes;
-    const GroupItem g = load_group_item(a, blockIdx.x * 4 + grp);
+    const GroupItem g = load_group_item(a, blk_ * 4 + grp);
     const int R = a.R;
     const bool rlive = r < R;
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
@@ -845,9 +832,10 @@ __global__ __launch_bounds__(64) void k_rows16_nm(const RowArgs a)
 // as T normalised products with H, evaluated in the b-dimensional span of
 // the samples: O(T b^2) instead of O(T b R) operations per row.
 template <int NM, int RW, bool BF16>
-__global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
+__global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
 {
-    const int id = blockIdx.x * 256 + threadIdx.x;
+    NTC_ROW_RESOLVE(a, blk_);
+    const int id = blk_ * 256 + threadIdx.x;
     if (id >= a.n_tiny)
         return;
     const int nm = (NM > 0) ? NM : a.nmodes;
@@ -856,7 +844,7 @@ __global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
     const int64_t base = a.rowptr[row];
     const int64_t n = a.rowptr[row + 1] - base;
     const int b = static_cast<int>(minibatch_size(a.c, n));  // 1 .. kTinyB
-    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.k, a.mode, a.l, row));
+    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, row));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const int64_t roff = static_cast<int64_t>(row) * R;
     float y[16];
@@ -999,10 +987,11 @@ __global__ __launch_bounds__(256) void k_tiny16(const RowArgs a)
 // groups sum the row's slots with a fixed stride, a fixed-order tree in LDS
 // combines them, and the first group finishes the row.
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_finalize16(const RowArgs a)
+__global__ __launch_bounds__(256) void k_finalize16(NTC_ROW_PARAMS)
 {
+    NTC_ROW_RESOLVE(a, blk_);
     __shared__ double s_part[16 * 16 * 17];
-    const SplitRow sr = a.split[blockIdx.x];
+    const SplitRow sr = a.split[blk_];
     const int tid = threadIdx.x;
     const int r = tid & 15;
     const int grp = tid >> 4;
@@ -1049,144 +1038,134 @@ __global__ __launch_bounds__(256) void k_finalize16(const RowArgs a)
     finish_row16<BF16>(a, sr.row, r, g, hd, y);
 }
 
-template <int RP, bool BF16>
-hipError_t launch_items_rp(const RowArgs &a, hipStream_t s)
-{
-    if (a.nmodes == 3)
-        hipLaunchKernelGGL((k_row_items<RP, 3, BF16>), dim3(a.n_items), dim3(64), 0, s, a);
-    else if (a.nmodes == 4)
-        hipLaunchKernelGGL((k_row_items<RP, 4, BF16>), dim3(a.n_items), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_row_items<RP, 0, BF16>), dim3(a.n_items), dim3(64), 0, s, a);
-    return hipGetLastError();
-}
-
-template <bool BF16, int KIND>
-hipError_t launch_items16_part(const RowArgs &a, hipStream_t s)
-{
-    const int count = a.n_group;
-    if (count <= 0)
-        return hipSuccess;
-    const dim3 grid((count + 3) / 4);
-    if (a.nmodes == 3)
-        hipLaunchKernelGGL((k_rows16<3, 4, BF16, KIND>), grid, dim3(64), 0, s, a);
-    else if (a.nmodes == 4)
-        hipLaunchKernelGGL((k_rows16<4, 4, BF16, KIND>), grid, dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_rows16<2, 4, BF16, KIND>), grid, dim3(64), 0, s, a);
-    return hipGetLastError();
-}
+#define NTC_GO(KERNEL, BLOCK) \
+    hipLaunchKernelGGL(KERNEL, dim3(L.blocks), dim3(BLOCK), 0, s, L.args, L.start, L.owner, L.n)
 
 template <bool BF16>
-hipError_t launch_chunks16(const RowArgs &a, hipStream_t s)
+hipError_t go_rows(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
-    const int nchunk = a.n_items - a.n_group;
-    if (nchunk <= 0 || a.nmodes > 4)
-        return hipSuccess;
-    if (a.nmodes == 3)
-        hipLaunchKernelGGL((k_chunk16<3, 4, BF16>), dim3(nchunk), dim3(256), 0, s, a);
-    else if (a.nmodes == 4)
-        hipLaunchKernelGGL((k_chunk16<4, 4, BF16>), dim3(nchunk), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_chunk16<2, 4, BF16>), dim3(nchunk), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-template <bool BF16>
-hipError_t launch_items16(const RowArgs &a, hipStream_t s)
-{
-    if (a.nmodes > 4) {
-        // 5 <= N <= 8: every item (whole rows and chunks) in the group kernel
-        if (a.n_items > 0)
-            hipLaunchKernelGGL((k_rows16_nm<BF16>), dim3((a.n_items + 3) / 4), dim3(64), 0, s, a);
-        return hipGetLastError();
-    }
-    return launch_items16_part<BF16, 1>(a, s);
-}
-
-template <bool BF16>
-hipError_t launch_items_b(const RowArgs &a, int rp, hipStream_t s)
-{
-    switch (rp) {
-    case 8:
-        return launch_items_rp<8, BF16>(a, s);
-    case 16:
-        return launch_items16<BF16>(a, s);
-    case 32:
-        return launch_items_rp<32, BF16>(a, s);
-    case 64:
-        return launch_items_rp<64, BF16>(a, s);
-    default:
-        return hipErrorInvalidValue;
-    }
-}
-
-template <bool BF16>
-hipError_t launch_final_b(const RowArgs &a, int rp, hipStream_t s)
-{
-    switch (rp) {
-    case 8:
-        hipLaunchKernelGGL((k_row_finalize<8, BF16>), dim3(a.n_split), dim3(64), 0, s, a);
-        break;
-    case 16:
-        hipLaunchKernelGGL((k_finalize16<BF16>), dim3(a.n_split), dim3(256), 0, s, a);
-        break;
-    case 32:
-        hipLaunchKernelGGL((k_row_finalize<32, BF16>), dim3(a.n_split), dim3(64), 0, s, a);
-        break;
-    case 64:
-        hipLaunchKernelGGL((k_row_finalize<64, BF16>), dim3(a.n_split), dim3(64), 0, s, a);
-        break;
-    default:
+    if (kc.rp == 16) {
+        if (kc.nmodes == 3)
+            NTC_GO((k_rows16<3, 4, BF16>), 64);
+        else if (kc.nmodes == 4)
+            NTC_GO((k_rows16<4, 4, BF16>), 64);
+        else if (kc.nmodes == 2)
+            NTC_GO((k_rows16<2, 4, BF16>), 64);
+        else
+            NTC_GO((k_rows16_nm<BF16>), 64);
+    } else if (kc.rp == 32) {
+        if (kc.nmodes == 3)
+            NTC_GO((k_row_items<32, 3, BF16>), 64);
+        else if (kc.nmodes == 4)
+            NTC_GO((k_row_items<32, 4, BF16>), 64);
+        else
+            NTC_GO((k_row_items<32, 0, BF16>), 64);
+    } else if (kc.rp == 64) {
+        if (kc.nmodes == 3)
+            NTC_GO((k_row_items<64, 3, BF16>), 64);
+        else if (kc.nmodes == 4)
+            NTC_GO((k_row_items<64, 4, BF16>), 64);
+        else
+            NTC_GO((k_row_items<64, 0, BF16>), 64);
+    } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <bool BF16>
+hipError_t go_finalize(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.rp == 16)
+        NTC_GO((k_finalize16<BF16>), 256);
+    else if (kc.rp == 32)
+        NTC_GO((k_row_finalize<32, BF16>), 64);
+    else if (kc.rp == 64)
+        NTC_GO((k_row_finalize<64, BF16>), 64);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <bool BF16>
+hipError_t go_tiny(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.nmodes == 3)
+        NTC_GO((k_tiny16<3, 4, BF16>), 256);
+    else if (kc.nmodes == 4)
+        NTC_GO((k_tiny16<4, 4, BF16>), 256);
+    else if (kc.nmodes == 2)
+        NTC_GO((k_tiny16<2, 4, BF16>), 256);
+    else
+        NTC_GO((k_tiny16<0, 8, BF16>), 256);
+    return hipGetLastError();
+}
+
+template <bool BF16>
+hipError_t go_chunks(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.nmodes == 3)
+        NTC_GO((k_chunk16<3, 4, BF16>), 256);
+    else if (kc.nmodes == 4)
+        NTC_GO((k_chunk16<4, 4, BF16>), 256);
+    else if (kc.nmodes == 2)
+        NTC_GO((k_chunk16<2, 4, BF16>), 256);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+#undef NTC_GO
+
+__global__ void k_advance(int64_t *k, int32_t n)
+{
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t < n)
+        k[t] += 1;
 }
 
 }  // namespace
 
-hipError_t launch_row_items(const RowArgs &a, int rp, bool bf16, hipStream_t s)
+int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items, int32_t n_group, int32_t n_split,
+                          int32_t n_tiny)
 {
-    if (a.n_items <= 0)
-        return hipSuccess;
-    return bf16 ? launch_items_b<true>(a, rp, s) : launch_items_b<false>(a, rp, s);
+    const bool g16 = kc.rp == 16;
+    switch (kind) {
+    case kRows:
+        return g16 ? (kc.nmodes > 4 ? (n_items + 3) / 4 : (n_group + 3) / 4) : n_items;
+    case kFinalize:
+        return n_split;
+    case kTiny:
+        return g16 ? (n_tiny + 255) / 256 : 0;
+    case kChunks:
+        return (g16 && kc.nmodes <= 4) ? n_items - n_group : 0;
+    }
+    return 0;
 }
 
-hipError_t launch_row_finalize(const RowArgs &a, int rp, bool bf16, hipStream_t s)
+hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s)
 {
-    if (a.n_split <= 0)
+    if (L.blocks <= 0 || L.n <= 0)
         return hipSuccess;
-    return bf16 ? launch_final_b<true>(a, rp, s) : launch_final_b<false>(a, rp, s);
+    const bool b = kc.bf16 != 0;
+    switch (kind) {
+    case kRows:
+        return b ? go_rows<true>(kc, L, s) : go_rows<false>(kc, L, s);
+    case kFinalize:
+        return b ? go_finalize<true>(kc, L, s) : go_finalize<false>(kc, L, s);
+    case kTiny:
+        return b ? go_tiny<true>(kc, L, s) : go_tiny<false>(kc, L, s);
+    case kChunks:
+        return b ? go_chunks<true>(kc, L, s) : go_chunks<false>(kc, L, s);
+    }
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_row_chunks(const RowArgs &a, int rp, bool bf16, hipStream_t s)
+hipError_t launch_advance(int64_t *k, int32_t n, hipStream_t s)
 {
-    if (rp != 16)
+    if (n <= 0)
         return hipSuccess;
-    return bf16 ? launch_chunks16<true>(a, s) : launch_chunks16<false>(a, s);
-}
-
-hipError_t launch_row_tiny(const RowArgs &a, bool bf16, hipStream_t s)
-{
-    if (a.n_tiny <= 0)
-        return hipSuccess;
-    const dim3 grid((a.n_tiny + 255) / 256);
-#define NTC_TINY(NMV, RWV)                                                                                  \
-    do {                                                                                                    \
-        if (bf16)                                                                                           \
-            hipLaunchKernelGGL((k_tiny16<NMV, RWV, true>), grid, dim3(256), 0, s, a);                       \
-        else                                                                                                \
-            hipLaunchKernelGGL((k_tiny16<NMV, RWV, false>), grid, dim3(256), 0, s, a);                      \
-    } while (0)
-    if (a.nmodes == 3)
-        NTC_TINY(3, 4);
-    else if (a.nmodes == 4)
-        NTC_TINY(4, 4);
-    else if (a.nmodes == 2)
-        NTC_TINY(2, 4);
-    else
-        NTC_TINY(0, 8);
-#undef NTC_TINY
+    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, s, k, n);
     return hipGetLastError();
 }
 

@@ -28,9 +28,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 PROFILES = os.path.join(ROOT, "profiles")
-# profile_sweep's launch kinds -> the kernels rocprofv3 reports for them (R = 16, N = 3)
-KERNEL_NAMES = {"row_items": "k_rows16<3, 4, false, 1>", "row_chunks": "k_chunk16<3, 4, false>",
-                "row_tiny": "k_tiny16<3, 4, false>", "row_finalize": "k_finalize16<false>"}
+
+
+def kernel_name(kind: str, nmodes: int, R: int, bf16: bool) -> str:
+    """The kernel rocprofv3 reports for one of profile_sweep's launch kinds (N <= 4)."""
+    b = "true" if bf16 else "false"
+    if R <= 16:
+        return {"row_items": f"k_rows16<{nmodes}, 4, {b}>", "row_chunks": f"k_chunk16<{nmodes}, 4, {b}>",
+                "row_tiny": f"k_tiny16<{nmodes}, 4, {b}>", "row_finalize": f"k_finalize16<{b}>"}[kind]
+    if R <= 32:
+        return {"row_items": f"k_rows32<{nmodes}, {b}>", "row_finalize": f"k_finalize32<{b}>"}[kind]
+    return {"row_items": f"k_row_items<64, {nmodes}, {b}>", "row_finalize": f"k_row_finalize<64, {b}>"}[kind]
 
 
 def log(*a):
@@ -76,6 +84,13 @@ def main():
     ap.add_argument("--bf16", action="store_true", help="BF16 shadow gathers (precision form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve"], default="c1",
+                    help="c1: one 100M-entry problem (default); c2: one 4-way 500M-entry R=32 problem; "
+                         "batch: many small problems in one pool; "
+                         "serve: Poisson arrivals into a pool")
+    ap.add_argument("--instances", type=int, default=256, help="batch/serve: number of problems")
+    ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-at-a-time baseline")
+    ap.add_argument("--rates", default="0.25,0.5,1,2", help="serve: arrival rates as fractions of saturation")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -84,16 +99,32 @@ def main():
               "the multi-GPU row sharding is a design note, not part of this build", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
+
     import numpy as np
 
     import paper_2109_09534_amd as ntc
     import synth
 
     ntc.lib()       # fails loudly without the HIP library
-    R, c, lam, max_inner = 16, 0.1, 1e-3, 1
+    c, lam, max_inner = 0.1, 1e-3, 1
     t0 = time.perf_counter()
-    log(f"generating the 480000x18000x2000 Zipf(1.1) workload, scale {args.scale} ...")
-    p = synth.c1(seed=args.seed, scale=args.scale)
+    if args.workload == "c2":
+        R = 32
+        log(f"generating the 1000000x500000x1000x100 Zipf(1.05) workload, scale {args.scale} ...")
+        p = synth.c2(seed=args.seed, scale=args.scale)
+        wl = ("4-way 1000000x500000x1000x100, 500M Zipf(1.05) entries, rank-32 CPD + N(0,0.05) clipped at 0, "
+              "5% test; R=32, c=0.1, lambda=1e-3, MAX_INNER=1")
+        args.no_cpu_baseline = True     # the FP64 oracle baseline is taken on the default workload
+    else:
+        R = 16
+        log(f"generating the 480000x18000x2000 Zipf(1.1) workload, scale {args.scale} ...")
+        p = synth.c1(seed=args.seed, scale=args.scale)
+        wl = ("3-way 480000x18000x2000, 100M Zipf(1.1) entries, rank-16 ratings 1..5, 5% test; R=16, c=0.1, "
+              "lambda=1e-3, MAX_INNER=1")
     gen_s = time.perf_counter() - t0
     log(f"generated {p.nnz} train / {p.test_values.shape[0]} test entries in {gen_s:.1f} s (SNR {p.snr:.2f})")
 
@@ -136,12 +167,12 @@ def main():
     avg_ms = kd["ms"] / kd["launches"]
     bytes_per_launch = kd["bytes"] / kd["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kfile = KERNEL_NAMES[dom].split("<")[0]
-    traffic_rec = load_traffic(f"{kfile}_c1{'_bf16' if args.bf16 else ''}_traffic.json")
+    kfile = kernel_name(dom, p.nmodes, R, args.bf16).split("<")[0]
+    traffic_rec = load_traffic(f"{kfile}_{args.workload}{'_bf16' if args.bf16 else ''}_traffic.json")
     traffic = traffic_rec["hbm_bytes_per_launch"] if traffic_rec else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dom], "avg_launch_ms": round(avg_ms, 4),
+                "kernel": kernel_name(dom, p.nmodes, R, args.bf16), "avg_launch_ms": round(avg_ms, 4),
                 "launches_per_sweep": kd["launches"],
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
                 "sweep_share": round(kd["ms"] / sum(v["ms"] for v in per_kernel.values()), 3)}
@@ -183,9 +214,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if not args.bf16 else "bf16-gather/f32",
         "data": "synthetic",
-        "config": {"workload": "3-way 480000x18000x2000, 100M Zipf(1.1) entries, rank-16 ratings 1..5, "
-                               "5% test; R=16, c=0.1, lambda=1e-3, MAX_INNER=1" +
-                               (" (BF16 gathers)" if args.bf16 else ""),
+        "config": {"workload": wl + (" (BF16 gathers)" if args.bf16 else ""),
                    "nnz_train": p.nnz, "scale": args.scale, "seed": args.seed,
                    "updates_per_sweep": upd_sweep, "row_steps_per_sweep": rows_sweep},
         "pct_hbm_peak": round(100 * hbm_frac, 2),
@@ -200,6 +229,190 @@ def main():
         "train_rmse": round(float(loss[1]), 6),
         "launches": per_mode,
     }
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------ batching form
+def _updates_per_sweep(p, c=0.1):
+    import numpy as np
+    u = 0
+    for m in range(len(p.dims)):
+        n = np.bincount(p.coords[:, m], minlength=p.dims[m]).astype(np.float64)
+        u += int(np.floor(c * n).sum())
+    return u
+
+
+def _stop_at(hist, W=5, tol=1e-4, cap=500):
+    """Sweep at which the held-out plateau rule stops (hist[k] after k sweeps)."""
+    for k in range(1, len(hist)):
+        if k >= cap or (k >= W and not (hist[k - W] - hist[k] >= tol * hist[k])):
+            return k
+    return None
+
+
+def _batch_problems(n, seed):
+    import synth
+    shapes = synth.c3_shapes(n, base_seed=1000 + 7919 * seed)
+    return shapes, [synth.c3_instance(*sh) for sh in shapes]
+
+
+def run_batch(args):
+    """Many independent 3-way problems (dims log-U[50,2000], nnz log-U[10k,2M],
+    R in {8,16,32}) solved to the held-out plateau in one pool, against the
+    same problems run one at a time through ntc_create/ntc_sweep/ntc_loss."""
+    import numpy as np
+
+    import paper_2109_09534_amd as ntc
+    ntc.lib()
+    n = args.instances
+    t0 = time.perf_counter()
+    shapes, probs = _batch_problems(n, args.seed)
+    gen_s = time.perf_counter() - t0
+    nnz = sum(p.nnz for p in probs)
+    log(f"generated {n} problems, {nnz} train entries in {gen_s:.1f} s")
+    kw = dict(c=0.1, lam=1e-3, gather_bf16=args.bf16)
+
+    pool = ntc.Pool(max_slots=n, window=5, tol=1e-4, max_sweeps=500)
+    t0 = time.perf_counter()
+    slots = []
+    for (dims, _, R, sd), p in zip(shapes, probs):
+        s = pool.admit(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
+                       test_values=p.test_values, **kw)
+        if s is None:
+            raise RuntimeError("the pool could not hold every problem")
+        slots.append(s)
+    admit_s = time.perf_counter() - t0
+    log(f"admitted {n} problems in {admit_s:.2f} s; {pool.info()}")
+    t0 = time.perf_counter()
+    sweeps = 0
+    while pool.info()["running"] > 0:
+        pool.step(1)
+        sweeps += 1
+    run_s = time.perf_counter() - t0
+    per = [pool.query(s) for s in slots]
+    upd = sum(_updates_per_sweep(p) * q[1] for p, q in zip(probs, per))
+    log(f"all stopped after {sweeps} pool sweeps, {run_s:.3f} s; {upd} updates")
+    pool.close()
+
+    plain = None
+    if not args.no_plain:
+        t0 = time.perf_counter()
+        diffs = []
+        for (dims, _, R, sd), p, q in zip(shapes, probs, per):
+            g = ntc.Problem(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
+                            test_values=p.test_values, stream=0, **kw)
+            hist = [g.loss()[2]]
+            while _stop_at(hist) is None:
+                g.sweep(1)
+                hist.append(g.loss()[2])
+            g.close()
+            diffs.append((len(hist) - 1 - q[1], abs(hist[-1] - q[2])))
+        plain_s = time.perf_counter() - t0
+        plain = {"value": round(n / plain_s, 3), "unit": "instances/s", "seconds": round(plain_s, 3),
+                 "kind": "the same problems one at a time through ntc_create/ntc_sweep/ntc_loss, create included",
+                 "max_stop_sweep_diff": int(max(abs(d[0]) for d in diffs)),
+                 "max_final_rmse_diff": float(max(d[1] for d in diffs))}
+        log(f"plain one-at-a-time: {plain_s:.2f} s")
+    out = {
+        "metric": "instances/s", "value": round(n / (admit_s + run_s), 3), "unit": "instances/s",
+        "n_gpus": 1, "steps": sweeps, "warmup": 0, "ms_per_step": round(run_s * 1e3 / max(sweeps, 1), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-gather/f32" if args.bf16 else "f32", "data": "synthetic",
+        "config": {"workload": f"{n} 3-way problems, dims log-U[50,2000], nnz log-U[10k,2M], R in {{8,16,32}}, "
+                               "planted CPD + N(0,0.01), 5% test; c=0.1, lambda=1e-3, plateau stop (W=5, 1e-4, "
+                               "cap 500)", "instances": n, "nnz_train": nnz, "seed": args.seed},
+        "instances_per_s_solve_only": round(n / run_s, 3),
+        "admit_s": round(admit_s, 3), "solve_s": round(run_s, 3), "generate_s": round(gen_s, 2),
+        "updates_per_s_solve": round(upd / run_s, 1),
+        "sweeps_per_instance": {"min": int(min(q[1] for q in per)), "median": float(np.median([q[1] for q in per])),
+                                "max": int(max(q[1] for q in per))},
+        "plain": plain,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Poisson arrivals into a pool (95% batching mixture, 5% 200000x50000x500
+    problems with 20M Zipf(1.1) entries, R = 16), BF16 gathers; latency is
+    arrival -> plateau stop, admission (host CSR build) included."""
+    import collections
+
+    import numpy as np
+
+    import paper_2109_09534_amd as ntc
+    import synth
+    ntc.lib()
+    rng = np.random.default_rng(args.seed)
+    n = args.instances
+    t0 = time.perf_counter()
+    shapes, small = _batch_problems(n, args.seed)
+    large = [synth.make_problem((200_000, 50_000, 500), 20_000_000, 16, zipf_s=1.1, noise_var=0.01,
+                                value_model="exact", test_frac=0.05, seed=90_000 + i, name="large")
+             for i in range(2)]
+    log(f"generated {n} small and {len(large)} large problems in {time.perf_counter() - t0:.1f} s")
+    reqs = []
+    for i in range(n):
+        if rng.random() < 0.05:
+            reqs.append((large[i % len(large)], 16, 50_000 + i))
+        else:
+            dims, _, R, sd = shapes[i]
+            reqs.append((small[i], R, sd))
+    kw = dict(c=0.1, lam=1e-3, gather_bf16=True)
+
+    def serve(rate):
+        """Open loop at `rate` requests/s (rate 0: everything arrives at once)."""
+        gaps = rng.exponential(1.0 / rate, n) if rate > 0 else np.zeros(n)
+        arrive = np.cumsum(gaps) - (gaps[0] if rate > 0 else 0.0)
+        pool = ntc.Pool(max_slots=min(n, 1024), window=5, tol=1e-4, max_sweeps=500)
+        queue = collections.deque()
+        slot_req = {}
+        lat = np.zeros(n)
+        nxt = done = 0
+        start = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - start
+            while nxt < n and arrive[nxt] <= now:
+                queue.append(nxt)
+                nxt += 1
+            while queue:
+                i = queue[0]
+                p, R, sd = reqs[i]
+                s = pool.admit(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
+                               test_values=p.test_values, **kw)
+                if s is None:
+                    break
+                queue.popleft()
+                slot_req[s] = i
+            if pool.info()["running"] > 0:
+                pool.step(1)
+            elif nxt < n:
+                time.sleep(max(0.0, min(arrive[nxt] - (time.perf_counter() - start), 0.05)))
+            for s in pool.stopped():
+                i = slot_req.pop(s)
+                lat[i] = time.perf_counter() - start - arrive[i]
+                pool.evict(s)
+                done += 1
+        wall = time.perf_counter() - start
+        pool.close()
+        return wall, lat
+
+    wall, lat = serve(0.0)
+    sat = n / wall
+    log(f"saturation (all {n} at once): {wall:.2f} s -> {sat:.2f} requests/s")
+    rows = [{"rate_fraction": 0.0, "rate": None, "completions_per_s": round(sat, 3),
+             "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4)}]
+    for f in [float(x) for x in args.rates.split(",") if x]:
+        wall, lat = serve(f * sat)
+        rows.append({"rate_fraction": f, "rate": round(f * sat, 3), "completions_per_s": round(n / wall, 3),
+                     "p50_s": round(float(np.percentile(lat, 50)), 4),
+                     "p99_s": round(float(np.percentile(lat, 99)), 4)})
+        log(f"rate {f} x saturation: p50 {rows[-1]['p50_s']} s, p99 {rows[-1]['p99_s']} s")
+    out = {"metric": "completions/s at saturation", "value": round(sat, 3), "unit": "requests/s", "n_gpus": 1,
+           "steps": n, "warmup": 0, "ms_per_step": round(1e3 / sat, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16-gather/f32", "data": "synthetic",
+           "config": {"workload": f"{n} requests: 95% batching mixture, 5% 200000x50000x500 20M Zipf(1.1) R=16; "
+                                  "BF16 gathers, plateau stop; Poisson arrivals", "requests": n, "seed": args.seed},
+           "latency": rows}
     print(json.dumps(out), flush=True)
 
 

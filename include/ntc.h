@@ -191,8 +191,84 @@ typedef struct ntc_launch_record {
  * order and the number of launches to *count.  Synchronising. */
 ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, int32_t *count);
 
+/* Upper bound of the device bytes ntc_create would allocate for this
+ * problem (factors, BF16 shadows, CSR records and row pointers, the row
+ * schedule, partial slots, held-out set, argument tables), computed on the
+ * host from the sizes alone.  Used for admission by free memory. */
+ntc_status ntc_estimate_bytes(int32_t nmodes, const int64_t *dims, int64_t nnz, int32_t rank,
+                              const ntc_params *p, size_t *bytes);
+
 /* Release all device and host memory of h (NULL is accepted). */
 ntc_status ntc_release(ntc_handle h);
+
+/* ------------------------------------------------------------------------
+ * Batching and serving: many independent problems on one GPU.
+ *
+ * A pool owns one device memory arena and up to max_slots problems.  Each
+ * admitted problem is a full ntc_create problem (own data, factors, seed
+ * and sweep counter) whose device memory comes from the arena.  A pool
+ * sweep runs Alg. 2 once for every running problem: per (mode, inner step)
+ * one launch of each row kernel covers all running problems of the same
+ * kernel family (padded rank, mode count, BF16 gathers), so a problem's
+ * rows take exactly the code path and arithmetic they take alone; a
+ * problem's factors after s pool sweeps are bit-identical to s ntc_sweep
+ * calls on it alone.  The launches of one sweep are captured once as a HIP
+ * graph and replayed until the set of running problems changes.
+ *
+ * Stop rule (checked after every sweep, per problem with a held-out set):
+ * stop after sweep s >= window when RMSE_test(s - window) - RMSE_test(s)
+ * < tol * RMSE_test(s), or at max_sweeps.  A stopped problem keeps its
+ * slot and memory (for queries) until ntc_pool_evict.
+ * ---------------------------------------------------------------------- */
+typedef struct ntc_pool *ntc_pool_handle;
+
+typedef struct ntc_pool_params {
+    size_t arena_bytes;       /* device memory for all problems (0 = 3/4 of free memory) */
+    int32_t max_slots;        /* concurrent problems, 1..65536 (default 1024) */
+    int32_t use_graph;        /* 1 = replay sweeps as a captured HIP graph (default), 0 = eager */
+    int32_t window;           /* stop rule window (default 5) */
+    int32_t max_sweeps;       /* stop after this many sweeps (default 500) */
+    double tol;               /* stop rule relative tolerance (default 1e-4) */
+    void *stream;             /* hipStream_t; NULL = the null stream */
+} ntc_pool_params;
+
+typedef enum { NTC_SLOT_FREE = 0, NTC_SLOT_RUNNING = 1, NTC_SLOT_STOPPED = 2 } ntc_slot_state;
+
+void ntc_pool_params_default(ntc_pool_params *p);
+ntc_status ntc_pool_create(ntc_pool_handle *out, const ntc_pool_params *p);
+
+/* Admit a problem (arguments as ntc_create; p->stream, the allocator and
+ * the overlap setting are replaced by the pool's).  Returns NTC_ENOMEM, with
+ * nothing changed, when no slot is free or the arena cannot hold it now;
+ * *slot receives the slot index on success. */
+ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                          const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
+                          int32_t *slot);
+
+/* Run `nsweeps` pool sweeps over the running problems, applying the stop
+ * rule after each.  Synchronising. */
+ntc_status ntc_pool_step(ntc_pool_handle pool, int32_t nsweeps);
+
+/* State of a slot: *state (ntc_slot_state), sweeps run, and the last
+ * held-out RMSE of the stop rule (NaN before the first check). */
+ntc_status ntc_pool_query(ntc_pool_handle pool, int32_t slot, int32_t *state, int64_t *sweeps, double *test_rmse);
+
+/* Full loss (as ntc_loss) and factors of a running or stopped slot. */
+ntc_status ntc_pool_loss(ntc_pool_handle pool, int32_t slot, double out[4]);
+ntc_status ntc_pool_get_factors(ntc_pool_handle pool, int32_t slot, int32_t mode, float *host_out);
+
+/* Slots that have stopped and are not yet evicted: up to cap indices into
+ * slots, the total through *count. */
+ntc_status ntc_pool_stopped(ntc_pool_handle pool, int32_t *slots, int32_t cap, int32_t *count);
+
+/* Free a slot and return its memory to the arena. */
+ntc_status ntc_pool_evict(ntc_pool_handle pool, int32_t slot);
+
+/* Arena bytes in use and free, running and stopped slot counts, sweeps run. */
+ntc_status ntc_pool_info(ntc_pool_handle pool, size_t *used, size_t *free_bytes, int32_t *running,
+                         int32_t *stopped, int64_t *pool_sweeps);
+
+ntc_status ntc_pool_release(ntc_pool_handle pool);
 
 /* Thread-local message of the last failing call on this thread. */
 const char *ntc_last_error(void);

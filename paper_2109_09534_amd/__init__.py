@@ -72,6 +72,12 @@ class _Params(ctypes.Structure):
     ]
 
 
+class _PoolParams(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
 class LaunchRecord(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("mode", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("samples", ctypes.c_int64), ("rows", ctypes.c_int64),
@@ -104,6 +110,21 @@ _SIGNATURES = [
     ("ntc_profile_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(LaunchRecord), ctypes.c_int32,
                                          _i32p]),
     ("ntc_release", ctypes.c_int, [ctypes.c_void_p]),
+    ("ntc_estimate_bytes", ctypes.c_int, [ctypes.c_int32, _i64p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)]),
+    ("ntc_pool_params_default", None, [ctypes.POINTER(_PoolParams)]),
+    ("ntc_pool_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_PoolParams)]),
+    ("ntc_pool_admit", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, ctypes.c_int64, _i32p, _f32p,
+                                      ctypes.c_int32, ctypes.POINTER(_Params), _i32p]),
+    ("ntc_pool_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("ntc_pool_query", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i32p, _i64p, _f64p]),
+    ("ntc_pool_loss", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p]),
+    ("ntc_pool_get_factors", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _f32p]),
+    ("ntc_pool_stopped", ctypes.c_int, [ctypes.c_void_p, _i32p, ctypes.c_int32, _i32p]),
+    ("ntc_pool_evict", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("ntc_pool_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t), _i32p, _i32p, _i64p]),
+    ("ntc_pool_release", ctypes.c_int, [ctypes.c_void_p]),
     ("ntc_last_error", ctypes.c_char_p, []),
     ("ntc_version", ctypes.c_char_p, []),
 ]
@@ -176,6 +197,46 @@ def host_csr(dims: Sequence[int], coords: np.ndarray, mode: int):
     return rp, perm[:nnz]
 
 
+def _make_params(N, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords, test_values, init, schedule):
+    """ntc_params for ntc_create / ntc_pool_admit, plus the arrays it points into."""
+    prm = _Params()
+    lib().ntc_params_default(ctypes.byref(prm))
+    prm.c, prm.lam, prm.max_inner, prm.power_iters, prm.seed = c, lam, max_inner, power_iters, seed
+    prm.gather_bf16 = 1 if gather_bf16 else 0
+    for key, val in (schedule or {}).items():
+        if key not in ("tiny_max", "item_samples", "overlap", "group_max"):
+            raise ValueError(f"unknown schedule field {key}")
+        setattr(prm, key, int(val))
+    keep = []
+    if test_coords is not None:
+        tc = np.ascontiguousarray(test_coords, dtype=np.int32)
+        tv = np.ascontiguousarray(test_values, dtype=np.float32)
+        keep += [tc, tv]
+        prm.n_test = tv.shape[0]
+        prm.test_coords = _p(tc, _i32p)
+        prm.test_values = _p(tv, _f32p)
+    if init is not None:
+        arrs = [np.ascontiguousarray(u, dtype=np.float32).reshape(-1) for u in init]
+        keep += arrs
+        ptrs = (_f32p * N)(*[_p(a, _f32p) for a in arrs])
+        keep.append(ptrs)
+        prm.init_factors = ptrs
+    return prm, keep
+
+
+def estimate_bytes(dims: Sequence[int], nnz: int, rank: int, **kw) -> int:
+    """Upper bound of the device bytes ntc_create allocates (ntc_estimate_bytes)."""
+    d = np.asarray([int(x) for x in dims], dtype=np.int64)
+    prm, _ = _make_params(len(d), kw.get("c", 0.1), kw.get("lam", 1e-3), kw.get("max_inner", 1),
+                          kw.get("power_iters", 20), kw.get("seed", 0), kw.get("gather_bf16", False), None, None,
+                          None, kw.get("schedule"))
+    prm.n_test = int(kw.get("n_test", 0))
+    out = ctypes.c_size_t()
+    _check(lib().ntc_estimate_bytes(len(d), _p(d, _i64p), int(nnz), int(rank), ctypes.byref(prm),
+                                    ctypes.byref(out)))
+    return out.value
+
+
 class _TorchAllocator:
     """Routes the library's device allocations through torch's caching allocator."""
 
@@ -219,28 +280,9 @@ class Problem:
         va = np.ascontiguousarray(values, dtype=np.float32)
         if co.ndim != 2 or co.shape[1] != self.N or co.shape[0] != va.shape[0]:
             raise ValueError("coords must be [nnz, nmodes] and values [nnz]")
-        prm = _Params()
-        L.ntc_params_default(ctypes.byref(prm))
-        prm.c, prm.lam, prm.max_inner, prm.power_iters, prm.seed = c, lam, max_inner, power_iters, seed
-        prm.gather_bf16 = 1 if gather_bf16 else 0
-        for key, val in (schedule or {}).items():
-            if key not in ("tiny_max", "item_samples", "overlap", "group_max"):
-                raise ValueError(f"unknown schedule field {key}")
-            setattr(prm, key, int(val))
-        keep = [d, co, va]
-        if test_coords is not None:
-            tc = np.ascontiguousarray(test_coords, dtype=np.int32)
-            tv = np.ascontiguousarray(test_values, dtype=np.float32)
-            keep += [tc, tv]
-            prm.n_test = tv.shape[0]
-            prm.test_coords = _p(tc, _i32p)
-            prm.test_values = _p(tv, _f32p)
-        if init is not None:
-            arrs = [np.ascontiguousarray(u, dtype=np.float32).reshape(-1) for u in init]
-            keep += arrs
-            ptrs = (_f32p * self.N)(*[_p(a, _f32p) for a in arrs])
-            keep.append(ptrs)
-            prm.init_factors = ptrs
+        prm, keep = _make_params(self.N, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords,
+                                 test_values, init, schedule)
+        keep += [d, co, va]
         if torch_allocator or (stream is not None and not isinstance(stream, int)):
             _require_single_runtime()
         prm.stream = self._stream_handle(stream)
@@ -357,3 +399,101 @@ class Problem:
         cnt = ctypes.c_int32(0)
         _check(lib().ntc_debug_sample(self._h, k, mode, l, row, _p(out, _i32p), ctypes.byref(cnt)))
         return out[: cnt.value].copy()
+
+
+SLOT_FREE, SLOT_RUNNING, SLOT_STOPPED = 0, 1, 2
+
+
+class Pool:
+    """Many independent problems on one GPU (ntc_pool_*): one device memory
+    arena, batched launches over all running problems, a HIP graph per sweep,
+    and a held-out plateau stop rule."""
+
+    def __init__(self, arena_bytes: int = 0, max_slots: int = 1024, use_graph: bool = True, window: int = 5,
+                 max_sweeps: int = 500, tol: float = 1e-4):
+        L = lib()
+        prm = _PoolParams()
+        L.ntc_pool_params_default(ctypes.byref(prm))
+        prm.arena_bytes, prm.max_slots, prm.use_graph = int(arena_bytes), int(max_slots), 1 if use_graph else 0
+        prm.window, prm.max_sweeps, prm.tol = int(window), int(max_sweeps), float(tol)
+        h = ctypes.c_void_p()
+        _check(L.ntc_pool_create(ctypes.byref(h), ctypes.byref(prm)))
+        self._h = h
+        self._dims = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ntc_pool_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def admit(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *, c: float = 0.1,
+              lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
+              gather_bf16: bool = False, test_coords=None, test_values=None, init=None,
+              schedule: Optional[dict] = None) -> Optional[int]:
+        """Slot index, or None when the pool cannot hold the problem now."""
+        d = np.asarray([int(x) for x in dims], dtype=np.int64)
+        co = np.ascontiguousarray(coords, dtype=np.int32)
+        va = np.ascontiguousarray(values, dtype=np.float32)
+        if co.ndim != 2 or co.shape[1] != d.size or co.shape[0] != va.shape[0]:
+            raise ValueError("coords must be [nnz, nmodes] and values [nnz]")
+        prm, keep = _make_params(d.size, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords,
+                                 test_values, init, schedule)
+        slot = ctypes.c_int32(-1)
+        st = lib().ntc_pool_admit(self._h, d.size, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
+                                  int(rank), ctypes.byref(prm), ctypes.byref(slot))
+        if st == -2:      # NTC_ENOMEM: not admitted now
+            return None
+        _check(st)
+        self._dims[slot.value] = (list(int(x) for x in d), int(rank))
+        return slot.value
+
+    def step(self, n: int = 1):
+        _check(lib().ntc_pool_step(self._h, int(n)))
+
+    def query(self, slot: int):
+        """(state, sweeps, last held-out RMSE)."""
+        st, sw, rm = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().ntc_pool_query(self._h, int(slot), ctypes.byref(st), ctypes.byref(sw), ctypes.byref(rm)))
+        return st.value, sw.value, rm.value
+
+    def loss(self, slot: int) -> np.ndarray:
+        out = np.zeros(4, dtype=np.float64)
+        _check(lib().ntc_pool_loss(self._h, int(slot), _p(out, _f64p)))
+        return out
+
+    def factors(self, slot: int, mode: int) -> np.ndarray:
+        dims, R = self._dims[slot]
+        out = np.empty((dims[mode], R), dtype=np.float32)
+        _check(lib().ntc_pool_get_factors(self._h, int(slot), int(mode), _p(out, _f32p)))
+        return out
+
+    def stopped(self) -> List[int]:
+        n = ctypes.c_int32()
+        _check(lib().ntc_pool_stopped(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        _check(lib().ntc_pool_stopped(self._h, _p(out, _i32p), out.size, ctypes.byref(n)))
+        return [int(x) for x in out[:n.value]]
+
+    def evict(self, slot: int):
+        _check(lib().ntc_pool_evict(self._h, int(slot)))
+        self._dims.pop(slot, None)
+
+    def info(self) -> dict:
+        used, free = ctypes.c_size_t(), ctypes.c_size_t()
+        run, stp, sw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().ntc_pool_info(self._h, ctypes.byref(used), ctypes.byref(free), ctypes.byref(run),
+                                   ctypes.byref(stp), ctypes.byref(sw)))
+        return {"used": used.value, "free": free.value, "running": run.value, "stopped": stp.value,
+                "sweeps": sw.value}

@@ -36,4 +36,14 @@ hipError_t launch_to_bf16(const float *U, uint16_t *U16, int64_t count, hipStrea
 hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed, int64_t k, int32_t mode,
                                int32_t l, double c, int32_t *pos_out, int32_t *count_out, hipStream_t s);
 
+// Batched held-out sums (the pool's stop rule): entry j owns blocks
+// [start[j], start[j+1]) (start has n+1 entries, owner one per block; owner
+// may be null when n == 1); out[2j] = sum of squared test residuals,
+// out[2j+1] = sum of squared test values.  part holds 2 doubles per block.
+int32_t test_blocks(int64_t n_test);
+hipError_t launch_test_sums(const LossArgs *args, const int32_t *start, const int32_t *owner, int32_t n,
+                            int32_t blocks, double *part, double *out, hipStream_t s);
+// *k[t] += 1 for t < n
+hipError_t launch_advance_many(int64_t *const *k, int32_t n, hipStream_t s);
+
 }  // namespace ntc

@@ -28,12 +28,18 @@ __device__ __forceinline__ double block_sum(double v, double *s)
 }
 
 // Prediction sum_r prod_m U_m[i_m, r] in FP64 from row offsets off[m] = i_m * R.
-template <bool VEC4>
-__device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t *off, int nm, int R)
+// Prediction sum_r prod_m U_m[i_m, r] in FP64 from row offsets off[m] = i_m * R.
+// LPE lanes share one entry: lane `sub` takes columns 4 sub .. 4 sub + 3
+// (R % 4 == 0, one float4 per mode, so a row is read by adjacent lanes),
+// then the lanes' partial sums are combined by a butterfly; LPE == 1 is the
+// scalar form for any R.  Every lane of the entry returns the same value.
+template <int LPE>
+__device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t *off, int nm, int R, int sub)
 {
     double pred = 0.0;
-    if (VEC4) {
-        for (int r = 0; r < R; r += 4) {
+    if (LPE > 1) {
+        const int r = 4 * sub;
+        if (r < R) {
             double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
             for (int m = 0; m < nm; ++m) {
                 const float4 u = *reinterpret_cast<const float4 *>(a.U[m] + off[m] + r);
@@ -42,11 +48,11 @@ __device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t 
                 p2 *= static_cast<double>(u.z);
                 p3 *= static_cast<double>(u.w);
             }
-            pred += p0;
-            pred += p1;
-            pred += p2;
-            pred += p3;
+            pred = (p0 + p1) + (p2 + p3);
         }
+#pragma unroll
+        for (int w = 1; w < LPE; w <<= 1)
+            pred += __shfl_xor(pred, w, 64);
     } else {
         for (int r = 0; r < R; ++r) {
             double prod = 1.0;
@@ -60,43 +66,59 @@ __device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t 
 
 // Training entries are walked in mode-0 CSR order; each record carries the
 // other coordinates (times R) and the row (times R, in a spare record word or
-// a side array), so an entry needs no search.  Fixed grid and per-thread
+// a side array), so an entry needs no search.  Fixed grid and per-lane
 // order: the sums are deterministic.
-template <bool VEC4>
+template <int LPE>
 __global__ __launch_bounds__(kLossThreads) void k_loss_partials(const LossArgs a)
 {
     __shared__ double s[kLossThreads];
     const int R = a.R;
     const int nm = a.nmodes;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int sub = threadIdx.x % LPE;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * (blockDim.x / LPE);
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * (blockDim.x / LPE) + threadIdx.x / LPE;
+    // every lane of a wave runs the same number of iterations (the butterfly
+    // needs all LPE lanes of an entry); entries past the end contribute 0
+    const int64_t iters_tr = (a.nnz + stride - 1) / stride;
     double sse = 0.0;
-    for (int64_t e = tid; e < a.nnz; e += stride) {
-        const uint32_t *rec = a.records0 + e * a.rec_words;
+    for (int64_t it = 0; it < iters_tr; ++it) {
+        const int64_t e = first + it * stride;
+        const bool live = e < a.nnz;
+        const int64_t ee = live ? e : 0;
+        const uint32_t *rec = a.records0 + ee * a.rec_words;
         uint32_t off[kMaxModes];
-        off[0] = a.row0 ? a.row0[e] : rec[a.row_word];
+        off[0] = a.row0 ? a.row0[ee] : rec[a.row_word];
         for (int m = 1; m < nm; ++m)
             off[m] = rec[m - 1];
-        const double pred = cpd_predict<VEC4>(a, off, nm, R);
+        const double pred = cpd_predict<LPE>(a, off, nm, R, sub);
         const double res = static_cast<double>(__uint_as_float(rec[nm - 1])) - pred;
-        sse += res * res;
+        if (live && sub == 0)
+            sse += res * res;
     }
     double tse = 0.0, tsx = 0.0;
-    for (int64_t e = tid; e < a.n_test; e += stride) {
-        const int32_t *cc = a.test_coords + e * nm;
+    const int64_t iters_te = (a.n_test + stride - 1) / stride;
+    for (int64_t it = 0; it < iters_te; ++it) {
+        const int64_t e = first + it * stride;
+        const bool live = e < a.n_test;
+        const int64_t ee = live ? e : 0;
+        const int32_t *cc = a.test_coords + ee * nm;
         uint32_t off[kMaxModes];
         for (int m = 0; m < nm; ++m)
             off[m] = static_cast<uint32_t>(cc[m]) * static_cast<uint32_t>(R);
-        const double pred = cpd_predict<VEC4>(a, off, nm, R);
-        const double x = static_cast<double>(a.test_values[e]);
+        const double pred = cpd_predict<LPE>(a, off, nm, R, sub);
+        const double x = static_cast<double>(a.test_values[ee]);
         const double res = x - pred;
-        tse += res * res;
-        tsx += x * x;
+        if (live && sub == 0) {
+            tse += res * res;
+            tsx += x * x;
+        }
     }
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t tstride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     double reg = 0.0;
     for (int m = 0; m < nm; ++m) {
         const int64_t cntm = a.dims[m] * R;
-        for (int64_t t = tid; t < cntm; t += stride) {
+        for (int64_t t = tid; t < cntm; t += tstride) {
             const double u = static_cast<double>(a.U[m][t]);
             reg += u * u;
         }
@@ -165,14 +187,89 @@ __global__ void k_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed
         pos[j] = static_cast<int32_t>(prp_index(prp, static_cast<uint32_t>(j)));
 }
 
+// ---------------------------------------------------------- batched forms
+typedef const __attribute__((address_space(4))) LossArgs CLossArgs;
+
+// Held-out sums of many problems in one launch: block b belongs to entry
+// owner[b] and is that entry's local block b - start[entry] of
+// start[entry+1] - start[entry]; part[2b] = sum of squared test residuals,
+// part[2b+1] = sum of squared test values over its strided share.
+__global__ __launch_bounds__(kLossThreads) void k_test_partials_b(const LossArgs *__restrict__ args,
+                                                                  const int32_t *__restrict__ start,
+                                                                  const int32_t *__restrict__ owner, int32_t n,
+                                                                  double *__restrict__ part)
+{
+    __shared__ double s[kLossThreads];
+    const int j = n > 1 ? owner[blockIdx.x] : 0;
+    const int b = static_cast<int>(blockIdx.x) - start[j];
+    const int nb = start[j + 1] - start[j];
+    CLossArgs &a = ((CLossArgs *)args)[j];
+    const int R = a.R;
+    const int nm = a.nmodes;
+    double tse = 0.0, tsx = 0.0;
+    for (int64_t e = static_cast<int64_t>(b) * blockDim.x + threadIdx.x; e < a.n_test;
+         e += static_cast<int64_t>(nb) * blockDim.x) {
+        const int32_t *cc = a.test_coords + e * nm;
+        double pred = 0.0;
+        for (int r = 0; r < R; ++r) {
+            double prod = 1.0;
+            for (int m = 0; m < nm; ++m)
+                prod *= static_cast<double>(a.U[m][static_cast<int64_t>(cc[m]) * R + r]);
+            pred += prod;
+        }
+        const double x = static_cast<double>(a.test_values[e]);
+        const double res = x - pred;
+        tse += res * res;
+        tsx += x * x;
+    }
+    tse = block_sum(tse, s);
+    tsx = block_sum(tsx, s);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = tse;
+        part[2 * blockIdx.x + 1] = tsx;
+    }
+}
+
+// One block per entry: sum the entry's block partials in block order.
+__global__ __launch_bounds__(kLossThreads) void k_test_final_b(const int32_t *__restrict__ start,
+                                                               const double *__restrict__ part,
+                                                               double *__restrict__ out)
+{
+    __shared__ double s[kLossThreads];
+    const int j = blockIdx.x;
+    for (int q = 0; q < 2; ++q) {
+        double v = 0.0;
+        for (int b = start[j] + threadIdx.x; b < start[j + 1]; b += blockDim.x)
+            v += part[2 * b + q];
+        v = block_sum(v, s);
+        if (threadIdx.x == 0)
+            out[2 * j + q] = v;
+    }
+}
+
+__global__ void k_advance_many(int64_t *const *__restrict__ k, int32_t n)
+{
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t < n)
+        *k[t] += 1;
+}
+
 }  // namespace
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s)
 {
-    if (a.R % 4 == 0)
-        hipLaunchKernelGGL(k_loss_partials<true>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+    // lanes per entry: one float4 of every factor row per lane
+    const int lpe = (a.R % 4 != 0) ? 1 : a.R <= 8 ? 2 : a.R <= 16 ? 4 : a.R <= 32 ? 8 : 16;
+    if (lpe == 16)
+        hipLaunchKernelGGL(k_loss_partials<16>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+    else if (lpe == 8)
+        hipLaunchKernelGGL(k_loss_partials<8>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+    else if (lpe == 4)
+        hipLaunchKernelGGL(k_loss_partials<4>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+    else if (lpe == 2)
+        hipLaunchKernelGGL(k_loss_partials<2>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_loss_partials<false>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+        hipLaunchKernelGGL(k_loss_partials<1>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -202,6 +299,31 @@ hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed
 {
     hipLaunchKernelGGL(k_debug_sample, dim3(64), dim3(256), 0, s, rowptr, row, seed, k, mode, l, c, pos_out,
                        count_out);
+    return hipGetLastError();
+}
+
+int32_t test_blocks(int64_t n_test)
+{
+    const int64_t per = 16 * kLossThreads;
+    const int64_t nb = (n_test + per - 1) / per;
+    return static_cast<int32_t>(nb < 1 ? 1 : nb > 64 ? 64 : nb);
+}
+
+hipError_t launch_test_sums(const LossArgs *args, const int32_t *start, const int32_t *owner, int32_t n,
+                            int32_t blocks, double *part, double *out, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_test_partials_b, dim3(blocks), dim3(kLossThreads), 0, s, args, start, owner, n, part);
+    hipLaunchKernelGGL(k_test_final_b, dim3(n), dim3(kLossThreads), 0, s, start, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_many(int64_t *const *k, int32_t n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_advance_many, dim3((n + 255) / 256), dim3(256), 0, s, k, n);
     return hipGetLastError();
 }
 

@@ -1014,6 +1014,50 @@ ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, 
     return NTC_OK;
 }
 
+ntc_status ntc_estimate_bytes(int32_t nmodes, const int64_t *dims, int64_t nnz, int32_t rank, const ntc_params *p,
+                              size_t *bytes)
+{
+    if (!dims || !bytes)
+        return fail(NTC_EINVAL, "null argument");
+    if (nmodes < 2 || nmodes > ntc::kMaxModes || rank < 1 || rank > ntc::kMaxRank || nnz < 0)
+        return fail(NTC_EINVAL, "nmodes, rank or nnz out of range");
+    ntc_params def;
+    ntc_params_default(&def);
+    const ntc_params &q = p ? *p : def;
+    const int64_t N = nmodes, R = rank, rp = padded_rank(rank), rw = record_words(nmodes);
+    const int64_t smax = q.item_samples > 0 ? q.item_samples : item_samples(static_cast<int>(rp));
+    const double c = (q.c > 0.0 && q.c <= 1.0) ? q.c : 1.0;
+    const int64_t inner = std::max<int32_t>(q.max_inner, 1);
+    auto up = [](int64_t b) { return static_cast<size_t>((std::max<int64_t>(b, 1) + 255) / 256 * 256); };
+    size_t t = 0;
+    int64_t maxI = 0;
+    for (int m = 0; m < nmodes; ++m) {
+        if (dims[m] < 1)
+            return fail(NTC_EINVAL, "dims must be >= 1");
+        maxI = std::max(maxI, dims[m]);
+        t += up((dims[m] + 1) * R * 4);
+        if (q.gather_bf16)
+            t += up((dims[m] + 1) * R * 2);
+        t += up((dims[m] + 1) * 8);                                   // rowptr
+        t += up(nnz * rw * 4);                                        // records
+        t += up(dims[m] * 4);                                         // one-row-per-lane rows
+        t += up((dims[m] + nnz / smax + 1) * 16);                     // work items
+        t += up(dims[m] * 16);                                        // split rows
+    }
+    if (inner > 1)
+        t += up((maxI + 1) * R * 4);
+    if (N >= rw)
+        t += up(nnz * 4);                                             // loss rows
+    const int64_t slots = 2 * static_cast<int64_t>(std::ceil(c * static_cast<double>(nnz) / smax)) + 1;
+    t += up(slots * (rp + rp * rp) * 8);
+    const int64_t nt = std::max<int64_t>(q.n_test, 1);
+    t += up(nt * N * 4) + up(nt * 4);
+    t += up(4 * ntc::kLossBlocks * 8) + up(32) + up((nnz + 1) * 4) + up(8);
+    t += up(N * inner * static_cast<int64_t>(sizeof(ntc::RowArgs)));
+    *bytes = t;
+    return NTC_OK;
+}
+
 ntc_status ntc_release(ntc_handle h)
 {
     delete h;

@@ -831,6 +831,45 @@ __global__ __launch_bounds__(64) void k_rows16_nm(NTC_ROW_PARAMS)
 // ||x||^2 = a^2 + 2 a u.c + u^T G u (||v0|| = 1).  This is the same iterate
 // as T normalised products with H, evaluated in the b-dimensional span of
 // the samples: O(T b^2) instead of O(T b R) operations per row.
+// One factor row of up to 16 columns into registers (zeros past R).  When
+// R % 4 == 0 every row starts on a 16-byte (FP32) or 8-byte (BF16) boundary
+// and is read with vector loads.
+__device__ __forceinline__ void load_row16(const float *p, int R, bool v4, float (&out)[16])
+{
+    if (v4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 t = 4 * q < R ? reinterpret_cast<const float4 *>(p)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            out[4 * q] = t.x;
+            out[4 * q + 1] = t.y;
+            out[4 * q + 2] = t.z;
+            out[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            out[r] = r < R ? p[r] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void load_row16(const uint16_t *p, int R, bool v4, float (&out)[16])
+{
+    if (v4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint2 t = 4 * q < R ? reinterpret_cast<const uint2 *>(p)[q] : make_uint2(0u, 0u);
+            out[4 * q] = __uint_as_float(t.x << 16);
+            out[4 * q + 1] = __uint_as_float(t.x & 0xFFFF0000u);
+            out[4 * q + 2] = __uint_as_float(t.y << 16);
+            out[4 * q + 3] = __uint_as_float(t.y & 0xFFFF0000u);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            out[r] = r < R ? bf16_to_f32(p[r]) : 0.0f;
+    }
+}
+
 template <int NM, int RW, bool BF16>
 __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
 {
@@ -840,6 +879,7 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
         return;
     const int nm = (NM > 0) ? NM : a.nmodes;
     const int R = a.R;
+    const bool v4 = (R & 3) == 0;  // uniform over the block (one problem per block)
     const int row = a.tiny[id];
     const int64_t base = a.rowptr[row];
     const int64_t n = a.rowptr[row + 1] - base;
@@ -848,19 +888,28 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const int64_t roff = static_cast<int64_t>(row) * R;
     float y[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-        y[r] = r < R ? ysrc[roff + r] : 0.0f;
+    load_row16(ysrc + roff, R, v4, y);
 
     // sampled records first (all in flight), then the factor rows
     uint32_t rec[kTinyB][RW];
 #pragma unroll
     for (int j = 0; j < kTinyB; ++j) {
-        const uint32_t q = j < b ? prp_index(prp, static_cast<uint32_t>(j)) : 0u;
-        const uint32_t *src = a.records + (base + q) * RW;
+        if (j < b) {
+            const uint32_t q = prp_index(prp, static_cast<uint32_t>(j));
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.records + (base + q) * RW);
 #pragma unroll
-        for (int w = 0; w < RW; ++w)
-            rec[j][w] = src[w];
+            for (int w4 = 0; w4 < RW / 4; ++w4) {
+                const uint4 t = src[w4];
+                rec[j][4 * w4] = t.x;
+                rec[j][4 * w4 + 1] = t.y;
+                rec[j][4 * w4 + 2] = t.z;
+                rec[j][4 * w4 + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < RW; ++w)
+                rec[j][w] = a.zrec[w];  // the zero rows, value 0
+        }
     }
     float kk[kTinyB][16];
     float gf[16];
@@ -871,25 +920,30 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
     for (int j = 0; j < kTinyB; ++j) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            kk[j][r] = (r < R && j < b) ? 1.0f : 0.0f;
+            kk[j][r] = 1.0f;
         for (int mm = 0; mm < nm - 1; ++mm) {
-            const int64_t o = static_cast<int64_t>(rec[j][mm]);  // coordinate * R
+            float f[16];
+            if (BF16)
+                load_row16(a.gath16[mm] + rec[j][mm], R, v4, f);  // coordinate * R
+            else
+                load_row16(a.gath[mm] + rec[j][mm], R, v4, f);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                if (r < R)
-                    kk[j][r] *= BF16 ? bf16_to_f32(a.gath16[mm][o + r]) : a.gath[mm][o + r];
+                kk[j][r] *= f[r];
         }
-        if (j < b) {
-            const float x = __uint_as_float(rec[j][nm - 1]);
-            float pred = 0.0f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                pred = fmaf(kk[j][r], y[r], pred);
-            const float res = pred - x;
+        for (int r = 0; r < 16; ++r)
+            kk[j][r] = r < R ? kk[j][r] : 0.0f;
+        // a missing sample has k = 0 (zero rows) and x = 0: it adds nothing
+        const float x = __uint_as_float(rec[j][nm - 1]);
+        float pred = 0.0f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                gf[r] = fmaf(res, kk[j][r], gf[r]);
-        }
+        for (int r = 0; r < 16; ++r)
+            pred = fmaf(kk[j][r], y[r], pred);
+        const float res = pred - x;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            gf[r] = fmaf(res, kk[j][r], gf[r]);
     }
 
     // c = K v0 and G = K K^T in FP64 (products of FP32 values are exact)
@@ -960,19 +1014,47 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
     if (L > 0.0) {
         const double sl = sqrt(L), sm = sqrt(lam);
         const double beta = (sl - sm) / (sl + sm);
+        // A_{l+1} = (y - g/L)_+ and Y_{l+1} = A_{l+1} + beta (A_{l+1} - A_l), four columns at a time
+        auto step4 = [&](int r0, float (&an4)[4], float (&yn4)[4]) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if (r < R) {
+            for (int u = 0; u < 4; ++u) {
+                const int r = r0 + u;
                 const double g = static_cast<double>(gf[r]) + lam * static_cast<double>(y[r]);
                 double an = static_cast<double>(y[r]) - g / L;
                 an = an > 0.0 ? an : 0.0;
-                const float a_prev = (a.l == 0) ? y[r] : a.A[roff + r];
-                const float af = static_cast<float>(an);
-                a.A[roff + r] = af;
+                const float ap = (a.l == 0) ? y[r] : (r < R ? a.A[roff + r] : 0.0f);
+                an4[u] = static_cast<float>(an);
+                yn4[u] = static_cast<float>(an + beta * (an - static_cast<double>(ap)));
+            }
+        };
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (4 * q >= R)
+                continue;
+            float an4[4], yn4[4];
+            step4(4 * q, an4, yn4);
+            if (v4) {
+                reinterpret_cast<float4 *>(a.A + roff)[q] = make_float4(an4[0], an4[1], an4[2], an4[3]);
                 if (BF16)
-                    a.A16[roff + r] = f32_to_bf16(af);
+                    reinterpret_cast<uint2 *>(a.A16 + roff)[q] =
+                        make_uint2(static_cast<uint32_t>(f32_to_bf16(an4[0])) |
+                                       (static_cast<uint32_t>(f32_to_bf16(an4[1])) << 16),
+                                   static_cast<uint32_t>(f32_to_bf16(an4[2])) |
+                                       (static_cast<uint32_t>(f32_to_bf16(an4[3])) << 16));
                 if (more)
-                    a.Y[roff + r] = static_cast<float>(an + beta * (an - static_cast<double>(a_prev)));
+                    reinterpret_cast<float4 *>(a.Y + roff)[q] = make_float4(yn4[0], yn4[1], yn4[2], yn4[3]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int r = 4 * q + u;
+                    if (r < R) {
+                        a.A[roff + r] = an4[u];
+                        if (BF16)
+                            a.A16[roff + r] = f32_to_bf16(an4[u]);
+                        if (more)
+                            a.Y[roff + r] = yn4[u];
+                    }
+                }
             }
         }
     } else if (more && a.l == 0) {
@@ -1038,6 +1120,241 @@ __global__ __launch_bounds__(256) void k_finalize16(NTC_ROW_PARAMS)
     finish_row16<BF16>(a, sr.row, r, g, hd, y);
 }
 
+// ------------------------------------------------- wave-per-item (R <= 32)
+//
+// 17 <= R <= 32, N <= 4: one wave per work item, split into two 32-lane
+// groups; lane r of a group owns column r.  The item's samples are taken 64
+// at a time (sampler and record fetch one per lane, staged in LDS) and
+// consumed two per step, one per group: each group gathers its sample's N-1
+// factor rows (128 contiguous bytes per mode, or 64 from the BF16 shadow),
+// forms the Khatri-Rao row k, reduces k.y over its 32 lanes and accumulates
+// g += (k.y - x) k in FP32.  One v_mfma_f32_32x32x2f32 per step adds both
+// groups' rank-1 updates k k^T into one 32x32 FP32 block (K = the two
+// groups), which is added into FP64 after every 32 samples.
+
+// Sum over the 32 lanes of a group (every lane of the group gets it).
+__device__ __forceinline__ float group32_sum_f32(float x)
+{
+    x += dpp_f32<kDppXor1>(x);
+    x += dpp_f32<kDppXor2>(x);
+    x += dpp_f32<kDppRor + 4>(x);
+    x += dpp_f32<kDppRor + 8>(x);
+    return x + __shfl_xor(x, 16, 64);
+}
+
+__device__ __forceinline__ double group32_sum_f64(double x)
+{
+    x += dpp_f64<kDppXor1>(x);
+    x += dpp_f64<kDppXor2>(x);
+    x += dpp_f64<kDppHalfMirror>(x);
+    x += dpp_f64<kDppMirror>(x);
+    return x + __shfl_xor(x, 16, 64);
+}
+
+constexpr int kSlot32 = 32 + 32 * 32;  // doubles per partial slot: g[32], row-major H[32][32]
+
+// Accumulator register v of lane l of v_mfma_f32_32x32x2f32 holds
+// H[(v % 4) + 8 (v / 4) + 4 (l / 32)][l % 32].
+__device__ __forceinline__ int mfma32_row(int v, int l)
+{
+    return (v & 3) + 8 * (v >> 2) + 4 * (l >> 5);
+}
+
+// Power method, step, projection and extrapolation for a 32-lane-group row.
+// Lane l: i = l % 32, half = l / 32 holds hd[q] = H[i][16 half + q] of the
+// sampled Hessian (without ridge); g: sampled gradient of column i (without
+// ridge), on every lane.
+template <bool BF16, class Args>
+__device__ void finish_row32(const Args &a, int row, int lane, double g, double (&hd)[16], float y, double *s_v)
+{
+    const int R = a.R;
+    const int i = lane & 31, half = lane >> 5;
+    const bool live = i < R;
+    if (live) {
+        g += a.lambda * static_cast<double>(y);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (16 * half + q == i)
+                hd[q] += a.lambda;
+    }
+    double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
+    // w_i = (H v)_i: each half sums its 16 columns, then the halves combine
+    auto matvec = [&](double vi) {
+        if (half == 0)
+            s_v[i] = vi;
+        __builtin_amdgcn_wave_barrier();
+        double w = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            w = fma(hd[q], s_v[16 * half + q], w);
+        __builtin_amdgcn_wave_barrier();
+        return w + __shfl_xor(w, 32, 64);
+    };
+    bool vanished = false;
+    for (int t = 0; t < a.power_iters; ++t) {
+        const double w = matvec(v);
+        const double n2 = group32_sum_f64(w * w);
+        if (!(n2 > 0.0)) {
+            vanished = true;
+            break;
+        }
+        v = w / sqrt(n2);
+    }
+    double L = 0.0;
+    if (!vanished)
+        L = group32_sum_f64(v * matvec(v));
+    if (!live || half != 0)
+        return;
+    const int64_t off = static_cast<int64_t>(row) * R + i;
+    const float a_prev = (a.l == 0) ? y : a.A[off];
+    const bool more = a.l + 1 < a.max_inner;
+    if (L > 0.0) {
+        double an = static_cast<double>(y) - g / L;
+        an = an > 0.0 ? an : 0.0;
+        const double sl = sqrt(L), sm = sqrt(a.lambda);
+        const double beta = (sl - sm) / (sl + sm);
+        const float af = static_cast<float>(an);
+        a.A[off] = af;
+        if (BF16)
+            a.A16[off] = f32_to_bf16(af);
+        if (more)
+            a.Y[off] = static_cast<float>(an + beta * (an - static_cast<double>(a_prev)));
+    } else if (more && a.l == 0) {
+        a.Y[off] = y;  // row skipped: Y_1 = Y_0
+    }
+}
+
+template <int NM, bool BF16>
+__global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    __shared__ uint4 s_rec[64];
+    __shared__ double s_h[16 * 64];  // FP64 sum of the accumulator: register v of lane l at v*64 + l
+    __shared__ double s_v[32];
+    const Item it = a.items[blk_];
+    const int lane = threadIdx.x;
+    const int r = lane & 31;
+    const int grp = lane >> 5;
+    const int R = a.R;
+    const bool rlive = r < R;
+    const int rr = rlive ? r : 0;
+
+    const int64_t base = a.rowptr[it.row];
+    const int64_t n = a.rowptr[it.row + 1] - base;
+    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, it.row));
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const float y = rlive ? ysrc[static_cast<int64_t>(it.row) * R + r] : 0.0f;
+    const uint4 zero_rec = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+        s_h[v * 64 + lane] = 0.0;
+
+    float gf = 0.0f;
+    for (int jb = it.j0; jb < it.j1; jb += 64) {
+        const int cnt = min(64, it.j1 - jb);
+        uint4 w0 = zero_rec;
+        if (lane < cnt) {
+            const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
+            w0 = *reinterpret_cast<const uint4 *>(a.records + (base + q) * 4);
+        }
+        __builtin_amdgcn_wave_barrier();  // the previous batch's reads of s_rec are done
+        s_rec[lane] = w0;
+        __builtin_amdgcn_wave_barrier();
+        const int steps = (cnt + 1) >> 1;
+        for (int h0 = 0; h0 < steps; h0 += 16) {
+            const int hs = min(16, steps - h0);
+            // all gathers of up to 16 steps first (a missing sample reads the zero rows)
+            float f[NM - 1][16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                if (t < hs) {
+                    const uint32_t *rec = reinterpret_cast<const uint32_t *>(&s_rec[2 * (h0 + t) + grp]);
+#pragma unroll
+                    for (int mm = 0; mm < NM - 1; ++mm) {
+                        const uint32_t e = rec[mm] + static_cast<uint32_t>(rr);
+                        if (BF16)
+                            f[mm][t] = bf16_to_f32(a.gath16[mm][e]);
+                        else
+                            f[mm][t] = a.gath[mm][e];
+                    }
+                }
+            }
+            f32x16 acc = {0.0f};
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                if (t < hs) {  // wave-uniform
+                    float k = f[0][t];
+#pragma unroll
+                    for (int mm = 1; mm < NM - 1; ++mm)
+                        k *= f[mm][t];
+                    k = rlive ? k : 0.0f;
+                    const uint32_t *rec = reinterpret_cast<const uint32_t *>(&s_rec[2 * (h0 + t) + grp]);
+                    const float x = __uint_as_float(rec[NM - 1]);  // 0 for a missing sample
+                    const float pred = group32_sum_f32(k * y);
+                    gf = fmaf(pred - x, k, gf);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(k, k, acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                s_h[v * 64 + lane] += static_cast<double>(acc[v]);
+        }
+    }
+    // gradient: both groups' partial sums of column r
+    double g = static_cast<double>(gf);
+    g += __shfl_xor(g, 32, 64);
+    __builtin_amdgcn_wave_barrier();
+
+    if (it.slot >= 0) {
+        double *P = a.partials + static_cast<int64_t>(it.slot) * kSlot32;
+        if (lane < 32)
+            P[lane] = g;
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            P[32 + mfma32_row(v, lane) * 32 + r] = s_h[v * 64 + lane];
+        return;
+    }
+    // lane (i, half) takes H[i][16 half + q]: stored by lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8)
+    const int i = r, half = grp;
+    const int src_v = (i & 3) + 4 * (i >> 3);
+    const int src_hi = 32 * ((i >> 2) & 1);
+    double hd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        hd[q] = s_h[src_v * 64 + src_hi + 16 * half + q];
+    finish_row32<BF16>(a, it.row, lane, g, hd, y, s_v);
+}
+
+// Split rows with 17 <= R <= 32: one wave sums the row's partial slots in
+// slot order, then the power method and step as above.
+template <bool BF16>
+__global__ __launch_bounds__(64) void k_finalize32(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    __shared__ double s_v[32];
+    const SplitRow sr = a.split[blk_];
+    const int lane = threadIdx.x;
+    const int i = lane & 31, half = lane >> 5;
+    double g = 0.0;
+    double hd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        hd[q] = 0.0;
+    for (int s = 0; s < sr.nslots; ++s) {
+        const double *P = a.partials + static_cast<int64_t>(sr.slot0 + s) * kSlot32;
+        g += P[i];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            hd[q] += P[32 + i * 32 + 16 * half + q];
+    }
+    float y = 0.0f;
+    if (i < a.R) {
+        const float *ysrc = (a.l == 0) ? a.A : a.Y;
+        y = ysrc[static_cast<int64_t>(sr.row) * a.R + i];
+    }
+    finish_row32<BF16>(a, sr.row, lane, g, hd, y, s_v);
+}
+
 #define NTC_GO(KERNEL, BLOCK) \
     hipLaunchKernelGGL(KERNEL, dim3(L.blocks), dim3(BLOCK), 0, s, L.args, L.start, L.owner, L.n)
 
@@ -1055,9 +1372,11 @@ hipError_t go_rows(const KernelClass &kc, const Launch &L, hipStream_t s)
             NTC_GO((k_rows16_nm<BF16>), 64);
     } else if (kc.rp == 32) {
         if (kc.nmodes == 3)
-            NTC_GO((k_row_items<32, 3, BF16>), 64);
+            NTC_GO((k_rows32<3, BF16>), 64);
         else if (kc.nmodes == 4)
-            NTC_GO((k_row_items<32, 4, BF16>), 64);
+            NTC_GO((k_rows32<4, BF16>), 64);
+        else if (kc.nmodes == 2)
+            NTC_GO((k_rows32<2, BF16>), 64);
         else
             NTC_GO((k_row_items<32, 0, BF16>), 64);
     } else if (kc.rp == 64) {
@@ -1079,7 +1398,7 @@ hipError_t go_finalize(const KernelClass &kc, const Launch &L, hipStream_t s)
     if (kc.rp == 16)
         NTC_GO((k_finalize16<BF16>), 256);
     else if (kc.rp == 32)
-        NTC_GO((k_row_finalize<32, BF16>), 64);
+        NTC_GO((k_finalize32<BF16>), 64);
     else if (kc.rp == 64)
         NTC_GO((k_row_finalize<64, BF16>), 64);
     else

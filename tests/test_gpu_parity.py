@@ -39,7 +39,7 @@ def _pair(p, R, *, init_seed=1, scale=None, **kw):
     init = synth.uniform_init(p.dims, R, init_seed, scale)
     g = ntc.Problem(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
                     init=init, stream=0, **kw)
-    okw = {k: v for k, v in kw.items() if k != "gather_bf16"}
+    okw = {k: v for k, v in kw.items() if k not in ("gather_bf16", "schedule")}
     o = O.Oracle(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
                  init=init, **okw)
     return g, o, init
@@ -96,6 +96,12 @@ CASES = {
     "zipf_power1": lambda: (synth.c1_small(seed=6), 16, dict(c=0.1, power_iters=1)),
     "zipf_power3_inner2": lambda: (synth.c1_small(seed=7), 16, dict(c=0.1, power_iters=3, max_inner=2)),
     "r8_power2_lam0": lambda: (synth.c0(seed=3), 8, dict(c=0.3, power_iters=2, lam=0.0)),
+    # 17 <= R <= 32: two 32-lane groups per wave, split rows through the partial slots
+    "r24_4way_split": lambda: (synth.make_problem((60, 50, 40, 30), 120_000, 12, seed=11, zipf_s=1.1), 24,
+                               dict(c=0.2, schedule={"item_samples": 128})),
+    "r32_inner2_power3": lambda: (synth.make_problem((200, 150, 80), 100_000, 16, seed=12), 32,
+                                  dict(c=0.3, max_inner=2, power_iters=3)),
+    "r20_matrix": lambda: (synth.make_problem((500, 400), 60_000, 8, seed=13), 20, dict(c=0.2)),
 }
 
 

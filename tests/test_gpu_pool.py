@@ -1,0 +1,167 @@
+"""Batching and serving form (ntc_pool_*), through the C ABI.
+
+A problem inside a pool takes exactly the kernels and arithmetic it takes
+alone, so after s pool sweeps its factors must be bit-identical to s
+ntc_sweep calls on it alone, whatever else shares the pool.  The stop rule,
+admission by arena memory and slot reuse are checked against their
+definitions.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2109_09534_amd as ntc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _mix(seed0=500):
+    """Small instances of the batching mixture: mixed dims, nnz and R, one
+    4-way, one BF16, one MAX_INNER = 2, one with Zipf heads (split rows)."""
+    out = []
+    shapes = [((60, 50, 40), 12000, 8, {}),
+              ((200, 90, 70), 40000, 16, {}),
+              ((120, 100, 30), 30000, 32, {}),
+              ((30, 25, 20, 12), 20000, 10, {}),
+              ((150, 80, 60), 35000, 16, {"gather_bf16": True}),
+              ((90, 70, 50), 25000, 12, {"max_inner": 2}),
+              ((400, 300, 40), 150000, 16, {"zipf": 1.1})]
+    for i, (dims, nnz, R, kw) in enumerate(shapes):
+        kw = dict(kw)
+        z = kw.pop("zipf", None)
+        p = synth.make_problem(dims, nnz, min(R, 8), zipf_s=z, noise_var=0.01, value_model="exact",
+                               test_frac=0.05, seed=seed0 + i, name="mix")
+        out.append((p, R, dict(seed=seed0 + i, **kw)))
+    return out
+
+
+def _alone(p, R, kw, sweeps):
+    g = ntc.Problem(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
+                    stream=0, **kw)
+    g.sweep(sweeps)
+    f = g.all_factors()
+    loss = g.loss()
+    g.close()
+    return f, loss
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_pool_sweeps_are_bit_identical_to_running_alone(use_graph):
+    mix = _mix()
+    sweeps = 4
+    with ntc.Pool(arena_bytes=2 << 30, max_slots=16, use_graph=use_graph, window=0, max_sweeps=1000) as pool:
+        slots = []
+        for p, R, kw in mix:
+            s = pool.admit(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
+                           **kw)
+            assert s is not None
+            slots.append(s)
+        _say(f"  admitted {len(slots)} problems, {pool.info()}")
+        pool.step(sweeps)
+        for (p, R, kw), s in zip(mix, slots):
+            st, sw, rm = pool.query(s)
+            assert st == ntc.SLOT_RUNNING and sw == sweeps
+            ref, loss = _alone(p, R, kw, sweeps)
+            for m in range(len(p.dims)):
+                got = pool.factors(s, m)
+                assert np.array_equal(got, ref[m]), (s, m, R, kw)
+            assert abs(rm - loss[2]) <= 1e-12 * max(loss[2], 1.0), (rm, loss[2])
+            _say(f"  slot {s}: dims {p.dims} R={R} {kw}: factors identical, test RMSE {rm:.6f}")
+
+
+def test_membership_changes_keep_every_problem_exact():
+    """Evict and admit between sweeps; the launch tables and graph are rebuilt
+    and every problem still matches its solo run for the sweeps it saw."""
+    mix = _mix(700)
+    with ntc.Pool(arena_bytes=2 << 30, max_slots=8, window=0, max_sweeps=1000) as pool:
+        first = [pool.admit(p.dims, p.coords, p.values, R, test_coords=p.test_coords,
+                            test_values=p.test_values, **kw) for p, R, kw in mix[:4]]
+        pool.step(2)
+        pool.evict(first[1])
+        late = [pool.admit(p.dims, p.coords, p.values, R, test_coords=p.test_coords,
+                           test_values=p.test_values, **kw) for p, R, kw in mix[4:]]
+        pool.step(3)
+        seen = {first[0]: (mix[0], 5), first[2]: (mix[2], 5), first[3]: (mix[3], 5)}
+        for s, item in zip(late, mix[4:]):
+            seen[s] = (item, 3)
+        for s, ((p, R, kw), n) in seen.items():
+            assert pool.query(s)[1] == n
+            ref, _ = _alone(p, R, kw, n)
+            for m in range(len(p.dims)):
+                assert np.array_equal(pool.factors(s, m), ref[m]), (s, m)
+        _say(f"  {len(seen)} problems exact across an eviction and {len(late)} late admissions")
+
+
+def test_stop_rule_and_slot_reuse():
+    p = synth.make_problem((80, 60, 50), 20000, 4, noise_var=0.01, value_model="exact", test_frac=0.1, seed=9)
+    R = 4
+    W, tol = 3, 1e-3
+    with ntc.Pool(arena_bytes=1 << 30, max_slots=4, window=W, tol=tol, max_sweeps=400) as pool:
+        s = pool.admit(p.dims, p.coords, p.values, R, c=0.5, test_coords=p.test_coords,
+                       test_values=p.test_values, seed=3)
+        for _ in range(500):
+            pool.step(1)
+            if pool.query(s)[0] == ntc.SLOT_STOPPED:
+                break
+        st, stop_at, _ = pool.query(s)
+        assert st == ntc.SLOT_STOPPED and pool.stopped() == [s]
+        # the same problem alone: the rule on its own test-RMSE history
+        g = ntc.Problem(p.dims, p.coords, p.values, R, c=0.5, test_coords=p.test_coords,
+                        test_values=p.test_values, seed=3, stream=0)
+        hist = [g.loss()[2]]
+        rule_at = None
+        for k in range(1, 401):
+            g.sweep(1)
+            hist.append(g.loss()[2])
+            if k >= W and not (hist[k - W] - hist[k] >= tol * hist[k]):
+                rule_at = k
+                break
+        g.close()
+        _say(f"  pool stopped after {stop_at} sweeps; the rule on the solo history fires at {rule_at}")
+        assert rule_at == stop_at
+        # the stopped problem no longer advances
+        pool.step(2)
+        assert pool.query(s)[1] == stop_at
+        used = pool.info()["used"]
+        pool.evict(s)
+        assert pool.info()["used"] == 0 and used > 0
+        s2 = pool.admit(p.dims, p.coords, p.values, R, c=0.5, test_coords=p.test_coords,
+                        test_values=p.test_values, seed=3)
+        assert s2 == s and pool.info()["used"] == used
+
+
+def test_admission_by_arena_memory():
+    p = synth.make_problem((100, 80, 60), 30000, 4, noise_var=0.0, value_model="exact", test_frac=0.05, seed=4)
+    need = ntc.estimate_bytes(p.dims, p.nnz, 16, n_test=p.test_values.shape[0])
+    cap = int(need * 3.5)
+    with ntc.Pool(arena_bytes=cap, max_slots=16, window=0) as pool:
+        slots = []
+        while True:
+            s = pool.admit(p.dims, p.coords, p.values, 16, test_coords=p.test_coords,
+                           test_values=p.test_values, seed=len(slots))
+            if s is None:
+                break
+            slots.append(s)
+            assert len(slots) < 16
+        info = pool.info()
+        _say(f"  estimate {need} B per problem, arena {cap} B: admitted {len(slots)}, {info}")
+        assert len(slots) >= 3
+        assert info["used"] <= len(slots) * need
+        pool.step(1)
+        # two neighbouring problems' memory makes one free block large enough again
+        pool.evict(slots[0])
+        pool.evict(slots[1])
+        assert pool.admit(p.dims, p.coords, p.values, 16, test_coords=p.test_coords,
+                          test_values=p.test_values, seed=99) is not None
+        # slots are a hard limit too
+    with ntc.Pool(arena_bytes=1 << 30, max_slots=2, window=0) as pool:
+        assert pool.admit(p.dims, p.coords, p.values, 8) is not None
+        assert pool.admit(p.dims, p.coords, p.values, 8) is not None
+        assert pool.admit(p.dims, p.coords, p.values, 8) is None

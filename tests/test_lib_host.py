@@ -95,3 +95,20 @@ def test_create_rejects_bad_data():
         ntc.Problem(p.dims, p.coords, p.values, 3, init=init, stream=0)
     with pytest.raises(ntc.NtcError, match="nmodes"):
         ntc.Problem([5], np.zeros((0, 1), np.int32), np.zeros(0, np.float32), 3, stream=0)
+
+
+def test_estimate_bytes_bounds_the_allocations():
+    """The admission estimate is host-only arithmetic: it covers at least the
+    records and factors and grows with every size."""
+    import paper_2109_09534_amd as ntc
+    dims = [480_000, 18_000, 2_000]
+    b = ntc.estimate_bytes(dims, 95_000_000, 16, n_test=5_000_000)
+    records = 3 * 95_000_000 * 16
+    factors = sum((d + 1) * 16 * 4 for d in dims)
+    assert b >= records + factors
+    assert ntc.estimate_bytes(dims, 95_000_000, 16, n_test=5_000_000, gather_bf16=True) > b
+    assert ntc.estimate_bytes(dims, 95_000_000, 32, n_test=5_000_000) > b
+    assert ntc.estimate_bytes(dims, 96_000_000, 16, n_test=5_000_000) > b
+    assert ntc.estimate_bytes(dims, 95_000_000, 16, n_test=5_000_000, max_inner=2) > b
+    with pytest.raises(ntc.NtcError):
+        ntc.estimate_bytes([10, 0, 3], 5, 4)

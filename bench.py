@@ -37,8 +37,10 @@ def kernel_name(kind: str, nmodes: int, R: int, bf16: bool) -> str:
         return {"row_items": f"k_rows16<{nmodes}, 4, {b}>", "row_chunks": f"k_chunk16<{nmodes}, 4, {b}>",
                 "row_tiny": f"k_tiny16<{nmodes}, 4, {b}>", "row_finalize": f"k_finalize16<{b}>"}[kind]
     if R <= 32:
-        return {"row_items": f"k_rows32<{nmodes}, {b}>", "row_finalize": f"k_finalize32<{b}>"}[kind]
-    return {"row_items": f"k_row_items<64, {nmodes}, {b}>", "row_finalize": f"k_row_finalize<64, {b}>"}[kind]
+        return {"row_items": f"k_rows32<{nmodes}, {b}>", "row_finalize": f"k_finalize32<{b}>",
+                "row_reduce": "k_reduce_slots<32>"}[kind]
+    return {"row_items": f"k_row_items<64, {nmodes}, {b}>", "row_finalize": f"k_row_finalize<64, {b}>",
+            "row_reduce": "k_reduce_slots<64>"}[kind]
 
 
 def log(*a):
@@ -91,6 +93,8 @@ def main():
     ap.add_argument("--instances", type=int, default=256, help="batch/serve: number of problems")
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-at-a-time baseline")
     ap.add_argument("--rates", default="0.25,0.5,1,2", help="serve: arrival rates as fractions of saturation")
+    ap.add_argument("--sweeps-per-step", type=int, default=4,
+                    help="batch/serve: pool sweeps between host checks (the stop rule runs on the device)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -183,6 +187,27 @@ def main():
     loss_ms = (time.perf_counter() - t0) * 1e3
     log(f"loss before {loss0}, after {loss} ({loss_ms:.1f} ms)")
 
+    other = None
+    if args.workload == "c2":
+        # the other precision on the same data, same seed and sweep count: rate and held-out quality
+        prob.close()
+        alt = not args.bf16
+        q = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=max_inner, seed=args.seed,
+                        gather_bf16=alt, test_coords=p.test_coords, test_values=p.test_values, stream=0)
+        if args.warmup > 0:
+            q.time_sweeps(args.warmup)
+        q.synchronize()
+        t1 = time.perf_counter()
+        q.time_sweeps(args.steps)
+        q.synchronize()
+        wall_q = time.perf_counter() - t1
+        q.time_sweeps(1)     # the same sweep count as the main problem before its loss
+        loss_q = q.loss()
+        q.close()
+        other = {"gather": "bf16" if alt else "f32", "value": round(upd_sweep * args.steps / wall_q, 1),
+                 "ms_per_step": round(wall_q * 1e3 / args.steps, 4), "test_rmse": round(float(loss_q[2]), 6)}
+        log(f"{other['gather']} gathers: {other['ms_per_step']} ms per sweep, test RMSE {other['test_rmse']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -229,6 +254,8 @@ def main():
         "train_rmse": round(float(loss[1]), 6),
         "launches": per_mode,
     }
+    if other is not None:
+        out["other_precision"] = other
     print(json.dumps(out), flush=True)
 
 
@@ -286,8 +313,8 @@ def run_batch(args):
     t0 = time.perf_counter()
     sweeps = 0
     while pool.info()["running"] > 0:
-        pool.step(1)
-        sweeps += 1
+        pool.step(args.sweeps_per_step)
+        sweeps += args.sweeps_per_step
     run_s = time.perf_counter() - t0
     per = [pool.query(s) for s in slots]
     upd = sum(_updates_per_sweep(p) * q[1] for p, q in zip(probs, per))
@@ -384,7 +411,7 @@ def run_serve(args):
                 queue.popleft()
                 slot_req[s] = i
             if pool.info()["running"] > 0:
-                pool.step(1)
+                pool.step(args.sweeps_per_step)
             elif nxt < n:
                 time.sleep(max(0.0, min(arrive[nxt] - (time.perf_counter() - start), 0.05)))
             for s in pool.stopped():

@@ -177,7 +177,9 @@ typedef struct ntc_launch_record {
                         1: finalize of rows split over several work items;
                         2: rows with at most 4 sampled entries, one per lane;
                         3: chunks of rows with many samples, one per 256-thread
-                        block (R <= 16) */
+                        block (R <= 16);
+                        4: second-level sums of the partial slots of rows split
+                        into many items (R > 16) */
     int32_t mode;    /* mode being updated */
     int32_t inner;   /* inner step l of Alg. 1 */
     int32_t blocks;  /* workgroups launched */
@@ -215,10 +217,11 @@ ntc_status ntc_release(ntc_handle h);
  * calls on it alone.  The launches of one sweep are captured once as a HIP
  * graph and replayed until the set of running problems changes.
  *
- * Stop rule (checked after every sweep, per problem with a held-out set):
- * stop after sweep s >= window when RMSE_test(s - window) - RMSE_test(s)
- * < tol * RMSE_test(s), or at max_sweeps.  A stopped problem keeps its
- * slot and memory (for queries) until ntc_pool_evict.
+ * Stop rule (evaluated on the device after every sweep, per problem with a
+ * held-out set): stop after sweep s >= window when RMSE_test(s - window) -
+ * RMSE_test(s) < tol * RMSE_test(s), or at max_sweeps (problems without a
+ * held-out set stop only there).  A stopped problem keeps its slot and
+ * memory (for queries) until ntc_pool_evict.
  * ---------------------------------------------------------------------- */
 typedef struct ntc_pool *ntc_pool_handle;
 
@@ -245,8 +248,11 @@ ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *d
                           const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
                           int32_t *slot);
 
-/* Run `nsweeps` pool sweeps over the running problems, applying the stop
- * rule after each.  Synchronising. */
+/* Enqueue `nsweeps` pool sweeps over the running problems back to back and
+ * wait for them.  The stop rule is applied on the device after every sweep;
+ * a problem that stops mid-way is not touched by the remaining sweeps, so
+ * its factors are those of the sweep at which it stopped whatever nsweeps
+ * is.  Synchronising. */
 ntc_status ntc_pool_step(ntc_pool_handle pool, int32_t nsweeps);
 
 /* State of a slot: *state (ntc_slot_state), sweeps run, and the last

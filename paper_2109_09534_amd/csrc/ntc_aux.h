@@ -46,4 +46,27 @@ hipError_t launch_test_sums(const LossArgs *args, const int32_t *start, const in
 // *k[t] += 1 for t < n
 hipError_t launch_advance_many(int64_t *const *k, int32_t n, hipStream_t s);
 
+// End of a pool sweep, per running problem j (device state indexed by slot):
+// unless it has already stopped, advance its sweep counters, record the
+// held-out RMSE of this sweep (test entry tidx[j] >= 0) and apply the stop
+// rule: stop after sweep s >= window when rmse(s - window) - rmse(s) <
+// tol * rmse(s), or when s >= max_sweeps.
+struct PoolRuleArgs {
+    int32_t n;                   // running problems
+    const int32_t *slot;         // [n] slot of each
+    int64_t *const *kdev;        // [n] the problems' sampler counters
+    const int32_t *tidx;         // [n] index into test_out, or -1 (no held-out set)
+    const int64_t *n_test;       // [n] held-out entries
+    const double *test_out;      // [2 * test entries] held-out sums of this sweep
+    int32_t *stop;               // [slots]
+    int64_t *sweeps;             // [slots]
+    int64_t *nhist;              // [slots] RMSE values recorded so far (the first at admission)
+    double *hist;                // [slots][window + 1] ring of recent RMSE values
+    double *last;                // [slots] most recent RMSE
+    int32_t window;
+    int32_t max_sweeps;
+    double tol;
+};
+hipError_t launch_pool_rule(const PoolRuleArgs &a, hipStream_t s);
+
 }  // namespace ntc

@@ -247,6 +247,35 @@ __global__ __launch_bounds__(kLossThreads) void k_test_final_b(const int32_t *__
     }
 }
 
+__global__ void k_pool_rule(const PoolRuleArgs a)
+{
+    const int j = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= a.n)
+        return;
+    const int slot = a.slot[j];
+    if (a.stop[slot] != 0)
+        return;
+    *a.kdev[j] += 1;
+    const int64_t s = a.sweeps[slot] + 1;
+    a.sweeps[slot] = s;
+    bool stop = s >= a.max_sweeps;
+    if (a.tidx[j] >= 0) {
+        const double rmse = sqrt(a.test_out[2 * a.tidx[j]] / static_cast<double>(a.n_test[j]));
+        const int W = a.window;
+        double *h = a.hist + static_cast<int64_t>(slot) * (W + 1);
+        const int64_t k = a.nhist[slot];  // this value is rmse after k sweeps
+        h[k % (W + 1)] = rmse;
+        a.nhist[slot] = k + 1;
+        a.last[slot] = rmse;
+        if (W > 0 && k >= W) {
+            const double then = h[(k - W) % (W + 1)];
+            stop = stop || !(then - rmse >= a.tol * rmse);
+        }
+    }
+    if (stop)
+        a.stop[slot] = 1;
+}
+
 __global__ void k_advance_many(int64_t *const *__restrict__ k, int32_t n)
 {
     const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
@@ -316,6 +345,14 @@ hipError_t launch_test_sums(const LossArgs *args, const int32_t *start, const in
         return hipSuccess;
     hipLaunchKernelGGL(k_test_partials_b, dim3(blocks), dim3(kLossThreads), 0, s, args, start, owner, n, part);
     hipLaunchKernelGGL(k_test_final_b, dim3(n), dim3(kLossThreads), 0, s, start, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool_rule(const PoolRuleArgs &a, hipStream_t s)
+{
+    if (a.n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pool_rule, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -167,7 +167,9 @@ struct ModeState {
     uint32_t *records = nullptr;
     Item *items = nullptr;
     SplitRow *split = nullptr;
-    int32_t *tiny = nullptr;
+    ntc::SlotGroup *groups = nullptr;
+    int32_t n_groups = 0;
+    ntc::RowItem *tiny = nullptr;
     int32_t n_tiny = 0;
     int64_t tiny_samples = 0;
     int32_t n_items = 0;
@@ -298,7 +300,10 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.records = m.records;
     a.items = m.items;
     a.split = m.split;
+    a.groups = m.groups;
+    a.n_groups = m.n_groups;
     a.tiny = m.tiny;
+    a.rows = (h->RP == 16 && h->N <= 4) ? reinterpret_cast<const ntc::RowItem *>(m.items) : nullptr;
     a.n_tiny = m.n_tiny;
     a.c = h->c;
     int w = 0;
@@ -361,8 +366,8 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
             NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         }
         // launch order: one-row-per-lane, chunks, rows, finalize of split rows
-        for (ntc::RowKernel kern : {ntc::kTiny, ntc::kChunks, ntc::kRows, ntc::kFinalize}) {
-            L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny);
+        for (ntc::RowKernel kern : {ntc::kTiny, ntc::kChunks, ntc::kRows, ntc::kReduce, ntc::kFinalize}) {
+            L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny, md.n_groups);
             if (L.blocks <= 0)
                 continue;
             hipStream_t st = (kern == ntc::kTiny && fork) ? h->side : h->stream;
@@ -382,10 +387,10 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
                 r.mode = mode;
                 r.inner = l;
                 r.blocks = L.blocks;
-                r.samples = kern == ntc::kRows ? md.row_samples : kern == ntc::kFinalize ? 0
-                            : kern == ntc::kTiny ? md.tiny_samples : md.chunk_samples;
+                r.samples = kern == ntc::kRows ? md.row_samples : kern == ntc::kTiny ? md.tiny_samples
+                            : kern == ntc::kChunks ? md.chunk_samples : 0;
                 r.rows = kern == ntc::kRows ? md.row_fused : kern == ntc::kFinalize ? md.n_split
-                         : kern == ntc::kTiny ? md.n_tiny : md.chunk_fused;
+                         : kern == ntc::kTiny ? md.n_tiny : kern == ntc::kChunks ? md.chunk_fused : 0;
                 probe->rec.push_back(r);
             }
         }
@@ -566,7 +571,18 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
         std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return bsz[a] > bsz[b]; });
         std::vector<Item> items, whole;
         std::vector<SplitRow> split;
-        std::vector<int32_t> tiny;
+        std::vector<ntc::SlotGroup> groups;
+        std::vector<ntc::RowItem> tiny;
+        auto row_item = [&](int32_t r) {
+            const int64_t b0 = md.h_rowptr[r];
+            return ntc::RowItem{r, static_cast<int32_t>(md.h_rowptr[r + 1] - b0), b0};
+        };
+        auto as_item = [](const ntc::RowItem &ri) {
+            Item it;
+            static_assert(sizeof(Item) == sizeof(ntc::RowItem), "item layouts");
+            std::memcpy(&it, &ri, sizeof(it));
+            return it;
+        };
         int32_t slot = 0;
         if (rp == 16) {
             // one row per lane / one row per 16-lane group / 16 groups per row chunk
@@ -576,13 +592,14 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
                 md.samples += b;
                 md.active_rows += 1;
                 if (b <= h->tiny_max) {
-                    tiny.push_back(r);
+                    tiny.push_back(row_item(r));
                     md.tiny_samples += b;
                 } else if (b <= h->group_max) {
                     md.fused_rows += 1;
                     md.row_fused += 1;
                     md.row_samples += b;
-                    items.push_back(Item{r, 0, static_cast<int32_t>(b), -1});
+                    // N <= 4: the group kernel reads these as RowItem
+                    items.push_back(h->N <= 4 ? as_item(row_item(r)) : Item{r, 0, static_cast<int32_t>(b), -1});
                 } else if (b <= smax) {
                     md.fused_rows += 1;
                     md.chunk_fused += 1;
@@ -619,20 +636,43 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
                     for (int64_t j0 = 0; j0 < b; j0 += smax)
                         items.push_back(Item{r, static_cast<int32_t>(j0),
                                              static_cast<int32_t>(std::min(b, j0 + smax)), slot++});
-                    split.push_back(SplitRow{r, s0, slot - s0, 0});
+                    const int32_t ns = slot - s0;
+                    if (ns > 2 * ntc::kFanIn) {
+                        // second level: groups of kFanIn slots, numbered after all first-level slots
+                        const int32_t g0 = static_cast<int32_t>(groups.size());
+                        for (int32_t q = 0; q < ns; q += ntc::kFanIn)
+                            groups.push_back(ntc::SlotGroup{s0 + q, std::min(ntc::kFanIn, ns - q), -1, 0});
+                        split.push_back(SplitRow{r, -1 - g0, static_cast<int32_t>(groups.size()) - g0, 0});
+                    } else {
+                        split.push_back(SplitRow{r, s0, ns, 0});
+                    }
                 }
             }
+            // second-level slots follow the first-level ones
+            for (size_t q = 0; q < groups.size(); ++q)
+                groups[q].dst = slot + static_cast<int32_t>(q);
+            for (SplitRow &sr : split)
+                if (sr.slot0 < 0)
+                    sr.slot0 = groups[static_cast<size_t>(-1 - sr.slot0)].dst;
+            slot += static_cast<int32_t>(groups.size());
         }
         md.n_partial = static_cast<int32_t>(items.size());
         items.insert(items.end(), whole.begin(), whole.end());
         md.n_tiny = static_cast<int32_t>(tiny.size());
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.tiny), tiny.size() * sizeof(int32_t), "tiny rows"));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.tiny), tiny.size() * sizeof(ntc::RowItem),
+                              "tiny rows"));
         if (!tiny.empty())
-            NTC_HIP(hipMemcpy(md.tiny, tiny.data(), tiny.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            NTC_HIP(hipMemcpy(md.tiny, tiny.data(), tiny.size() * sizeof(ntc::RowItem), hipMemcpyHostToDevice));
         md.n_items = static_cast<int32_t>(items.size());
         md.n_split = static_cast<int32_t>(split.size());
         md.n_slots = slot;
         max_slots = std::max(max_slots, slot);
+        md.n_groups = static_cast<int32_t>(groups.size());
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.groups), groups.size() * sizeof(ntc::SlotGroup),
+                              "slot groups"));
+        if (!groups.empty())
+            NTC_HIP(hipMemcpy(md.groups, groups.data(), groups.size() * sizeof(ntc::SlotGroup),
+                              hipMemcpyHostToDevice));
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.items), items.size() * sizeof(Item), "items"));
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.split), split.size() * sizeof(SplitRow), "split"));
         if (!items.empty())
@@ -710,9 +750,9 @@ ntc_status ntc::problem_view(ntc_handle h, ntc::ProblemView *v)
     v->kdev = h->kdev;
     for (int m = 0; m < h->N; ++m) {
         const ModeState &md = h->md[m];
-        for (int kind = 0; kind < 4; ++kind)
+        for (int kind = 0; kind < ntc::kRowKernels; ++kind)
             v->blocks[m][kind] = ntc::row_kernel_blocks(static_cast<ntc::RowKernel>(kind), v->kc, md.n_items,
-                                                        md.n_group, md.n_split, md.n_tiny);
+                                                        md.n_group, md.n_split, md.n_tiny, md.n_groups);
         v->U[m] = h->U[m];
     }
     v->n_test = h->n_test;

@@ -20,6 +20,15 @@ struct Item {
     int32_t slot;
 };
 
+// A whole row for the kernels that take rows with few samples (R <= 16,
+// N <= 4): its CSR offset and length ride along, so the kernel needs no
+// row-pointer lookup before it can sample.  Same size as Item.
+struct RowItem {
+    int32_t row;
+    int32_t n;
+    int64_t base;
+};
+
 // A row whose minibatch is split over `nslots` consecutive partial slots.
 struct SplitRow {
     int32_t row;
@@ -28,13 +37,26 @@ struct SplitRow {
     int32_t pad;
 };
 
+// Rows split into many items (R > 16) first sum groups of up to kFanIn
+// consecutive partial slots into one second-level slot, so no finalize has
+// to walk thousands of slots: {first source slot, count, destination slot}.
+struct SlotGroup {
+    int32_t src;
+    int32_t count;
+    int32_t dst;
+    int32_t pad;
+};
+constexpr int kFanIn = 32;
+
 // Arguments of the row kernels for one (mode, inner step).
 struct RowArgs {
     const int64_t *rowptr;        // [I+1] CSR of this mode
     const uint32_t *records;      // [nnz][rec_words]: other-mode coordinates * R (increasing mode), value bits
     const Item *items;
     const SplitRow *split;
-    const int32_t *tiny;          // rows whose minibatch has 1..kTinyB samples (R <= 16 kernels)
+    const SlotGroup *groups;      // (R > 16) second-level slot sums, n_groups of them
+    const RowItem *tiny;          // rows whose minibatch has 1..kTinyB samples (R <= 16 kernels)
+    const RowItem *rows;          // (R <= 16, N <= 4) items [0, n_group) stored as RowItem
     const float *gath[kMaxModes - 1];     // other modes' FP32 factors, increasing mode order
     const uint16_t *gath16[kMaxModes - 1];// their BF16 shadows (precision form)
     float *A;                     // this mode's factor (A_l in, A_{l+1} out, in place)
@@ -45,6 +67,7 @@ struct RowArgs {
                                   // other mode, value 0
     uint64_t seed;
     const int64_t *kptr;          // sweep counter k of the problem (device)
+    const int32_t *stop;          // pool: nonzero once the problem has stopped (device), else null
     double lambda;
     double c;
     int32_t mode;
@@ -60,6 +83,7 @@ struct RowArgs {
                                   // items [n_group, n_items) row chunks for the block kernel
     int32_t n_split;
     int32_t n_tiny;
+    int32_t n_groups;
 };
 
 // Rows whose minibatch has at most this many samples run one row per lane.
@@ -89,11 +113,13 @@ struct KernelClass {
 // one per 256-thread block; kTiny rows with B_p <= kTinyB, one per lane;
 // kFinalize combines the partial slots of split rows.  R > 16: kRows takes
 // every work item, one per wave.
-enum RowKernel { kRows = 0, kFinalize = 1, kTiny = 2, kChunks = 3 };
+// kReduce (R > 16) sums groups of partial slots of rows split into many items.
+enum RowKernel { kRows = 0, kFinalize = 1, kTiny = 2, kChunks = 3, kReduce = 4 };
+constexpr int kRowKernels = 5;
 
 // Grid blocks one problem needs for `kind`.
 int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items, int32_t n_group, int32_t n_split,
-                          int32_t n_tiny);
+                          int32_t n_tiny, int32_t n_groups);
 hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s);
 // k[t] += 1 for t < n (the sweep counters, once per sweep)
 hipError_t launch_advance(int64_t *k, int32_t n, hipStream_t s);

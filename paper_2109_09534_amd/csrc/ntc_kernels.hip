@@ -25,7 +25,8 @@ namespace {
 
 // Every row kernel runs one launch over one or many problems (a Launch):
 // block b belongs to entry owner[b] (entry 0 when there is one entry) and is
-// that entry's local block b - start[entry].  The entry's RowArgs are read
+// that entry's local block b - start[entry]; a problem of a pool that has
+// stopped leaves at once.  The entry's RowArgs are read
 // through the constant address space: they never change during a launch, so
 // every field is a scalar load that the compiler may repeat at any point
 // instead of holding it in registers.
@@ -40,7 +41,9 @@ typedef const __attribute__((address_space(4))) RowArgs CRowArgs;
         ent_ = owner_[blockIdx.x];                           \
         blk -= start_[ent_];                                 \
     }                                                        \
-    CRowArgs &a = ((CRowArgs *)args_)[ent_]
+    CRowArgs &a = ((CRowArgs *)args_)[ent_];                 \
+    if (a.stop != nullptr && *a.stop != 0)                   \
+        return
 
 template <int W>
 __device__ __forceinline__ float group_sum(float v)
@@ -336,13 +339,25 @@ __device__ __forceinline__ double row_sum_f64(double x)
     return x;
 }
 
-// w += sum_{s>=1} hd[s] * v[sigma_s(lane)]
+// (H v)_lane = sum_s hd[s] * v[sigma_s(lane)], as four independent FMA
+// chains (s mod 4) summed at the end, so the latency of one product is four
+// FMAs deep instead of sixteen.
 template <int S>
-__device__ __forceinline__ void skew_matvec(const double (&hd)[16], double v, double &w)
+__device__ __forceinline__ void skew_chain(const double (&hd)[16], double v, double &w)
 {
     w = fma(hd[S], dpp_f64<kDppRor + S>(v), w);
-    if constexpr (S + 1 < 16)
-        skew_matvec<S + 1>(hd, v, w);
+    if constexpr (S + 4 < 16)
+        skew_chain<S + 4>(hd, v, w);
+}
+
+__device__ __forceinline__ double skew_matvec(const double (&hd)[16], double v)
+{
+    double w0 = hd[0] * v, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+    skew_chain<4>(hd, v, w0);
+    skew_chain<1>(hd, v, w1);
+    skew_chain<2>(hd, v, w2);
+    skew_chain<3>(hd, v, w3);
+    return (w0 + w1) + (w2 + w3);
 }
 
 // Power method, step, projection and extrapolation for the row owned by
@@ -361,8 +376,7 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
     double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
     bool vanished = false;
     for (int t = 0; t < a.power_iters; ++t) {
-        double w = hd[0] * v;
-        skew_matvec<1>(hd, v, w);
+        const double w = skew_matvec(hd, v);
         const double n2 = row_sum_f64(w * w);
         if (!(n2 > 0.0)) {
             vanished = true;
@@ -372,8 +386,7 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
     }
     double L = 0.0;
     if (!vanished) {
-        double w = hd[0] * v;
-        skew_matvec<1>(hd, v, w);
+        const double w = skew_matvec(hd, v);
         L = row_sum_f64(v * w);
     }
     if (!live)
@@ -420,6 +433,22 @@ struct GroupItem {
     int64_t base;
     Prp prp;
 };
+
+// Whole row `id` of the group kernel (N <= 4), from its RowItem.
+template <class Args>
+__device__ __forceinline__ GroupItem load_row_item(const Args &a, int id)
+{
+    GroupItem g;
+    g.has = id < a.n_group;
+    RowItem ri{0, 1, 0};
+    if (g.has)
+        ri = a.rows[id];
+    g.base = ri.base;
+    g.len = g.has ? static_cast<int>(minibatch_size(a.c, ri.n)) : 0;
+    g.it = Item{ri.row, 0, g.len, -1};
+    g.prp = make_prp(static_cast<uint32_t>(ri.n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, ri.row));
+    return g;
+}
 
 template <class Args>
 __device__ __forceinline__ GroupItem load_group_item(const Args &a, int id)
@@ -506,8 +535,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
     const int r = lane & 15;
     const int grp = lane >> 4;
     // whole rows: items [0, n_group), four per wave
-    const int id = blk_ * 4 + grp;
-    const GroupItem g = load_group_item(a, id < a.n_group ? id : a.n_items);
+    const GroupItem g = load_row_item(a, blk_ * 4 + grp);
     const int R = a.R;
     const bool rlive = r < R;
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
@@ -880,9 +908,10 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
     const int nm = (NM > 0) ? NM : a.nmodes;
     const int R = a.R;
     const bool v4 = (R & 3) == 0;  // uniform over the block (one problem per block)
-    const int row = a.tiny[id];
-    const int64_t base = a.rowptr[row];
-    const int64_t n = a.rowptr[row + 1] - base;
+    const RowItem ri = a.tiny[id];
+    const int row = ri.row;
+    const int64_t base = ri.base;
+    const int64_t n = ri.n;
     const int b = static_cast<int>(minibatch_size(a.c, n));  // 1 .. kTinyB
     const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, row));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
@@ -1183,11 +1212,12 @@ __device__ void finish_row32(const Args &a, int row, int lane, double g, double 
         if (half == 0)
             s_v[i] = vi;
         __builtin_amdgcn_wave_barrier();
-        double w = 0.0;
+        double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 16; ++q)
-            w = fma(hd[q], s_v[16 * half + q], w);
+            w4[q & 3] = fma(hd[q], s_v[16 * half + q], w4[q & 3]);
         __builtin_amdgcn_wave_barrier();
+        const double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
         return w + __shfl_xor(w, 32, 64);
     };
     bool vanished = false;
@@ -1325,34 +1355,57 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
     finish_row32<BF16>(a, it.row, lane, g, hd, y, s_v);
 }
 
-// Split rows with 17 <= R <= 32: one wave sums the row's partial slots in
-// slot order, then the power method and step as above.
+// Split rows with 17 <= R <= 32: a 256-thread block sums the row's partial
+// slots, thread t taking entries t, t + 256, ... of the slot in slot order
+// (coalesced, a fixed order per entry), then its first wave runs the power
+// method and step as above.
 template <bool BF16>
-__global__ __launch_bounds__(64) void k_finalize32(NTC_ROW_PARAMS)
+__global__ __launch_bounds__(256) void k_finalize32(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
+    __shared__ double s_p[kSlot32];
     __shared__ double s_v[32];
     const SplitRow sr = a.split[blk_];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kSlot32; e += 256) {
+        double acc = 0.0;
+        for (int q = 0; q < sr.nslots; ++q)
+            acc += a.partials[static_cast<int64_t>(sr.slot0 + q) * kSlot32 + e];
+        s_p[e] = acc;
+    }
+    __syncthreads();
+    if (tid >= 64)
+        return;
+    const int lane = tid;
     const int i = lane & 31, half = lane >> 5;
-    double g = 0.0;
+    const double g = s_p[i];
     double hd[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-        hd[q] = 0.0;
-    for (int s = 0; s < sr.nslots; ++s) {
-        const double *P = a.partials + static_cast<int64_t>(sr.slot0 + s) * kSlot32;
-        g += P[i];
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            hd[q] += P[32 + i * 32 + 16 * half + q];
-    }
+        hd[q] = s_p[32 + i * 32 + 16 * half + q];
     float y = 0.0f;
     if (i < a.R) {
         const float *ysrc = (a.l == 0) ? a.A : a.Y;
         y = ysrc[static_cast<int64_t>(sr.row) * a.R + i];
     }
     finish_row32<BF16>(a, sr.row, lane, g, hd, y, s_v);
+}
+
+// Second-level slot sums of rows split into many items: one 256-thread
+// block per group, thread t summing entries t, t + 256, ... over the group's
+// slots in slot order.
+template <int RP>
+__global__ __launch_bounds__(256) void k_reduce_slots(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    constexpr int S = RP + RP * RP;
+    const SlotGroup gr = a.groups[blk_];
+    for (int e = threadIdx.x; e < S; e += 256) {
+        double acc = 0.0;
+        for (int q = 0; q < gr.count; ++q)
+            acc += a.partials[static_cast<int64_t>(gr.src + q) * S + e];
+        a.partials[static_cast<int64_t>(gr.dst) * S + e] = acc;
+    }
 }
 
 #define NTC_GO(KERNEL, BLOCK) \
@@ -1398,7 +1451,7 @@ hipError_t go_finalize(const KernelClass &kc, const Launch &L, hipStream_t s)
     if (kc.rp == 16)
         NTC_GO((k_finalize16<BF16>), 256);
     else if (kc.rp == 32)
-        NTC_GO((k_finalize32<BF16>), 64);
+        NTC_GO((k_finalize32<BF16>), 256);
     else if (kc.rp == 64)
         NTC_GO((k_row_finalize<64, BF16>), 64);
     else
@@ -1434,6 +1487,19 @@ hipError_t go_chunks(const KernelClass &kc, const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
+template <bool BF16>
+hipError_t go_reduce(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    (void)sizeof(BF16);
+    if (kc.rp == 32)
+        NTC_GO((k_reduce_slots<32>), 256);
+    else if (kc.rp == 64)
+        NTC_GO((k_reduce_slots<64>), 256);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 #undef NTC_GO
 
 __global__ void k_advance(int64_t *k, int32_t n)
@@ -1446,7 +1512,7 @@ __global__ void k_advance(int64_t *k, int32_t n)
 }  // namespace
 
 int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items, int32_t n_group, int32_t n_split,
-                          int32_t n_tiny)
+                          int32_t n_tiny, int32_t n_groups)
 {
     const bool g16 = kc.rp == 16;
     switch (kind) {
@@ -1458,6 +1524,8 @@ int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items
         return g16 ? (n_tiny + 255) / 256 : 0;
     case kChunks:
         return (g16 && kc.nmodes <= 4) ? n_items - n_group : 0;
+    case kReduce:
+        return g16 ? 0 : n_groups;
     }
     return 0;
 }
@@ -1476,6 +1544,8 @@ hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch
         return b ? go_tiny<true>(kc, L, s) : go_tiny<false>(kc, L, s);
     case kChunks:
         return b ? go_chunks<true>(kc, L, s) : go_chunks<false>(kc, L, s);
+    case kReduce:
+        return go_reduce<false>(kc, L, s);
     }
     return hipErrorInvalidValue;
 }

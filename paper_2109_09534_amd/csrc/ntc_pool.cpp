@@ -126,8 +126,8 @@ void arena_free(void *p, void *ctx)
 struct Slot {
     ntc_handle h = nullptr;
     int32_t state = NTC_SLOT_FREE;
-    int64_t sweeps = 0;
-    std::vector<double> rmse;  // held-out RMSE after 0, 1, 2, ... sweeps
+    int64_t sweeps = 0;        // host copy of the device count
+    double rmse = 0.0;         // last held-out RMSE (NaN without a held-out set)
     ntc::ProblemView view{};
 };
 
@@ -153,8 +153,8 @@ struct ntc_pool {
     char *tab = nullptr;
     size_t tab_cap = 0;
     std::vector<PoolLaunch> launches;
-    int64_t *const *adv = nullptr;
-    int32_t n_adv = 0;
+    ntc::PoolRuleArgs rule{};
+    int32_t n_run = 0;
     const ntc::LossArgs *t_args = nullptr;
     const int32_t *t_start = nullptr;
     const int32_t *t_owner = nullptr;
@@ -162,7 +162,13 @@ struct ntc_pool {
     std::vector<int32_t> t_slot;  // test entry -> slot
     double *t_part = nullptr;     // [2 * 64 * max_slots]
     double *t_out = nullptr;      // [2 * max_slots]
-    double *t_host = nullptr;     // pinned copy of t_out
+    // device state of the stop rule, per slot, and its pinned host copy
+    int32_t *st_stop = nullptr;
+    int64_t *st_sweeps = nullptr;
+    int64_t *st_nhist = nullptr;
+    double *st_hist = nullptr;    // [slots][window + 1]
+    double *st_last = nullptr;
+    char *st_host = nullptr;      // sweeps | last | stop, copied back after each step
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -186,8 +192,12 @@ struct ntc_pool {
             (void)hipFree(t_part);
         if (t_out)
             (void)hipFree(t_out);
-        if (t_host)
-            (void)hipHostFree(t_host);
+        for (void *q : {static_cast<void *>(st_stop), static_cast<void *>(st_sweeps), static_cast<void *>(st_nhist),
+                        static_cast<void *>(st_hist), static_cast<void *>(st_last)})
+            if (q)
+                (void)hipFree(q);
+        if (st_host)
+            (void)hipHostFree(st_host);
         if (arena_mem)
             (void)hipFree(arena_mem);
         if (own_stream && stream)
@@ -267,7 +277,7 @@ ntc_status rebuild(ntc_pool *pool)
     };
     std::vector<Pending> pend;
     TableImage img;
-    const ntc::RowKernel order[4] = {ntc::kTiny, ntc::kChunks, ntc::kRows, ntc::kFinalize};
+    const ntc::RowKernel order[5] = {ntc::kTiny, ntc::kChunks, ntc::kRows, ntc::kReduce, ntc::kFinalize};
     for (int m = 0; m < maxN; ++m) {
         for (int l = 0; l < maxL; ++l) {
             for (const auto &kc : classes) {
@@ -282,7 +292,9 @@ ntc_status rebuild(ntc_pool *pool)
                         const int32_t b = v.blocks[m][kind];
                         if (b <= 0)
                             continue;
-                        args.push_back(v.args_host[m * v.max_inner + l]);
+                        ntc::RowArgs ra = v.args_host[m * v.max_inner + l];
+                        ra.stop = pool->st_stop + i;
+                        args.push_back(ra);
                         start.push_back(blocks);
                         owner.insert(owner.end(), static_cast<size_t>(b), static_cast<int32_t>(args.size() - 1));
                         blocks += b;
@@ -298,20 +310,23 @@ ntc_status rebuild(ntc_pool *pool)
             }
         }
     }
-    std::vector<int64_t *> kp;
-    for (int32_t i : run)
-        kp.push_back(pool->slots[i].view.kdev);
-    const size_t adv_off = img.put(kp.data(), kp.size() * sizeof(int64_t *));
-
-    // held-out sums for the stop rule
+    // held-out sums for the stop rule, and the rule's per-problem tables
     std::vector<ntc::LossArgs> targs;
-    std::vector<int32_t> tstart, towner;
+    std::vector<int32_t> tstart, towner, rslot, rtidx;
+    std::vector<int64_t *> kp;
+    std::vector<int64_t> rntest;
     pool->t_slot.clear();
     int32_t tb = 0;
     for (int32_t i : run) {
         const ntc::ProblemView &v = pool->slots[i].view;
-        if (v.n_test <= 0)
+        rslot.push_back(i);
+        kp.push_back(v.kdev);
+        rntest.push_back(v.n_test);
+        if (v.n_test <= 0) {
+            rtidx.push_back(-1);
             continue;
+        }
+        rtidx.push_back(static_cast<int32_t>(targs.size()));
         ntc::LossArgs a{};
         a.test_coords = v.test_coords;
         a.test_values = v.test_values;
@@ -328,6 +343,10 @@ ntc_status rebuild(ntc_pool *pool)
         pool->t_slot.push_back(i);
     }
     tstart.push_back(tb);
+    const size_t rs_off = img.put(rslot.data(), rslot.size() * sizeof(int32_t));
+    const size_t rk_off = img.put(kp.data(), kp.size() * sizeof(int64_t *));
+    const size_t rt_off = img.put(rtidx.data(), rtidx.size() * sizeof(int32_t));
+    const size_t rn_off = img.put(rntest.data(), rntest.size() * sizeof(int64_t));
     const size_t ta_off = img.put(targs.data(), targs.size() * sizeof(ntc::LossArgs));
     const size_t ts_off = img.put(tstart.data(), tstart.size() * sizeof(int32_t));
     const size_t to_off = img.put(towner.data(), towner.size() * sizeof(int32_t));
@@ -352,8 +371,22 @@ ntc_status rebuild(ntc_pool *pool)
         pl.L.blocks = pd.blocks;
         pool->launches.push_back(pl);
     }
-    pool->adv = reinterpret_cast<int64_t *const *>(base + adv_off);
-    pool->n_adv = static_cast<int32_t>(kp.size());
+    ntc::PoolRuleArgs &r = pool->rule;
+    r.n = static_cast<int32_t>(rslot.size());
+    r.slot = reinterpret_cast<const int32_t *>(base + rs_off);
+    r.kdev = reinterpret_cast<int64_t *const *>(base + rk_off);
+    r.tidx = reinterpret_cast<const int32_t *>(base + rt_off);
+    r.n_test = reinterpret_cast<const int64_t *>(base + rn_off);
+    r.test_out = pool->t_out;
+    r.stop = pool->st_stop;
+    r.sweeps = pool->st_sweeps;
+    r.nhist = pool->st_nhist;
+    r.hist = pool->st_hist;
+    r.last = pool->st_last;
+    r.window = pool->p.window;
+    r.max_sweeps = pool->p.max_sweeps;
+    r.tol = pool->p.tol;
+    pool->n_run = r.n;
     pool->t_args = reinterpret_cast<const ntc::LossArgs *>(base + ta_off);
     pool->t_start = reinterpret_cast<const int32_t *>(base + ts_off);
     pool->t_owner = reinterpret_cast<const int32_t *>(base + to_off);
@@ -363,15 +396,16 @@ ntc_status rebuild(ntc_pool *pool)
     return NTC_OK;
 }
 
-// One pool sweep: every row launch in (mode, inner step) order, then the
-// sweep counters, then the held-out sums of the stop rule.
+// One pool sweep: every row launch in (mode, inner step) order (problems
+// that have stopped leave at once), the held-out sums, then the stop rule,
+// which also advances the sweep counters of the problems still running.
 ntc_status enqueue_sweep(ntc_pool *pool)
 {
     for (const PoolLaunch &pl : pool->launches)
         POOL_HIP(ntc::launch_row_kernel(pl.kind, pl.kc, pl.L, pool->stream));
-    POOL_HIP(ntc::launch_advance_many(pool->adv, pool->n_adv, pool->stream));
     POOL_HIP(ntc::launch_test_sums(pool->t_args, pool->t_start, pool->t_owner, pool->n_t, pool->t_blocks,
                                    pool->t_part, pool->t_out, pool->stream));
+    POOL_HIP(ntc::launch_pool_rule(pool->rule, pool->stream));
     return NTC_OK;
 }
 
@@ -390,19 +424,6 @@ ntc_status capture(ntc_pool *pool)
     pool->graph = g;
     POOL_HIP(hipGraphInstantiate(&pool->exec, pool->graph, nullptr, nullptr, 0));
     return NTC_OK;
-}
-
-// Stop rule after a sweep (window W, tolerance tol, cap max_sweeps).
-bool should_stop(const ntc_pool *pool, const Slot &s)
-{
-    if (s.sweeps >= pool->p.max_sweeps)
-        return true;
-    const int64_t W = pool->p.window;
-    const int64_t k = static_cast<int64_t>(s.rmse.size()) - 1;  // rmse[k] is after k sweeps
-    if (W <= 0 || k < W)
-        return false;
-    const double now = s.rmse[k], then = s.rmse[k - W];
-    return !(then - now >= pool->p.tol * now);
 }
 
 }  // namespace
@@ -471,9 +492,15 @@ ntc_status ntc_pool_create(ntc_pool_handle *out, const ntc_pool_params *p)
     }
     pool->arena.reset(pool->arena_mem, cap);
     const size_t ms = static_cast<size_t>(q.max_slots);
+    const size_t W1 = static_cast<size_t>(q.window) + 1;
     if (hipMalloc(reinterpret_cast<void **>(&pool->t_part), ms * 64 * 2 * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&pool->t_out), ms * 2 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&pool->t_host), ms * 2 * sizeof(double), 0) != hipSuccess) {
+        hipMalloc(reinterpret_cast<void **>(&pool->st_stop), ms * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&pool->st_sweeps), ms * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&pool->st_nhist), ms * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&pool->st_hist), ms * W1 * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&pool->st_last), ms * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&pool->st_host), ms * (4 + 8 + 8), 0) != hipSuccess) {
         (void)hipGetLastError();
         delete pool;
         return fail(NTC_ENOMEM, "pool buffers");
@@ -526,8 +553,26 @@ ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *d
         s = Slot{};
         return st;
     }
-    if (s.view.n_test > 0)
-        s.rmse.push_back(loss[2]);
+    s.rmse = s.view.n_test > 0 ? loss[2] : std::numeric_limits<double>::quiet_NaN();
+    {
+        const int32_t zero = 0;
+        const int64_t zero64 = 0, nh = s.view.n_test > 0 ? 1 : 0;
+        hipError_t e = hipMemcpy(pool->st_stop + free_slot, &zero, sizeof(zero), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pool->st_sweeps + free_slot, &zero64, sizeof(zero64), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pool->st_nhist + free_slot, &nh, sizeof(nh), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pool->st_hist + static_cast<size_t>(free_slot) * (pool->p.window + 1), &s.rmse,
+                          sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pool->st_last + free_slot, &s.rmse, sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)ntc_release(h);
+            s = Slot{};
+            return fail(NTC_EDEVICE, std::string("pool state upload failed: ") + hipGetErrorString(e));
+        }
+    }
     s.state = NTC_SLOT_RUNNING;
     pool->dirty = true;
     *slot = free_slot;
@@ -540,11 +585,15 @@ ntc_status ntc_pool_step(ntc_pool_handle pool, int32_t nsweeps)
         return fail(NTC_EINVAL, "null pool");
     if (nsweeps < 0)
         return fail(NTC_EINVAL, "nsweeps must be >= 0");
+    if (nsweeps == 0)
+        return NTC_OK;
+    if (pool->dirty)
+        POOL_TRY(rebuild(pool));
+    if (pool->n_run == 0)
+        return NTC_OK;  // nothing running
+    // the sweeps run back to back; the stop rule is applied on the device
+    // after every sweep, and a stopped problem's kernels leave at once
     for (int32_t it = 0; it < nsweeps; ++it) {
-        if (pool->dirty)
-            POOL_TRY(rebuild(pool));
-        if (pool->n_adv == 0)
-            return NTC_OK;  // nothing running
         if (pool->p.use_graph) {
             if (!pool->exec)
                 POOL_TRY(capture(pool));
@@ -552,28 +601,27 @@ ntc_status ntc_pool_step(ntc_pool_handle pool, int32_t nsweeps)
         } else {
             POOL_TRY(enqueue_sweep(pool));
         }
-        if (pool->n_t > 0)
-            POOL_HIP(hipMemcpyAsync(pool->t_host, pool->t_out, 2 * sizeof(double) * pool->n_t,
-                                    hipMemcpyDeviceToHost, pool->stream));
-        POOL_HIP(hipStreamSynchronize(pool->stream));
-        pool->sweeps += 1;
-        std::vector<double> rm(pool->slots.size(), std::numeric_limits<double>::quiet_NaN());
-        for (int32_t j = 0; j < pool->n_t; ++j) {
-            const int32_t i = pool->t_slot[j];
-            rm[i] = std::sqrt(pool->t_host[2 * j] / static_cast<double>(pool->slots[i].view.n_test));
-        }
-        for (int32_t i = 0; i < static_cast<int32_t>(pool->slots.size()); ++i) {
-            Slot &s = pool->slots[i];
-            if (s.state != NTC_SLOT_RUNNING)
-                continue;
-            s.sweeps += 1;
-            ntc::note_sweeps(s.h, 1);
-            if (s.view.n_test > 0)
-                s.rmse.push_back(rm[i]);
-            if (should_stop(pool, s)) {
-                s.state = NTC_SLOT_STOPPED;
-                pool->dirty = true;
-            }
+    }
+    const size_t ms = pool->slots.size();
+    int64_t *h_sweeps = reinterpret_cast<int64_t *>(pool->st_host);
+    double *h_last = reinterpret_cast<double *>(pool->st_host + ms * 8);
+    int32_t *h_stop = reinterpret_cast<int32_t *>(pool->st_host + ms * 16);
+    POOL_HIP(hipMemcpyAsync(h_stop, pool->st_stop, ms * 4, hipMemcpyDeviceToHost, pool->stream));
+    POOL_HIP(hipMemcpyAsync(h_sweeps, pool->st_sweeps, ms * 8, hipMemcpyDeviceToHost, pool->stream));
+    POOL_HIP(hipMemcpyAsync(h_last, pool->st_last, ms * 8, hipMemcpyDeviceToHost, pool->stream));
+    POOL_HIP(hipStreamSynchronize(pool->stream));
+    pool->sweeps += nsweeps;
+    for (size_t i = 0; i < ms; ++i) {
+        Slot &s = pool->slots[i];
+        if (s.state != NTC_SLOT_RUNNING)
+            continue;
+        ntc::note_sweeps(s.h, h_sweeps[i] - s.sweeps);
+        s.sweeps = h_sweeps[i];
+        if (s.view.n_test > 0)
+            s.rmse = h_last[i];
+        if (h_stop[i] != 0) {
+            s.state = NTC_SLOT_STOPPED;
+            pool->dirty = true;
         }
     }
     return NTC_OK;
@@ -588,7 +636,7 @@ ntc_status ntc_pool_query(ntc_pool_handle pool, int32_t slot, int32_t *state, in
     if (sweeps)
         *sweeps = s.sweeps;
     if (test_rmse)
-        *test_rmse = s.rmse.empty() ? std::numeric_limits<double>::quiet_NaN() : s.rmse.back();
+        *test_rmse = s.h ? s.rmse : std::numeric_limits<double>::quiet_NaN();
     return NTC_OK;
 }
 

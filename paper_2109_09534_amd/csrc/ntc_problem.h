@@ -22,7 +22,7 @@ struct ProblemView {
     int32_t max_inner;
     const RowArgs *args_host;      // [nmodes * max_inner]: row-kernel arguments of (mode, inner step)
     int64_t *kdev;                 // device sweep counter read by the row kernels
-    int32_t blocks[kMaxModes][4];  // grid blocks per mode and RowKernel kind
+    int32_t blocks[kMaxModes][kRowKernels];  // grid blocks per mode and RowKernel kind
     const float *U[kMaxModes];     // device factors
     int64_t n_test;                // held-out set on the device
     const int32_t *test_coords;

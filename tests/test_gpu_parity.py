@@ -102,6 +102,9 @@ CASES = {
     "r32_inner2_power3": lambda: (synth.make_problem((200, 150, 80), 100_000, 16, seed=12), 32,
                                   dict(c=0.3, max_inner=2, power_iters=3)),
     "r20_matrix": lambda: (synth.make_problem((500, 400), 60_000, 8, seed=13), 20, dict(c=0.2)),
+    # rows split into more than 64 items: partial slots summed in groups first
+    "r24_slot_groups": lambda: (synth.make_problem((60, 50, 40), 70_000, 8, seed=14, zipf_s=1.1), 24,
+                                dict(c=0.8, schedule={"item_samples": 16})),
 }
 
 

@@ -106,8 +106,9 @@ def test_stop_rule_and_slot_reuse():
     with ntc.Pool(arena_bytes=1 << 30, max_slots=4, window=W, tol=tol, max_sweeps=400) as pool:
         s = pool.admit(p.dims, p.coords, p.values, R, c=0.5, test_coords=p.test_coords,
                        test_values=p.test_values, seed=3)
-        for _ in range(500):
-            pool.step(1)
+        # several sweeps per step: the device applies the rule after each one
+        for _ in range(100):
+            pool.step(7)
             if pool.query(s)[0] == ntc.SLOT_STOPPED:
                 break
         st, stop_at, _ = pool.query(s)
@@ -123,9 +124,13 @@ def test_stop_rule_and_slot_reuse():
             if k >= W and not (hist[k - W] - hist[k] >= tol * hist[k]):
                 rule_at = k
                 break
+        solo = g.all_factors()
         g.close()
         _say(f"  pool stopped after {stop_at} sweeps; the rule on the solo history fires at {rule_at}")
         assert rule_at == stop_at
+        # frozen at the stop sweep although the step ran past it
+        for m in range(3):
+            assert np.array_equal(pool.factors(s, m), solo[m])
         # the stopped problem no longer advances
         pool.step(2)
         assert pool.query(s)[1] == stop_at

@@ -71,7 +71,7 @@ def load_traffic(name: str):
     except (OSError, ValueError):
         return None
     from paper_2109_09534_amd.profiling import source_hash
-    if d.get("kernel_source_hash") != source_hash():
+    if d.get("kernel_source_hash") != source_hash(bool(d.get("wide"))):
         return None
     return d
 

@@ -26,7 +26,7 @@ struct LossArgs {
     double *out;                  // [4]
 };
 
-constexpr int kLossBlocks = 512;
+constexpr int kLossBlocks = 2048;  // 32 waves per CU: enough loads in flight
 constexpr int kLossThreads = 256;
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s);

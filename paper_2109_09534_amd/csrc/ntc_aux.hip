@@ -28,18 +28,12 @@ __device__ __forceinline__ double block_sum(double v, double *s)
 }
 
 // Prediction sum_r prod_m U_m[i_m, r] in FP64 from row offsets off[m] = i_m * R.
-// Prediction sum_r prod_m U_m[i_m, r] in FP64 from row offsets off[m] = i_m * R.
-// LPE lanes share one entry: lane `sub` takes columns 4 sub .. 4 sub + 3
-// (R % 4 == 0, one float4 per mode, so a row is read by adjacent lanes),
-// then the lanes' partial sums are combined by a butterfly; LPE == 1 is the
-// scalar form for any R.  Every lane of the entry returns the same value.
-template <int LPE>
-__device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t *off, int nm, int R, int sub)
+template <bool VEC4>
+__device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t *off, int nm, int R)
 {
     double pred = 0.0;
-    if (LPE > 1) {
-        const int r = 4 * sub;
-        if (r < R) {
+    if (VEC4) {
+        for (int r = 0; r < R; r += 4) {
             double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
             for (int m = 0; m < nm; ++m) {
                 const float4 u = *reinterpret_cast<const float4 *>(a.U[m] + off[m] + r);
@@ -48,11 +42,11 @@ __device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t 
                 p2 *= static_cast<double>(u.z);
                 p3 *= static_cast<double>(u.w);
             }
-            pred = (p0 + p1) + (p2 + p3);
+            pred += p0;
+            pred += p1;
+            pred += p2;
+            pred += p3;
         }
-#pragma unroll
-        for (int w = 1; w < LPE; w <<= 1)
-            pred += __shfl_xor(pred, w, 64);
     } else {
         for (int r = 0; r < R; ++r) {
             double prod = 1.0;
@@ -66,59 +60,43 @@ __device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t 
 
 // Training entries are walked in mode-0 CSR order; each record carries the
 // other coordinates (times R) and the row (times R, in a spare record word or
-// a side array), so an entry needs no search.  Fixed grid and per-lane
+// a side array), so an entry needs no search.  Fixed grid and per-thread
 // order: the sums are deterministic.
-template <int LPE>
+template <bool VEC4>
 __global__ __launch_bounds__(kLossThreads) void k_loss_partials(const LossArgs a)
 {
     __shared__ double s[kLossThreads];
     const int R = a.R;
     const int nm = a.nmodes;
-    const int sub = threadIdx.x % LPE;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * (blockDim.x / LPE);
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * (blockDim.x / LPE) + threadIdx.x / LPE;
-    // every lane of a wave runs the same number of iterations (the butterfly
-    // needs all LPE lanes of an entry); entries past the end contribute 0
-    const int64_t iters_tr = (a.nnz + stride - 1) / stride;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     double sse = 0.0;
-    for (int64_t it = 0; it < iters_tr; ++it) {
-        const int64_t e = first + it * stride;
-        const bool live = e < a.nnz;
-        const int64_t ee = live ? e : 0;
-        const uint32_t *rec = a.records0 + ee * a.rec_words;
+    for (int64_t e = tid; e < a.nnz; e += stride) {
+        const uint32_t *rec = a.records0 + e * a.rec_words;
         uint32_t off[kMaxModes];
-        off[0] = a.row0 ? a.row0[ee] : rec[a.row_word];
+        off[0] = a.row0 ? a.row0[e] : rec[a.row_word];
         for (int m = 1; m < nm; ++m)
             off[m] = rec[m - 1];
-        const double pred = cpd_predict<LPE>(a, off, nm, R, sub);
+        const double pred = cpd_predict<VEC4>(a, off, nm, R);
         const double res = static_cast<double>(__uint_as_float(rec[nm - 1])) - pred;
-        if (live && sub == 0)
-            sse += res * res;
+        sse += res * res;
     }
     double tse = 0.0, tsx = 0.0;
-    const int64_t iters_te = (a.n_test + stride - 1) / stride;
-    for (int64_t it = 0; it < iters_te; ++it) {
-        const int64_t e = first + it * stride;
-        const bool live = e < a.n_test;
-        const int64_t ee = live ? e : 0;
-        const int32_t *cc = a.test_coords + ee * nm;
+    for (int64_t e = tid; e < a.n_test; e += stride) {
+        const int32_t *cc = a.test_coords + e * nm;
         uint32_t off[kMaxModes];
         for (int m = 0; m < nm; ++m)
             off[m] = static_cast<uint32_t>(cc[m]) * static_cast<uint32_t>(R);
-        const double pred = cpd_predict<LPE>(a, off, nm, R, sub);
-        const double x = static_cast<double>(a.test_values[ee]);
+        const double pred = cpd_predict<VEC4>(a, off, nm, R);
+        const double x = static_cast<double>(a.test_values[e]);
         const double res = x - pred;
-        if (live && sub == 0) {
-            tse += res * res;
-            tsx += x * x;
-        }
+        tse += res * res;
+        tsx += x * x;
     }
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t tstride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     double reg = 0.0;
     for (int m = 0; m < nm; ++m) {
         const int64_t cntm = a.dims[m] * R;
-        for (int64_t t = tid; t < cntm; t += tstride) {
+        for (int64_t t = tid; t < cntm; t += stride) {
             const double u = static_cast<double>(a.U[m][t]);
             reg += u * u;
         }
@@ -287,18 +265,10 @@ __global__ void k_advance_many(int64_t *const *__restrict__ k, int32_t n)
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s)
 {
-    // lanes per entry: one float4 of every factor row per lane
-    const int lpe = (a.R % 4 != 0) ? 1 : a.R <= 8 ? 2 : a.R <= 16 ? 4 : a.R <= 32 ? 8 : 16;
-    if (lpe == 16)
-        hipLaunchKernelGGL(k_loss_partials<16>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
-    else if (lpe == 8)
-        hipLaunchKernelGGL(k_loss_partials<8>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
-    else if (lpe == 4)
-        hipLaunchKernelGGL(k_loss_partials<4>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
-    else if (lpe == 2)
-        hipLaunchKernelGGL(k_loss_partials<2>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+    if (a.R % 4 == 0)
+        hipLaunchKernelGGL(k_loss_partials<true>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_loss_partials<1>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+        hipLaunchKernelGGL(k_loss_partials<false>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, a);
     return hipGetLastError();
 }

@@ -1,0 +1,96 @@
+// Device helpers shared by the row kernels of libntc (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ntc_internal.h"
+
+namespace ntc {
+namespace {
+
+// Every row kernel runs one launch over one or many problems (a Launch):
+// block b belongs to entry owner[b] (entry 0 when there is one entry) and is
+// that entry's local block b - start[entry]; a problem of a pool that has
+// stopped leaves at once.  The entry's RowArgs are read
+// through the constant address space: they never change during a launch, so
+// every field is a scalar load that the compiler may repeat at any point
+// instead of holding it in registers.
+typedef const __attribute__((address_space(4))) RowArgs CRowArgs;
+#define NTC_ROW_PARAMS                                                                                       \
+    const RowArgs *__restrict__ args_, const int32_t *__restrict__ start_, const int32_t *__restrict__ owner_, \
+        const int32_t nent_
+#define NTC_ROW_RESOLVE(a, blk)                              \
+    int blk = static_cast<int>(blockIdx.x);                  \
+    int ent_ = 0;                                            \
+    if (nent_ > 1) {                                         \
+        ent_ = owner_[blockIdx.x];                           \
+        blk -= start_[ent_];                                 \
+    }                                                        \
+    CRowArgs &a = ((CRowArgs *)args_)[ent_];                 \
+    if (a.stop != nullptr && *a.stop != 0)                   \
+        return
+
+template <int W>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// DPP controls (gfx9): quad permutations, half-row and row mirrors, row rotations.
+constexpr int kDppXor1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+constexpr int kDppRor = 0x120;       // + s: row_ror:s
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 16 lanes of a DPP row: quad butterflies, then two row
+// rotations (every lane gets the sum; lanes may differ in the last bit).
+__device__ __forceinline__ float row_sum_f32(float x)
+{
+    x += dpp_f32<kDppXor1>(x);
+    x += dpp_f32<kDppXor2>(x);
+    x += dpp_f32<kDppRor + 4>(x);
+    x += dpp_f32<kDppRor + 8>(x);
+    return x;
+}
+
+__device__ __forceinline__ double row_sum_f64(double x)
+{
+    x += dpp_f64<kDppXor1>(x);
+    x += dpp_f64<kDppXor2>(x);
+    x += dpp_f64<kDppHalfMirror>(x);
+    x += dpp_f64<kDppMirror>(x);
+    return x;
+}
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+}  // namespace
+}  // namespace ntc

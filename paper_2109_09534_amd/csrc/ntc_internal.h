@@ -121,6 +121,8 @@ constexpr int kRowKernels = 5;
 int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items, int32_t n_group, int32_t n_split,
                           int32_t n_tiny, int32_t n_groups);
 hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s);
+// the R > 16 kernels (called by launch_row_kernel)
+hipError_t launch_row_kernel_wide(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s);
 // k[t] += 1 for t < n (the sweep counters, once per sweep)
 hipError_t launch_advance(int64_t *k, int32_t n, hipStream_t s);
 

@@ -1,0 +1,640 @@
+// Row kernels of libntc for 16 < R <= 64 on gfx950 (wave64).
+//
+// R > 32, or N > 4: one 64-lane workgroup per work item.  The wave is split
+// into G = 64/RP groups of RP lanes; lane r of a group owns column r of the
+// rank dimension.  A batch of up to 64 samples is mapped one sample per lane
+// for the sampler and the record fetch (one 16/32-byte record per lane),
+// staged in LDS, then consumed G samples at a time: every group gathers its
+// sample's N-1 factor rows (one contiguous 4R-byte segment per mode, or 2R
+// bytes from the BF16 shadow), forms the Khatri-Rao row k (Hadamard product,
+// increasing mode order), reduces k.y with shuffles inside the group, and
+// accumulates g += (k.y - x) k in FP32 and the row Hessian H += k k^T in
+// FP64.  Groups are combined at the end of the item; a whole-row item then
+// runs the FP64 power method for L_p and the fused step/projection/
+// extrapolation; a split item writes its partial (g, H) and the finalize
+// kernel combines the partials in slot order.
+#include <hip/hip_runtime.h>
+
+#include "ntc_bf16.h"
+#include "ntc_dev.h"
+#include "ntc_internal.h"
+#include "ntc_rng.h"
+
+namespace ntc {
+namespace {
+
+// Power method, step, projection and extrapolation for one row (Alg. 1,
+// L_p, A_{l+1}, beta, Y_{l+1}).  Called by all 64 lanes; lanes r < RP of the
+// first group hold g[r] (sampled gradient without ridge) and row r of the
+// sampled H (without ridge); all other lanes pass zeros.
+template <int RP, bool BF16, class Args>
+__device__ void finish_row(const Args &a, int row, int lane, double g, double (&h)[RP], float y, double *s_v)
+{
+    const int R = a.R;
+    const bool live = lane < RP && lane < R;
+    if (live) {
+        g += a.lambda * static_cast<double>(y);
+#pragma unroll
+        for (int q = 0; q < RP; ++q)
+            if (q == lane)
+                h[q] += a.lambda;  // static register index; diagonal of row `lane`
+    }
+    double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
+    bool vanished = false;
+    for (int t = 0; t < a.power_iters; ++t) {
+        if (lane < RP)
+            s_v[lane] = v;
+        __syncthreads();
+        double w = 0.0;
+        if (lane < RP) {
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                w += h[q] * s_v[q];
+        }
+        __syncthreads();
+        const double n2 = wave_sum(w * w);
+        if (!(n2 > 0.0)) {
+            vanished = true;
+            break;
+        }
+        v = w / sqrt(n2);
+    }
+    double L = 0.0;
+    if (!vanished) {
+        if (lane < RP)
+            s_v[lane] = v;
+        __syncthreads();
+        double w = 0.0;
+        if (lane < RP) {
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                w += h[q] * s_v[q];
+        }
+        __syncthreads();
+        L = wave_sum(v * w);
+    }
+    if (!live)
+        return;
+    const int64_t off = static_cast<int64_t>(row) * R + lane;
+    const float a_prev = (a.l == 0) ? y : a.A[off];
+    const bool more = a.l + 1 < a.max_inner;
+    if (L > 0.0) {
+        double an = static_cast<double>(y) - g / L;
+        an = an > 0.0 ? an : 0.0;
+        const double sl = sqrt(L), sm = sqrt(a.lambda);
+        const double beta = (sl - sm) / (sl + sm);
+        const float af = static_cast<float>(an);
+        a.A[off] = af;
+        if (BF16)
+            a.A16[off] = f32_to_bf16(af);
+        if (more)
+            a.Y[off] = static_cast<float>(an + beta * (an - static_cast<double>(a_prev)));
+    } else if (more && a.l == 0) {
+        a.Y[off] = y;  // row skipped: Y_1 = Y_0
+    }
+}
+
+template <int RP, int NM, bool BF16>
+__global__ __launch_bounds__(64) void k_row_items(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    constexpr int G = 64 / RP;
+    constexpr int RED = (G > 1) ? 64 * RP : 1;
+    __shared__ uint32_t s_rec[64 * 8];
+    __shared__ float s_k[64];
+    __shared__ double s_red[RED];
+    __shared__ double s_v[RP];
+    __shared__ double s_g[64];
+
+    const int nm = (NM > 0) ? NM : a.nmodes;
+    const int rw = (NM > 0) ? ((NM <= 4) ? 4 : 8) : a.rec_words;
+    const Item it = a.items[blk_];
+    const int lane = threadIdx.x;
+    const int r = lane % RP;
+    const int grp = lane / RP;
+    const int R = a.R;
+    const bool rlive = r < R;
+
+    const int64_t base = a.rowptr[it.row];
+    const int64_t n = a.rowptr[it.row + 1] - base;
+    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, it.row));
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const float y = rlive ? ysrc[static_cast<int64_t>(it.row) * R + r] : 0.0f;
+
+    float gacc = 0.0f;
+    double h[RP];
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+        h[q] = 0.0;
+
+    for (int jb = it.j0; jb < it.j1; jb += 64) {
+        const int cnt = min(64, it.j1 - jb);
+        if (lane < cnt) {
+            const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.records + (base + q) * rw);
+            const uint4 w0 = src[0];
+            s_rec[lane * 8 + 0] = w0.x;
+            s_rec[lane * 8 + 1] = w0.y;
+            s_rec[lane * 8 + 2] = w0.z;
+            s_rec[lane * 8 + 3] = w0.w;
+            if (rw == 8) {
+                const uint4 w1 = src[1];
+                s_rec[lane * 8 + 4] = w1.x;
+                s_rec[lane * 8 + 5] = w1.y;
+                s_rec[lane * 8 + 6] = w1.z;
+                s_rec[lane * 8 + 7] = w1.w;
+            }
+        }
+        __syncthreads();
+        for (int t0 = 0; t0 < cnt; t0 += G) {
+            const int t = t0 + grp;
+            const bool valid = t < cnt;
+            float kv = 0.0f, x = 0.0f;
+            if (valid) {
+                kv = rlive ? 1.0f : 0.0f;
+                for (int mm = 0; mm < nm - 1; ++mm) {
+                    const int64_t off = s_rec[t * 8 + mm];  // coordinate * R
+                    float f = 0.0f;
+                    if (rlive) {
+                        if (BF16)
+                            f = bf16_to_f32(a.gath16[mm][off + r]);
+                        else
+                            f = a.gath[mm][off + r];
+                    }
+                    kv *= f;
+                }
+                x = __uint_as_float(s_rec[t * 8 + nm - 1]);
+            }
+            const float pred = group_sum<RP>(kv * y);
+            const float res = valid ? pred - x : 0.0f;
+            gacc = fmaf(res, kv, gacc);
+            s_k[lane] = kv;
+            __syncthreads();
+            const double kd = static_cast<double>(kv);
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                h[q] = fma(kd, static_cast<double>(s_k[grp * RP + q]), h[q]);
+            __syncthreads();
+        }
+    }
+
+    // combine the groups into the first group
+    double g = static_cast<double>(gacc);
+    if (G > 1) {
+        s_g[lane] = g;
+#pragma unroll
+        for (int q = 0; q < RP; ++q)
+            s_red[lane * RP + q] = h[q];
+        __syncthreads();
+        if (grp == 0) {
+            for (int gg = 1; gg < G; ++gg) {
+                g += s_g[gg * RP + r];
+#pragma unroll
+                for (int q = 0; q < RP; ++q)
+                    h[q] += s_red[(gg * RP + r) * RP + q];
+            }
+        } else {
+            g = 0.0;
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                h[q] = 0.0;
+        }
+        __syncthreads();
+    }
+
+    if (it.slot >= 0) {
+        if (lane < RP) {
+            double *P = a.partials + static_cast<int64_t>(it.slot) * (RP + RP * RP);
+            P[lane] = g;
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                P[RP + lane * RP + q] = h[q];
+        }
+        return;
+    }
+    finish_row<RP, BF16>(a, it.row, lane, g, h, y, s_v);
+}
+
+template <int RP, bool BF16>
+__global__ __launch_bounds__(64) void k_row_finalize(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    __shared__ double s_v[RP];
+    const SplitRow sr = a.split[blk_];
+    const int lane = threadIdx.x;
+    const int R = a.R;
+    double g = 0.0;
+    double h[RP];
+#pragma unroll
+    for (int q = 0; q < RP; ++q)
+        h[q] = 0.0;
+    float y = 0.0f;
+    if (lane < RP) {
+        for (int s = 0; s < sr.nslots; ++s) {
+            const double *P = a.partials + static_cast<int64_t>(sr.slot0 + s) * (RP + RP * RP);
+            g += P[lane];
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                h[q] += P[RP + lane * RP + q];
+        }
+        if (lane < R) {
+            const float *ysrc = (a.l == 0) ? a.A : a.Y;
+            y = ysrc[static_cast<int64_t>(sr.row) * R + lane];
+        }
+    }
+    finish_row<RP, BF16>(a, sr.row, lane, g, h, y, s_v);
+}
+
+// ------------------------------------------------- wave-per-item (R <= 32)
+//
+// 17 <= R <= 32, N <= 4: one wave per work item, split into four 16-lane
+// groups; lane j of a group owns columns 2j and 2j + 1.  The item's samples
+// are taken 64 at a time (sampler and record fetch one per lane, staged in
+// LDS) and consumed four per step, one per group: each group gathers its
+// sample's N-1 factor rows (one 8-byte pair per lane: 128 contiguous bytes
+// per mode, or 64 from the BF16 shadow), forms the Khatri-Rao row k, reduces
+// k.y over its 16 lanes with DPP and accumulates g += (k.y - x) k in FP32.
+// With the columns ordered evens first, H has three distinct 16x16 blocks
+// (even-even, even-odd, odd-odd); one v_mfma_f32_16x16x4f32 per block and
+// step adds the four groups' rank-1 updates (K = the four groups) in FP32,
+// added into FP64 after every 32 samples.
+
+// Sum over the 32 lanes of a group (every lane of the group gets it).
+__device__ __forceinline__ float group32_sum_f32(float x)
+{
+    x += dpp_f32<kDppXor1>(x);
+    x += dpp_f32<kDppXor2>(x);
+    x += dpp_f32<kDppRor + 4>(x);
+    x += dpp_f32<kDppRor + 8>(x);
+    return x + __shfl_xor(x, 16, 64);
+}
+
+__device__ __forceinline__ double group32_sum_f64(double x)
+{
+    x += dpp_f64<kDppXor1>(x);
+    x += dpp_f64<kDppXor2>(x);
+    x += dpp_f64<kDppHalfMirror>(x);
+    x += dpp_f64<kDppMirror>(x);
+    return x + __shfl_xor(x, 16, 64);
+}
+
+constexpr int kSlot32 = 32 + 32 * 32;  // doubles per partial slot: g[32], row-major H[32][32]
+
+// Accumulator register v of lane l of v_mfma_f32_32x32x2f32 holds
+// H[(v % 4) + 8 (v / 4) + 4 (l / 32)][l % 32].
+__device__ __forceinline__ int mfma32_row(int v, int l)
+{
+    return (v & 3) + 8 * (v >> 2) + 4 * (l >> 5);
+}
+
+// Power method, step, projection and extrapolation for a row held by the
+// whole wave, with H in any symmetric ordering of the columns.  Lane l:
+// i = l % 32, half = l / 32 holds hd[q] = H[i][16 half + q] of the sampled
+// Hessian (without ridge) in that ordering; index i stands for column `col`
+// of the factor; g: sampled gradient of that column (without ridge), y its
+// Y value, on every lane.
+template <bool BF16, class Args>
+__device__ void finish_row32(const Args &a, int row, int lane, int col, double g, double (&hd)[16], float y,
+                             double *s_v)
+{
+    const int R = a.R;
+    const int i = lane & 31, half = lane >> 5;
+    const bool live = col < R;
+    if (live) {
+        g += a.lambda * static_cast<double>(y);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (16 * half + q == i)
+                hd[q] += a.lambda;
+    }
+    double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
+    // w_i = (H v)_i: each half sums its 16 columns, then the halves combine
+    auto matvec = [&](double vi) {
+        if (half == 0)
+            s_v[i] = vi;
+        __builtin_amdgcn_wave_barrier();
+        double w4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            w4[q & 3] = fma(hd[q], s_v[16 * half + q], w4[q & 3]);
+        __builtin_amdgcn_wave_barrier();
+        const double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
+        return w + __shfl_xor(w, 32, 64);
+    };
+    bool vanished = false;
+    for (int t = 0; t < a.power_iters; ++t) {
+        const double w = matvec(v);
+        const double n2 = group32_sum_f64(w * w);
+        if (!(n2 > 0.0)) {
+            vanished = true;
+            break;
+        }
+        v = w / sqrt(n2);
+    }
+    double L = 0.0;
+    if (!vanished)
+        L = group32_sum_f64(v * matvec(v));
+    if (!live || half != 0)
+        return;
+    const int64_t off = static_cast<int64_t>(row) * R + col;
+    const float a_prev = (a.l == 0) ? y : a.A[off];
+    const bool more = a.l + 1 < a.max_inner;
+    if (L > 0.0) {
+        double an = static_cast<double>(y) - g / L;
+        an = an > 0.0 ? an : 0.0;
+        const double sl = sqrt(L), sm = sqrt(a.lambda);
+        const double beta = (sl - sm) / (sl + sm);
+        const float af = static_cast<float>(an);
+        a.A[off] = af;
+        if (BF16)
+            a.A16[off] = f32_to_bf16(af);
+        if (more)
+            a.Y[off] = static_cast<float>(an + beta * (an - static_cast<double>(a_prev)));
+    } else if (more && a.l == 0) {
+        a.Y[off] = y;  // row skipped: Y_1 = Y_0
+    }
+}
+
+template <int NM, bool BF16>
+__global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    __shared__ uint4 s_rec[64];
+    __shared__ double s_h[12 * 64];  // FP64 sums of the EE, EO, OO blocks: register v of lane l at v*64 + l
+    __shared__ double s_g[2 * 64];
+    __shared__ double s_v[32];
+    const Item it = a.items[blk_];
+    const int lane = threadIdx.x;
+    const int j = lane & 15;    // columns 2j (even) and 2j + 1 (odd)
+    const int grp = lane >> 4;  // which of the step's four samples
+    const int R = a.R;
+    const int c0 = 2 * j, c1 = 2 * j + 1;
+    const bool l0 = c0 < R, l1 = c1 < R;
+    const bool pairs = (R & 1) == 0;  // every row starts 8 bytes (FP32) / 4 bytes (BF16) aligned
+
+    const int64_t base = a.rowptr[it.row];
+    const int64_t n = a.rowptr[it.row + 1] - base;
+    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, it.row));
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const int64_t roff = static_cast<int64_t>(it.row) * R;
+    const float y0 = l0 ? ysrc[roff + c0] : 0.0f;
+    const float y1 = l1 ? ysrc[roff + c1] : 0.0f;
+    const uint4 zero_rec = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+#pragma unroll
+    for (int v = 0; v < 12; ++v)
+        s_h[v * 64 + lane] = 0.0;
+    // columns past R read columns 0 and 1 of the same row (never past its
+    // end: the zero row is the last row of the table) and are masked afterwards
+    const uint32_t e0 = l0 ? c0 : 0, e1 = l1 ? c1 : 1;
+    const uint32_t pc = l0 ? c0 : 0;  // pair offset (R even: c0 < R implies c0 + 1 < R)
+
+    float gf0 = 0.0f, gf1 = 0.0f;
+    for (int jb = it.j0; jb < it.j1; jb += 64) {
+        const int cnt = min(64, it.j1 - jb);
+        uint4 w0 = zero_rec;
+        if (lane < cnt) {
+            const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
+            w0 = *reinterpret_cast<const uint4 *>(a.records + (base + q) * 4);
+        }
+        __builtin_amdgcn_wave_barrier();  // the previous batch's reads of s_rec are done
+        s_rec[lane] = w0;
+        __builtin_amdgcn_wave_barrier();
+        const int steps = (cnt + 3) >> 2;
+        for (int h0 = 0; h0 < steps; h0 += 8) {
+            const int hs = min(8, steps - h0);
+            // all gathers of up to 8 steps first (a missing sample reads the zero rows)
+            float f0[NM - 1][8], f1[NM - 1][8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < hs) {
+                    const uint4 rec = s_rec[4 * (h0 + t) + grp];
+                    const uint32_t rw[3] = {rec.x, rec.y, rec.z};
+#pragma unroll
+                    for (int mm = 0; mm < NM - 1; ++mm) {
+                        if (BF16) {
+                            const uint16_t *src = a.gath16[mm] + rw[mm];
+                            if (pairs) {
+                                const uint32_t w = *reinterpret_cast<const uint32_t *>(src + pc);
+                                f0[mm][t] = __uint_as_float(w << 16);
+                                f1[mm][t] = __uint_as_float(w & 0xFFFF0000u);
+                            } else {
+                                f0[mm][t] = bf16_to_f32(src[e0]);
+                                f1[mm][t] = bf16_to_f32(src[e1]);
+                            }
+                        } else {
+                            const float *src = a.gath[mm] + rw[mm];
+                            if (pairs) {
+                                const float2 w = *reinterpret_cast<const float2 *>(src + pc);
+                                f0[mm][t] = w.x;
+                                f1[mm][t] = w.y;
+                            } else {
+                                f0[mm][t] = src[e0];
+                                f1[mm][t] = src[e1];
+                            }
+                        }
+                    }
+                }
+            }
+            f32x4 ee = {0.0f}, eo = {0.0f}, oo = {0.0f};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < hs) {  // wave-uniform
+                    float k0 = f0[0][t], k1 = f1[0][t];
+#pragma unroll
+                    for (int mm = 1; mm < NM - 1; ++mm) {
+                        k0 *= f0[mm][t];
+                        k1 *= f1[mm][t];
+                    }
+                    k0 = l0 ? k0 : 0.0f;
+                    k1 = l1 ? k1 : 0.0f;
+                    const uint4 rec = s_rec[4 * (h0 + t) + grp];
+                    const uint32_t xw[4] = {rec.x, rec.y, rec.z, rec.w};
+                    const float x = __uint_as_float(xw[NM - 1]);  // 0 for a missing sample
+                    const float pred = row_sum_f32(fmaf(k0, y0, k1 * y1));
+                    const float res = pred - x;
+                    gf0 = fmaf(res, k0, gf0);
+                    gf1 = fmaf(res, k1, gf1);
+                    // the four groups' samples: K = 4 of each 16x16 block of the column-permuted H
+                    ee = __builtin_amdgcn_mfma_f32_16x16x4f32(k0, k0, ee, 0, 0, 0);
+                    eo = __builtin_amdgcn_mfma_f32_16x16x4f32(k0, k1, eo, 0, 0, 0);
+                    oo = __builtin_amdgcn_mfma_f32_16x16x4f32(k1, k1, oo, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                s_h[v * 64 + lane] += static_cast<double>(ee[v]);
+                s_h[(4 + v) * 64 + lane] += static_cast<double>(eo[v]);
+                s_h[(8 + v) * 64 + lane] += static_cast<double>(oo[v]);
+            }
+        }
+    }
+    // gradient of columns 2j and 2j + 1: the four groups' partial sums in group order
+    s_g[lane] = static_cast<double>(gf0);
+    s_g[64 + lane] = static_cast<double>(gf1);
+    __builtin_amdgcn_wave_barrier();
+    // block entries: register v of lane l holds D[4 (l / 16) + v][l % 16]
+    auto blk = [&](int b, int r, int c) { return s_h[(4 * b + (r & 3)) * 64 + 16 * (r >> 2) + c]; };
+    auto gsum = [&](int c) {
+        const int par = c & 1, jj = c >> 1;
+        return ((s_g[64 * par + jj] + s_g[64 * par + 16 + jj]) + s_g[64 * par + 32 + jj]) + s_g[64 * par + 48 + jj];
+    };
+
+    if (it.slot >= 0) {
+        // partial slot in column order: H[2i][2c] = EE[i][c], H[2i][2c+1] = EO[i][c] = H[2c+1][2i],
+        // H[2i+1][2c+1] = OO[i][c]
+        double *P = a.partials + static_cast<int64_t>(it.slot) * kSlot32;
+        if (lane < 32)
+            P[lane] = gsum(lane);
+        const int cc = lane & 15;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = 4 * (lane >> 4) + v;
+            P[32 + (2 * ii) * 32 + 2 * cc] = s_h[v * 64 + lane];
+            P[32 + (2 * ii) * 32 + 2 * cc + 1] = s_h[(4 + v) * 64 + lane];
+            P[32 + (2 * cc + 1) * 32 + 2 * ii] = s_h[(4 + v) * 64 + lane];
+            P[32 + (2 * ii + 1) * 32 + 2 * cc + 1] = s_h[(8 + v) * 64 + lane];
+        }
+        return;
+    }
+    // the power method on the permuted order: index p < 16 is column 2p, p >= 16 is column 2(p-16)+1
+    const int i = lane & 31, half = lane >> 5;
+    const int col = i < 16 ? 2 * i : 2 * (i - 16) + 1;
+    double hd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        if (i < 16)
+            hd[q] = half == 0 ? blk(0, i, q) : blk(1, i, q);
+        else
+            hd[q] = half == 0 ? blk(1, q, i - 16) : blk(2, i - 16, q);
+    }
+    const double g = gsum(col);
+    const float y = col < R ? ysrc[roff + col] : 0.0f;
+    finish_row32<BF16>(a, it.row, lane, col, g, hd, y, s_v);
+}
+
+// Split rows with 17 <= R <= 32: a 256-thread block sums the row's partial
+// slots, thread t taking entries t, t + 256, ... of the slot in slot order
+// (coalesced, a fixed order per entry), then its first wave runs the power
+// method and step as above.
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_finalize32(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    __shared__ double s_p[kSlot32];
+    __shared__ double s_v[32];
+    const SplitRow sr = a.split[blk_];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kSlot32; e += 256) {
+        double acc = 0.0;
+        for (int q = 0; q < sr.nslots; ++q)
+            acc += a.partials[static_cast<int64_t>(sr.slot0 + q) * kSlot32 + e];
+        s_p[e] = acc;
+    }
+    __syncthreads();
+    if (tid >= 64)
+        return;
+    const int lane = tid;
+    const int i = lane & 31, half = lane >> 5;
+    const double g = s_p[i];
+    double hd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        hd[q] = s_p[32 + i * 32 + 16 * half + q];
+    float y = 0.0f;
+    if (i < a.R) {
+        const float *ysrc = (a.l == 0) ? a.A : a.Y;
+        y = ysrc[static_cast<int64_t>(sr.row) * a.R + i];
+    }
+    finish_row32<BF16>(a, sr.row, lane, i, g, hd, y, s_v);
+}
+
+// Second-level slot sums of rows split into many items: one 256-thread
+// block per group, thread t summing entries t, t + 256, ... over the group's
+// slots in slot order.
+template <int RP>
+__global__ __launch_bounds__(256) void k_reduce_slots(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    constexpr int S = RP + RP * RP;
+    const SlotGroup gr = a.groups[blk_];
+    for (int e = threadIdx.x; e < S; e += 256) {
+        double acc = 0.0;
+        for (int q = 0; q < gr.count; ++q)
+            acc += a.partials[static_cast<int64_t>(gr.src + q) * S + e];
+        a.partials[static_cast<int64_t>(gr.dst) * S + e] = acc;
+    }
+}
+
+#define NTC_GO(KERNEL, BLOCK) \
+    hipLaunchKernelGGL(KERNEL, dim3(L.blocks), dim3(BLOCK), 0, s, L.args, L.start, L.owner, L.n)
+
+template <bool BF16>
+hipError_t go_rows(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.rp == 32) {
+        if (kc.nmodes == 3)
+            NTC_GO((k_rows32<3, BF16>), 64);
+        else if (kc.nmodes == 4)
+            NTC_GO((k_rows32<4, BF16>), 64);
+        else if (kc.nmodes == 2)
+            NTC_GO((k_rows32<2, BF16>), 64);
+        else
+            NTC_GO((k_row_items<32, 0, BF16>), 64);
+    } else if (kc.rp == 64) {
+        if (kc.nmodes == 3)
+            NTC_GO((k_row_items<64, 3, BF16>), 64);
+        else if (kc.nmodes == 4)
+            NTC_GO((k_row_items<64, 4, BF16>), 64);
+        else
+            NTC_GO((k_row_items<64, 0, BF16>), 64);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <bool BF16>
+hipError_t go_finalize(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.rp == 32)
+        NTC_GO((k_finalize32<BF16>), 256);
+    else if (kc.rp == 64)
+        NTC_GO((k_row_finalize<64, BF16>), 64);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t go_reduce(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.rp == 32)
+        NTC_GO((k_reduce_slots<32>), 256);
+    else if (kc.rp == 64)
+        NTC_GO((k_reduce_slots<64>), 256);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+#undef NTC_GO
+
+}  // namespace
+
+hipError_t launch_row_kernel_wide(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    const bool b = kc.bf16 != 0;
+    switch (kind) {
+    case kRows:
+        return b ? go_rows<true>(kc, L, s) : go_rows<false>(kc, L, s);
+    case kFinalize:
+        return b ? go_finalize<true>(kc, L, s) : go_finalize<false>(kc, L, s);
+    case kReduce:
+        return go_reduce(kc, L, s);
+    case kTiny:
+    case kChunks:
+        return hipSuccess;
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ntc

@@ -27,15 +27,17 @@ import sqlite3
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-ROW_KERNEL_SOURCES = ["ntc_kernels.hip", "ntc_rng.h", "ntc_bf16.h", "ntc_internal.h"]
+ROW_KERNEL_SOURCES = ["ntc_kernels.hip", "ntc_dev.h", "ntc_rng.h", "ntc_bf16.h", "ntc_internal.h"]
+WIDE_KERNEL_SOURCES = ["ntc_kernels_wide.hip"]
 ROW_KERNELS = ("k_rows16", "k_chunk16", "k_tiny16", "k_finalize16", "k_row_items", "k_row_finalize",
-               "k_rows16_nm")
+               "k_rows16_nm", "k_rows32", "k_finalize32", "k_reduce_slots")
 
 
-def source_hash() -> str:
-    """Hash of the sources the row kernels are compiled from."""
+def source_hash(wide: bool = False) -> str:
+    """Hash of the sources the row kernels are compiled from (wide: the
+    R > 16 kernels too)."""
     h = hashlib.sha256()
-    for fn in ROW_KERNEL_SOURCES:
+    for fn in ROW_KERNEL_SOURCES + (WIDE_KERNEL_SOURCES if wide else []):
         with open(os.path.join(PKG, "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -81,7 +83,7 @@ def _per_dispatch(path: str, counter: str):
 
 
 def traffic(kernel: str, fetch: str, write: str, copy_fetch: str, copy_write: str, copy_bytes: int,
-            command: str) -> dict:
+            command: str, wide: bool = False) -> dict:
     """HBM bytes per launch of `kernel` (name prefix, e.g. 'k_chunk16<3, 4, false>')."""
     kib = 1024.0
     scale = {}
@@ -104,7 +106,7 @@ def traffic(kernel: str, fetch: str, write: str, copy_fetch: str, copy_write: st
             "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
             "fetch_kib_per_dispatch": per["FETCH_SIZE"][:n], "write_kib_per_dispatch": per["WRITE_SIZE"][:n],
             "copy_bytes": copy_bytes, "scale": {k: round(v, 4) for k, v in scale.items()},
-            "kernel_source_hash": source_hash(), "command": command}
+            "kernel_source_hash": source_hash(wide), "wide": wide, "command": command}
 
 
 def main(argv=None):
@@ -120,13 +122,14 @@ def main(argv=None):
     for k in ("kernel", "fetch", "write", "copy-fetch", "copy-write", "command"):
         f.add_argument("--" + k, required=True)
     f.add_argument("--copy-bytes", type=int, required=True)
+    f.add_argument("--wide", action="store_true", help="the kernel is one of the R > 16 kernels")
     f.add_argument("--out")
     a = ap.parse_args(argv)
     if a.what == "trace":
         text = trace(a.dir, a.title, a.command, a.last)
     else:
-        text = json.dumps(traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.command),
-                          indent=1) + "\n"
+        text = json.dumps(traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.command,
+                                  a.wide), indent=1) + "\n"
     if a.out:
         with open(a.out, "w") as fh:
             fh.write(text)

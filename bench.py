@@ -92,6 +92,8 @@ def main():
                          "serve: Poisson arrivals into a pool")
     ap.add_argument("--instances", type=int, default=256, help="batch/serve: number of problems")
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-at-a-time baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch: library default schedule instead of one tuned per kernel family")
     ap.add_argument("--rates", default="0.25,0.5,1,2", help="serve: arrival rates as fractions of saturation")
     ap.add_argument("--sweeps-per-step", type=int, default=4,
                     help="batch/serve: pool sweeps between host checks (the stop rule runs on the device)")
@@ -299,12 +301,26 @@ def run_batch(args):
     log(f"generated {n} problems, {nnz} train entries in {gen_s:.1f} s")
     kw = dict(c=0.1, lam=1e-3, gather_bf16=args.bf16)
 
+    # one schedule per kernel family (R <= 16, R <= 32), tuned on its largest problem
+    sched = {}
+    tune_s = 0.0
+    if not args.no_autotune:
+        from paper_2109_09534_amd import autotune
+        t0 = time.perf_counter()
+        sched = autotune.tune_classes([(p.dims, p.coords, p.values, sh[2]) for sh, p in zip(shapes, probs)],
+                                      sweeps=3, **kw)
+        tune_s = time.perf_counter() - t0
+        log(f"autotuned schedules {sched} in {tune_s:.1f} s")
+
+    def schedule_of(R):
+        return sched.get(16 if R <= 16 else 32 if R <= 32 else 64, {})
+
     pool = ntc.Pool(max_slots=n, window=5, tol=1e-4, max_sweeps=500)
     t0 = time.perf_counter()
     slots = []
     for (dims, _, R, sd), p in zip(shapes, probs):
         s = pool.admit(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
-                       test_values=p.test_values, **kw)
+                       test_values=p.test_values, schedule=schedule_of(R), **kw)
         if s is None:
             raise RuntimeError("the pool could not hold every problem")
         slots.append(s)
@@ -327,7 +343,7 @@ def run_batch(args):
         diffs = []
         for (dims, _, R, sd), p, q in zip(shapes, probs, per):
             g = ntc.Problem(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
-                            test_values=p.test_values, stream=0, **kw)
+                            test_values=p.test_values, stream=0, schedule=schedule_of(R), **kw)
             hist = [g.loss()[2]]
             while _stop_at(hist) is None:
                 g.sweep(1)
@@ -350,6 +366,7 @@ def run_batch(args):
                                "cap 500)", "instances": n, "nnz_train": nnz, "seed": args.seed},
         "instances_per_s_solve_only": round(n / run_s, 3),
         "admit_s": round(admit_s, 3), "solve_s": round(run_s, 3), "generate_s": round(gen_s, 2),
+        "autotune_s": round(tune_s, 2), "schedules": {str(k): v for k, v in sched.items()},
         "updates_per_s_solve": round(upd / run_s, 1),
         "sweeps_per_instance": {"min": int(min(q[1] for q in per)), "median": float(np.median([q[1] for q in per])),
                                 "max": int(max(q[1] for q in per))},

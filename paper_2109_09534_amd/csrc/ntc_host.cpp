@@ -289,7 +289,7 @@ ntc_status alloc_or_fail(ntc_problem *h, void **dst, size_t bytes, const char *w
 
 ntc::KernelClass kernel_class(const ntc_problem *h)
 {
-    return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0};
+    return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0, (h->RP == 32 && h->R % 2 == 0) ? 1 : 0};
 }
 
 ntc::RowArgs row_args(ntc_problem *h, int mode, int l)

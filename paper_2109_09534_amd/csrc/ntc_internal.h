@@ -101,11 +101,14 @@ struct Launch {
     int32_t blocks;
 };
 
-// Kernel family of a problem: padded rank (16, 32, 64), mode count, BF16 gathers.
+// Kernel family of a problem: padded rank (16, 32, 64), mode count, BF16
+// gathers, and (R <= 32 kernels) whether R is even, so that column pairs of a
+// factor row are read with one load.
 struct KernelClass {
     int32_t rp;
     int32_t nmodes;
     int32_t bf16;
+    int32_t pairs;
 };
 
 // The row kernels.  R <= 16: kRows takes whole rows with B_p <= group_max, one

@@ -59,6 +59,7 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
     }
     double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
     bool vanished = false;
+    double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
     for (int t = 0; t < a.power_iters; ++t) {
         const double w = skew_matvec(hd, v);
         const double n2 = row_sum_f64(w * w);
@@ -66,12 +67,16 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
             vanished = true;
             break;
         }
-        v = w / sqrt(n2);
+        // scale by a power of two near 1/||w||: exact, so the iterate keeps
+        // the direction of the normalised one without a square root or a division
+        const int e = ilogb(n2) >> 1;
+        v = ldexp(w, -e);
+        vv = ldexp(n2, -2 * e);  // ||v||^2, exactly
     }
     double L = 0.0;
     if (!vanished) {
         const double w = skew_matvec(hd, v);
-        L = row_sum_f64(v * w);
+        L = row_sum_f64(v * w) / vv;
     }
     if (!live)
         return;

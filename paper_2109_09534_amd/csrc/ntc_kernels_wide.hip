@@ -41,6 +41,7 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
     }
     double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
     bool vanished = false;
+    double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
     for (int t = 0; t < a.power_iters; ++t) {
         if (lane < RP)
             s_v[lane] = v;
@@ -57,7 +58,11 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
             vanished = true;
             break;
         }
-        v = w / sqrt(n2);
+        // scale by a power of two near 1/||w||: exact, so the iterate keeps
+        // the direction of the normalised one without a square root or a division
+        const int e = ilogb(n2) >> 1;
+        v = ldexp(w, -e);
+        vv = ldexp(n2, -2 * e);  // ||v||^2, exactly
     }
     double L = 0.0;
     if (!vanished) {
@@ -71,7 +76,7 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
                 w += h[q] * s_v[q];
         }
         __syncthreads();
-        L = wave_sum(v * w);
+        L = wave_sum(v * w) / vv;
     }
     if (!live)
         return;
@@ -322,6 +327,7 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
         return w + __shfl_xor(w, 32, 64);
     };
     bool vanished = false;
+    double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
     for (int t = 0; t < a.power_iters; ++t) {
         const double w = matvec(v);
         const double n2 = group32_sum_f64(w * w);
@@ -329,11 +335,15 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
             vanished = true;
             break;
         }
-        v = w / sqrt(n2);
+        // scale by a power of two near 1/||w||: exact, so the iterate keeps
+        // the direction of the normalised one without a square root or a division
+        const int e = ilogb(n2) >> 1;
+        v = ldexp(w, -e);
+        vv = ldexp(n2, -2 * e);  // ||v||^2, exactly
     }
     double L = 0.0;
     if (!vanished)
-        L = group32_sum_f64(v * matvec(v));
+        L = group32_sum_f64(v * matvec(v)) / vv;
     if (!live || half != 0)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + col;
@@ -355,11 +365,11 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
     }
 }
 
-template <int NM, bool BF16>
+template <int NM, bool BF16, bool PAIRS>
 __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
-    __shared__ uint4 s_rec[64];
+    __shared__ uint4 s_rec[2 * 64];
     __shared__ double s_h[12 * 64];  // FP64 sums of the EE, EO, OO blocks: register v of lane l at v*64 + l
     __shared__ double s_g[2 * 64];
     __shared__ double s_v[32];
@@ -370,7 +380,8 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
     const int R = a.R;
     const int c0 = 2 * j, c1 = 2 * j + 1;
     const bool l0 = c0 < R, l1 = c1 < R;
-    const bool pairs = (R & 1) == 0;  // every row starts 8 bytes (FP32) / 4 bytes (BF16) aligned
+    // PAIRS (R even): every row starts 8-byte (FP32) / 4-byte (BF16) aligned,
+    // so a lane reads its two columns with one load
 
     const int64_t base = a.rowptr[it.row];
     const int64_t n = a.rowptr[it.row + 1] - base;
@@ -379,7 +390,6 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
     const int64_t roff = static_cast<int64_t>(it.row) * R;
     const float y0 = l0 ? ysrc[roff + c0] : 0.0f;
     const float y1 = l1 ? ysrc[roff + c1] : 0.0f;
-    const uint4 zero_rec = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
 #pragma unroll
     for (int v = 0; v < 12; ++v)
         s_h[v * 64 + lane] = 0.0;
@@ -388,85 +398,131 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
     const uint32_t e0 = l0 ? c0 : 0, e1 = l1 ? c1 : 1;
     const uint32_t pc = l0 ? c0 : 0;  // pair offset (R even: c0 < R implies c0 + 1 < R)
 
-    float gf0 = 0.0f, gf1 = 0.0f;
-    for (int jb = it.j0; jb < it.j1; jb += 64) {
-        const int cnt = min(64, it.j1 - jb);
-        uint4 w0 = zero_rec;
-        if (lane < cnt) {
+    // Software pipeline over blocks of 64 samples (one record per lane,
+    // double-buffered in LDS) and sub-batches of 4 steps (16 samples): the
+    // records of block k+1 are in flight while block k is reduced, and the
+    // gathers of sub-batch s+1 while sub-batch s is.
+    struct Sub {
+        float f0[NM - 1][4], f1[NM - 1][4];
+    };
+    auto fetch = [&](int jb) {
+        uint4 w = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+        if (lane < it.j1 - jb) {
             const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
-            w0 = *reinterpret_cast<const uint4 *>(a.records + (base + q) * 4);
+            w = *reinterpret_cast<const uint4 *>(a.records + (base + q) * 4);
         }
-        __builtin_amdgcn_wave_barrier();  // the previous batch's reads of s_rec are done
-        s_rec[lane] = w0;
-        __builtin_amdgcn_wave_barrier();
-        const int steps = (cnt + 3) >> 2;
-        for (int h0 = 0; h0 < steps; h0 += 8) {
-            const int hs = min(8, steps - h0);
-            // all gathers of up to 8 steps first (a missing sample reads the zero rows)
-            float f0[NM - 1][8], f1[NM - 1][8];
+        return w;
+    };
+    // gathers of steps [s0, s0 + ns) of a staged block (a missing sample reads the zero rows)
+    auto issue = [&](const uint4 *buf, int s0, int ns, Sub &S) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (t < hs) {
-                    const uint4 rec = s_rec[4 * (h0 + t) + grp];
-                    const uint32_t rw[3] = {rec.x, rec.y, rec.z};
+        for (int t = 0; t < 4; ++t) {
+            if (t < ns) {
+                const uint4 rec = buf[4 * (s0 + t) + grp];
+                const uint32_t rw[3] = {rec.x, rec.y, rec.z};
 #pragma unroll
-                    for (int mm = 0; mm < NM - 1; ++mm) {
-                        if (BF16) {
-                            const uint16_t *src = a.gath16[mm] + rw[mm];
-                            if (pairs) {
-                                const uint32_t w = *reinterpret_cast<const uint32_t *>(src + pc);
-                                f0[mm][t] = __uint_as_float(w << 16);
-                                f1[mm][t] = __uint_as_float(w & 0xFFFF0000u);
-                            } else {
-                                f0[mm][t] = bf16_to_f32(src[e0]);
-                                f1[mm][t] = bf16_to_f32(src[e1]);
-                            }
+                for (int mm = 0; mm < NM - 1; ++mm) {
+                    if (BF16) {
+                        const uint16_t *src = a.gath16[mm] + rw[mm];
+                        if (PAIRS) {
+                            const uint32_t w = *reinterpret_cast<const uint32_t *>(src + pc);
+                            S.f0[mm][t] = __uint_as_float(w << 16);
+                            S.f1[mm][t] = __uint_as_float(w & 0xFFFF0000u);
                         } else {
-                            const float *src = a.gath[mm] + rw[mm];
-                            if (pairs) {
-                                const float2 w = *reinterpret_cast<const float2 *>(src + pc);
-                                f0[mm][t] = w.x;
-                                f1[mm][t] = w.y;
-                            } else {
-                                f0[mm][t] = src[e0];
-                                f1[mm][t] = src[e1];
-                            }
+                            S.f0[mm][t] = bf16_to_f32(src[e0]);
+                            S.f1[mm][t] = bf16_to_f32(src[e1]);
+                        }
+                    } else {
+                        const float *src = a.gath[mm] + rw[mm];
+                        if (PAIRS) {
+                            const float2 w = *reinterpret_cast<const float2 *>(src + pc);
+                            S.f0[mm][t] = w.x;
+                            S.f1[mm][t] = w.y;
+                        } else {
+                            S.f0[mm][t] = src[e0];
+                            S.f1[mm][t] = src[e1];
                         }
                     }
                 }
             }
-            f32x4 ee = {0.0f}, eo = {0.0f}, oo = {0.0f};
+        }
+    };
+    float gf0 = 0.0f, gf1 = 0.0f;
+    f32x4 ee = {0.0f}, eo = {0.0f}, oo = {0.0f};
+    auto compute = [&](const uint4 *buf, int s0, int ns, const Sub &S) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (t < hs) {  // wave-uniform
-                    float k0 = f0[0][t], k1 = f1[0][t];
+        for (int t = 0; t < 4; ++t) {
+            if (t < ns) {  // wave-uniform
+                float k0 = S.f0[0][t], k1 = S.f1[0][t];
 #pragma unroll
-                    for (int mm = 1; mm < NM - 1; ++mm) {
-                        k0 *= f0[mm][t];
-                        k1 *= f1[mm][t];
-                    }
-                    k0 = l0 ? k0 : 0.0f;
-                    k1 = l1 ? k1 : 0.0f;
-                    const uint4 rec = s_rec[4 * (h0 + t) + grp];
-                    const uint32_t xw[4] = {rec.x, rec.y, rec.z, rec.w};
-                    const float x = __uint_as_float(xw[NM - 1]);  // 0 for a missing sample
-                    const float pred = row_sum_f32(fmaf(k0, y0, k1 * y1));
-                    const float res = pred - x;
-                    gf0 = fmaf(res, k0, gf0);
-                    gf1 = fmaf(res, k1, gf1);
-                    // the four groups' samples: K = 4 of each 16x16 block of the column-permuted H
-                    ee = __builtin_amdgcn_mfma_f32_16x16x4f32(k0, k0, ee, 0, 0, 0);
-                    eo = __builtin_amdgcn_mfma_f32_16x16x4f32(k0, k1, eo, 0, 0, 0);
-                    oo = __builtin_amdgcn_mfma_f32_16x16x4f32(k1, k1, oo, 0, 0, 0);
+                for (int mm = 1; mm < NM - 1; ++mm) {
+                    k0 *= S.f0[mm][t];
+                    k1 *= S.f1[mm][t];
                 }
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                s_h[v * 64 + lane] += static_cast<double>(ee[v]);
-                s_h[(4 + v) * 64 + lane] += static_cast<double>(eo[v]);
-                s_h[(8 + v) * 64 + lane] += static_cast<double>(oo[v]);
+                k0 = l0 ? k0 : 0.0f;
+                k1 = l1 ? k1 : 0.0f;
+                const uint4 rec = buf[4 * (s0 + t) + grp];
+                const uint32_t xw[4] = {rec.x, rec.y, rec.z, rec.w};
+                const float x = __uint_as_float(xw[NM - 1]);  // 0 for a missing sample
+                const float pred = row_sum_f32(fmaf(k0, y0, k1 * y1));
+                const float res = pred - x;
+                gf0 = fmaf(res, k0, gf0);
+                gf1 = fmaf(res, k1, gf1);
+                // the four groups' samples: K = 4 of each 16x16 block of the column-permuted H
+                ee = __builtin_amdgcn_mfma_f32_16x16x4f32(k0, k0, ee, 0, 0, 0);
+                eo = __builtin_amdgcn_mfma_f32_16x16x4f32(k0, k1, eo, 0, 0, 0);
+                oo = __builtin_amdgcn_mfma_f32_16x16x4f32(k1, k1, oo, 0, 0, 0);
             }
         }
+    };
+    // FP32 block sums of 32 samples go into FP64
+    auto flush = [&]() {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            s_h[v * 64 + lane] += static_cast<double>(ee[v]);
+            s_h[(4 + v) * 64 + lane] += static_cast<double>(eo[v]);
+            s_h[(8 + v) * 64 + lane] += static_cast<double>(oo[v]);
+            ee[v] = 0.0f;
+            eo[v] = 0.0f;
+            oo[v] = 0.0f;
+        }
+    };
+    auto nsteps = [&](int jb, int sub) {  // valid steps of sub-batch `sub` of the block at jb
+        const int steps = (min(64, it.j1 - jb) + 3) >> 2;
+        return max(0, min(4, steps - 4 * sub));
+    };
+
+    Sub SA, SB;
+    int buf = 0;
+    if (it.j0 < it.j1) {
+        const uint4 w = fetch(it.j0);
+        s_rec[lane] = w;
+        __builtin_amdgcn_wave_barrier();
+        issue(s_rec, 0, nsteps(it.j0, 0), SA);
+    }
+    for (int jb = it.j0; jb < it.j1; jb += 64) {
+        const bool more = jb + 64 < it.j1;
+        uint4 wn = make_uint4(0u, 0u, 0u, 0u);
+        if (more)
+            wn = fetch(jb + 64);  // in flight during this block
+        const uint4 *cur = s_rec + 64 * buf;
+        issue(cur, 4, nsteps(jb, 1), SB);
+        compute(cur, 0, nsteps(jb, 0), SA);
+        issue(cur, 8, nsteps(jb, 2), SA);
+        compute(cur, 4, nsteps(jb, 1), SB);
+        flush();
+        issue(cur, 12, nsteps(jb, 3), SB);
+        compute(cur, 8, nsteps(jb, 2), SA);
+        if (more) {
+            uint4 *nxt = s_rec + 64 * (buf ^ 1);
+            nxt[lane] = wn;
+            __builtin_amdgcn_wave_barrier();
+            issue(nxt, 0, nsteps(jb + 64, 0), SA);
+        }
+        compute(cur, 12, nsteps(jb, 3), SB);
+        flush();
+        __builtin_amdgcn_wave_barrier();  // this block's reads of s_rec come before its next staging
+        buf ^= 1;
     }
     // gradient of columns 2j and 2j + 1: the four groups' partial sums in group order
     s_g[lane] = static_cast<double>(gf0);
@@ -568,18 +624,28 @@ __global__ __launch_bounds__(256) void k_reduce_slots(NTC_ROW_PARAMS)
 #define NTC_GO(KERNEL, BLOCK) \
     hipLaunchKernelGGL(KERNEL, dim3(L.blocks), dim3(BLOCK), 0, s, L.args, L.start, L.owner, L.n)
 
+template <bool BF16, bool PAIRS>
+hipError_t go_rows32(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.nmodes == 3)
+        NTC_GO((k_rows32<3, BF16, PAIRS>), 64);
+    else if (kc.nmodes == 4)
+        NTC_GO((k_rows32<4, BF16, PAIRS>), 64);
+    else
+        NTC_GO((k_rows32<2, BF16, PAIRS>), 64);
+    return hipGetLastError();
+}
+
 template <bool BF16>
 hipError_t go_rows(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.rp == 32) {
-        if (kc.nmodes == 3)
-            NTC_GO((k_rows32<3, BF16>), 64);
-        else if (kc.nmodes == 4)
-            NTC_GO((k_rows32<4, BF16>), 64);
-        else if (kc.nmodes == 2)
-            NTC_GO((k_rows32<2, BF16>), 64);
-        else
+        if (kc.nmodes > 4)
             NTC_GO((k_row_items<32, 0, BF16>), 64);
+        else if (kc.pairs)
+            return go_rows32<BF16, true>(kc, L, s);
+        else
+            return go_rows32<BF16, false>(kc, L, s);
     } else if (kc.rp == 64) {
         if (kc.nmodes == 3)
             NTC_GO((k_row_items<64, 3, BF16>), 64);

@@ -170,3 +170,25 @@ def test_admission_by_arena_memory():
         assert pool.admit(p.dims, p.coords, p.values, 8) is not None
         assert pool.admit(p.dims, p.coords, p.values, 8) is not None
         assert pool.admit(p.dims, p.coords, p.values, 8) is None
+
+
+def test_autotuned_schedule_keeps_parity_with_the_oracle():
+    """The tuner only reorders sums: the schedule it picks must still match
+    the oracle to the one-sweep bar."""
+    import oracle as O
+    from paper_2109_09534_amd import autotune
+    O.build(force=False)
+    p = synth.c1_small(seed=5)
+    R = 16
+    best, table = autotune.tune(p.dims, p.coords, p.values, R, c=0.1, sweeps=2)
+    _say("  " + ", ".join(f"{c or 'defaults'}: {ms:.3f} ms" for c, ms in table) + f" -> {best or 'defaults'}")
+    assert len(table) == len(autotune.candidates_for(R))
+    init = synth.uniform_init(p.dims, R, 1, synth.init_scale(p.values, R, 3))
+    g = ntc.Problem(p.dims, p.coords, p.values, R, c=0.1, init=init, schedule=best, stream=0)
+    o = O.Oracle(p.dims, p.coords, p.values, R, c=0.1, init=init)
+    g.sweep(1)
+    o.sweep(1)
+    for m in range(3):
+        ref = o.factors(m)
+        err = np.linalg.norm(g.factors(m) - ref) / np.linalg.norm(ref)
+        assert err <= 1e-5, (m, err)

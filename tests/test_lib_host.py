@@ -112,3 +112,14 @@ def test_estimate_bytes_bounds_the_allocations():
     assert ntc.estimate_bytes(dims, 95_000_000, 16, n_test=5_000_000, max_inner=2) > b
     with pytest.raises(ntc.NtcError):
         ntc.estimate_bytes([10, 0, 3], 5, 4)
+
+
+def test_autotune_candidates_cover_both_kernel_families():
+    from paper_2109_09534_amd import autotune
+    narrow, wide = autotune.candidates_for(16), autotune.candidates_for(32)
+    assert {} in narrow and {} in wide
+    allowed = {"tiny_max", "item_samples", "overlap", "group_max"}
+    for c in narrow + wide:
+        assert set(c) <= allowed
+        for v in c.values():
+            assert isinstance(v, int)

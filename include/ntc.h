@@ -104,6 +104,26 @@ void ntc_params_default(ntc_params *p);
 ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
                       const int32_t *coords, const float *values, int32_t rank, const ntc_params *p);
 
+/* ntc_create in two steps, for callers that build problems on other host
+ * threads while the GPU works (serving):
+ *   ntc_prepare      validates the arguments and does all host work (CSR of
+ *                    every mode, row schedule, copies of the held-out set and
+ *                    initial factors); it touches no device and no shared
+ *                    state, so any host thread may call it;
+ *   ntc_create_prepared  allocates, uploads and initialises, like the second
+ *                    half of ntc_create; p supplies only stream, allocator and
+ *                    overlap (its method parameters are those given to
+ *                    ntc_prepare); the prepared problem is not consumed;
+ *   ntc_prepared_bytes   the exact device bytes ntc_create_prepared allocates
+ *                    (allocations rounded to 256 bytes);
+ *   ntc_prepared_release frees it (NULL is accepted). */
+typedef struct ntc_prepared *ntc_prepared_handle;
+ntc_status ntc_prepare(ntc_prepared_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                       const int32_t *coords, const float *values, int32_t rank, const ntc_params *p);
+ntc_status ntc_create_prepared(ntc_handle *out, ntc_prepared_handle prepared, const ntc_params *p);
+ntc_status ntc_prepared_bytes(ntc_prepared_handle prepared, size_t *bytes);
+ntc_status ntc_prepared_release(ntc_prepared_handle prepared);
+
 /* Enqueue `nsweeps` iterations of Alg. 2 (each: modes 0..N-1 in order, each
  * mode one S_NMC call of Alg. 1 with MAX_INNER inner steps), advancing k by
  * one per sweep.  Asynchronous: returns once the work is enqueued. */
@@ -247,6 +267,10 @@ ntc_status ntc_pool_create(ntc_pool_handle *out, const ntc_pool_params *p);
 ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *dims, int64_t nnz,
                           const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
                           int32_t *slot);
+
+/* Admit a problem built by ntc_prepare (on any thread): only the device
+ * work happens here.  Same results and errors as ntc_pool_admit. */
+ntc_status ntc_pool_admit_prepared(ntc_pool_handle pool, ntc_prepared_handle prepared, int32_t *slot);
 
 /* Enqueue `nsweeps` pool sweeps over the running problems back to back and
  * wait for them.  The stop rule is applied on the device after every sweep;

@@ -112,6 +112,13 @@ _SIGNATURES = [
     ("ntc_release", ctypes.c_int, [ctypes.c_void_p]),
     ("ntc_estimate_bytes", ctypes.c_int, [ctypes.c_int32, _i64p, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)]),
+    ("ntc_prepare", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, _i64p, ctypes.c_int64, _i32p,
+                                   _f32p, ctypes.c_int32, ctypes.POINTER(_Params)]),
+    ("ntc_create_prepared", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                           ctypes.POINTER(_Params)]),
+    ("ntc_prepared_bytes", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    ("ntc_prepared_release", ctypes.c_int, [ctypes.c_void_p]),
+    ("ntc_pool_admit_prepared", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _i32p]),
     ("ntc_pool_params_default", None, [ctypes.POINTER(_PoolParams)]),
     ("ntc_pool_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_PoolParams)]),
     ("ntc_pool_admit", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, ctypes.c_int64, _i32p, _f32p,
@@ -299,6 +306,27 @@ class Problem:
         self.c, self.lam, self.max_inner, self.power_iters, self.seed = c, lam, max_inner, power_iters, seed
         self.gather_bf16 = gather_bf16
 
+    @classmethod
+    def from_prepared(cls, prepared: "Prepared", *, c: float = 0.1, lam: float = 1e-3, max_inner: int = 1,
+                      power_iters: int = 20, seed: int = 0, gather_bf16: bool = False, stream=None) -> "Problem":
+        """The device half of ntc_create on a Prepared problem.  The method
+        parameters are those the problem was prepared with; the ones given
+        here only label the Python object."""
+        self = cls.__new__(cls)
+        prm = _Params()
+        lib().ntc_params_default(ctypes.byref(prm))
+        if stream is not None and not isinstance(stream, int):
+            _require_single_runtime()
+        prm.stream = cls._stream_handle(stream)
+        h = ctypes.c_void_p()
+        _check(lib().ntc_create_prepared(ctypes.byref(h), prepared._h, ctypes.byref(prm)))
+        self._h = h
+        self._allocator = None
+        self.dims, self.N, self.R = list(prepared.dims), len(prepared.dims), prepared.rank
+        self.c, self.lam, self.max_inner, self.power_iters, self.seed = c, lam, max_inner, power_iters, seed
+        self.gather_bf16 = gather_bf16
+        return self
+
     @staticmethod
     def _stream_handle(stream):
         if stream is None or stream == 0:
@@ -404,6 +432,47 @@ class Problem:
 SLOT_FREE, SLOT_RUNNING, SLOT_STOPPED = 0, 1, 2
 
 
+class Prepared:
+    """The host half of ntc_create (ntc_prepare): CSR of every mode, row
+    schedule and copies of the held-out set and init, with no device work.
+    The C call releases the GIL, so problems can be prepared on worker
+    threads while the GPU sweeps."""
+
+    def __init__(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *, c: float = 0.1,
+                 lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
+                 gather_bf16: bool = False, test_coords=None, test_values=None, init=None,
+                 schedule: Optional[dict] = None):
+        d = np.asarray([int(x) for x in dims], dtype=np.int64)
+        co = np.ascontiguousarray(coords, dtype=np.int32)
+        va = np.ascontiguousarray(values, dtype=np.float32)
+        if co.ndim != 2 or co.shape[1] != d.size or co.shape[0] != va.shape[0]:
+            raise ValueError("coords must be [nnz, nmodes] and values [nnz]")
+        prm, keep = _make_params(d.size, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords,
+                                 test_values, init, schedule)
+        h = ctypes.c_void_p()
+        _check(lib().ntc_prepare(ctypes.byref(h), d.size, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
+                                 int(rank), ctypes.byref(prm)))
+        self._h = h
+        self.dims, self.rank = [int(x) for x in d], int(rank)
+
+    @property
+    def device_bytes(self) -> int:
+        out = ctypes.c_size_t()
+        _check(lib().ntc_prepared_bytes(self._h, ctypes.byref(out)))
+        return out.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ntc_prepared_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Pool:
     """Many independent problems on one GPU (ntc_pool_*): one device memory
     arena, batched launches over all running problems, a HIP graph per sweep,
@@ -457,6 +526,16 @@ class Pool:
             return None
         _check(st)
         self._dims[slot.value] = (list(int(x) for x in d), int(rank))
+        return slot.value
+
+    def admit_prepared(self, prepared: "Prepared") -> Optional[int]:
+        """Slot index, or None when the pool cannot hold it now."""
+        slot = ctypes.c_int32(-1)
+        st = lib().ntc_pool_admit_prepared(self._h, prepared._h, ctypes.byref(slot))
+        if st == -2:      # NTC_ENOMEM: not admitted now
+            return None
+        _check(st)
+        self._dims[slot.value] = (list(prepared.dims), prepared.rank)
         return slot.value
 
     def step(self, n: int = 1):

@@ -426,8 +426,43 @@ ntc_status validate_factor(const float *src, int64_t count, int mode)
     return NTC_OK;
 }
 
-ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t nnz, const int32_t *coords,
-                       const float *values, int32_t R, const ntc_params &p)
+}  // namespace
+
+// Everything ntc_create computes on the host before it touches the device:
+// the validated parameters, the CSR records and row pointers of every mode,
+// the row schedule, the held-out set and the initial factors.  Building one
+// needs no device and no shared state, so it may run on any host thread.
+struct ntc_prepared {
+    int N = 0, R = 0, RP = 0, rw = 0;
+    int64_t dims[ntc::kMaxModes] = {};
+    int64_t nnz = 0;
+    double c = 0.1, lambda = 1e-3;
+    int max_inner = 1, power_iters = 20;
+    uint64_t seed = 0;
+    bool bf16 = false;
+    int tiny_max = ntc::kTinyB, item_samples = 0, group_max = 256;
+    struct Mode {
+        ModeState st;                      // counts of the schedule (device pointers unset)
+        std::vector<uint32_t> rec;         // [nnz][rw]
+        std::vector<ntc::RowItem> tiny;
+        std::vector<Item> items;
+        std::vector<SplitRow> split;
+        std::vector<ntc::SlotGroup> groups;
+    } md[ntc::kMaxModes];
+    std::vector<uint32_t> row0;            // row * R of every mode-0 record (N = 4 or 8)
+    int32_t row_word = -1;
+    int32_t max_slots = 0;
+    int64_t max_row = 0;
+    std::vector<int32_t> test_coords;
+    std::vector<float> test_values;
+    std::vector<std::vector<float>> init;  // caller's factors, or empty for the default init
+    float init_scale = 1.0f;
+};
+
+namespace {
+
+ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t nnz, const int32_t *coords,
+                        const float *values, int32_t R, const ntc_params &p)
 {
     if (N < 2 || N > ntc::kMaxModes)
         return fail(NTC_EINVAL, "nmodes must be in [2, 8]");
@@ -487,92 +522,59 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
             NTC_TRY(validate_factor(p.init_factors[m], dims[m] * R, m));
         }
 
-    h->N = N;
-    h->R = R;
-    h->RP = padded_rank(R);
-    h->rw = record_words(N);
-    h->nnz = nnz;
-    h->c = p.c;
-    h->lambda = p.lambda;
-    h->max_inner = p.max_inner;
-    h->power_iters = p.power_iters;
-    h->seed = p.seed;
-    h->bf16 = p.gather_bf16 != 0;
-    h->stream = static_cast<hipStream_t>(p.stream);
-    h->alloc = p.dev_alloc;
-    h->dfree = p.dev_free;
-    h->actx = p.alloc_ctx;
-    h->tiny_max = p.tiny_max < 0 ? ntc::kTinyB : p.tiny_max;
-    h->item_samples = p.item_samples;
-    h->group_max = p.group_max > 0 ? p.group_max : 256;
-    NTC_HIP(hipGetDevice(&h->device));
-    if (p.overlap) {
-        NTC_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-        NTC_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-        NTC_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-    }
+    q->N = N;
+    q->R = R;
+    q->RP = padded_rank(R);
+    q->rw = record_words(N);
+    q->nnz = nnz;
+    q->c = p.c;
+    q->lambda = p.lambda;
+    q->max_inner = p.max_inner;
+    q->power_iters = p.power_iters;
+    q->seed = p.seed;
+    q->bf16 = p.gather_bf16 != 0;
+    q->tiny_max = p.tiny_max < 0 ? ntc::kTinyB : p.tiny_max;
+    q->item_samples = p.item_samples;
+    q->group_max = p.group_max > 0 ? p.group_max : 256;
     for (int m = 0; m < N; ++m)
-        h->dims[m] = dims[m];
-
-    // factors and shadows
-    int64_t maxI = 0;
-    // every factor has one extra all-zero row (index I_m): the gathers of a
-    // missing sample read it, so its Khatri-Rao row is exactly zero
-    for (int m = 0; m < N; ++m) {
-        const int64_t cntm = (dims[m] + 1) * R;
-        maxI = std::max(maxI, dims[m]);
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U[m]), cntm * sizeof(float), "factor"));
-        NTC_HIP(hipMemset(h->U[m], 0, cntm * sizeof(float)));
-        if (h->bf16) {
-            NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U16[m]), cntm * sizeof(uint16_t), "bf16 shadow"));
-            NTC_HIP(hipMemset(h->U16[m], 0, cntm * sizeof(uint16_t)));
-        }
-    }
-    if (h->max_inner > 1)
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->Y), maxI * R * sizeof(float), "Y buffer"));
+        q->dims[m] = dims[m];
 
     // CSR per mode and the static schedule
-    std::vector<uint32_t> rec(static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw);
-    const int rp = h->RP;
-    const int smax = h->item_samples > 0 ? h->item_samples : item_samples(rp);
-    int32_t max_slots = 0;
+    const int rp = q->RP;
+    const int smax = q->item_samples > 0 ? q->item_samples : item_samples(rp);
     for (int m = 0; m < N; ++m) {
-        ModeState &md = h->md[m];
+        ntc_prepared::Mode &pm = q->md[m];
+        ModeState &md = pm.st;
         md.I = dims[m];
+        pm.rec.assign(static_cast<size_t>(std::max<int64_t>(nnz, 1)) * q->rw, 0u);
         // mode 0's records also carry the row (times R) for the loss: in the
         // padding word when there is one, else in a separate array
-        const int own = (m == 0 && N < h->rw) ? N : -1;
-        csr_build(N, dims, nnz, coords, values, m, h->rw, md.h_rowptr, rec.data(), nullptr,
+        const int own = (m == 0 && N < q->rw) ? N : -1;
+        csr_build(N, dims, nnz, coords, values, m, q->rw, md.h_rowptr, pm.rec.data(), nullptr,
                   static_cast<uint32_t>(R), own);
         if (m == 0 && own < 0 && nnz > 0) {
-            std::vector<uint32_t> rowR(static_cast<size_t>(nnz));
+            q->row0.assign(static_cast<size_t>(nnz), 0u);
             for (int64_t r = 0; r < md.I; ++r)
                 for (int64_t e = md.h_rowptr[r]; e < md.h_rowptr[r + 1]; ++e)
-                    rowR[e] = static_cast<uint32_t>(r * R);
-            NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->row0), static_cast<size_t>(nnz) * 4, "loss rows"));
-            NTC_HIP(hipMemcpy(h->row0, rowR.data(), static_cast<size_t>(nnz) * 4, hipMemcpyHostToDevice));
+                    q->row0[e] = static_cast<uint32_t>(r * R);
         }
         if (m == 0)
-            h->row_word = own;
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.rowptr), (md.I + 1) * sizeof(int64_t), "rowptr"));
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.records),
-                              static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw * 4, "records"));
-        NTC_HIP(hipMemcpy(md.rowptr, md.h_rowptr.data(), (md.I + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-        NTC_HIP(hipMemcpy(md.records, rec.data(), static_cast<size_t>(nnz) * h->rw * 4, hipMemcpyHostToDevice));
+            q->row_word = own;
         std::vector<int32_t> rows;
         std::vector<int64_t> bsz(static_cast<size_t>(md.I));
         for (int64_t r = 0; r < md.I; ++r) {
             const int64_t n = md.h_rowptr[r + 1] - md.h_rowptr[r];
-            h->max_row = std::max(h->max_row, n);
-            bsz[r] = ntc::minibatch_size(h->c, n);
+            q->max_row = std::max(q->max_row, n);
+            bsz[r] = ntc::minibatch_size(q->c, n);
             if (bsz[r] > 0)
                 rows.push_back(static_cast<int32_t>(r));
         }
         std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return bsz[a] > bsz[b]; });
-        std::vector<Item> items, whole;
-        std::vector<SplitRow> split;
-        std::vector<ntc::SlotGroup> groups;
-        std::vector<ntc::RowItem> tiny;
+        std::vector<Item> &items = pm.items;
+        std::vector<Item> whole;
+        std::vector<SplitRow> &split = pm.split;
+        std::vector<ntc::SlotGroup> &groups = pm.groups;
+        std::vector<ntc::RowItem> &tiny = pm.tiny;
         auto row_item = [&](int32_t r) {
             const int64_t b0 = md.h_rowptr[r];
             return ntc::RowItem{r, static_cast<int32_t>(md.h_rowptr[r + 1] - b0), b0};
@@ -591,15 +593,15 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
                 const int64_t b = bsz[r];
                 md.samples += b;
                 md.active_rows += 1;
-                if (b <= h->tiny_max) {
+                if (b <= q->tiny_max) {
                     tiny.push_back(row_item(r));
                     md.tiny_samples += b;
-                } else if (b <= h->group_max) {
+                } else if (b <= q->group_max) {
                     md.fused_rows += 1;
                     md.row_fused += 1;
                     md.row_samples += b;
                     // N <= 4: the group kernel reads these as RowItem
-                    items.push_back(h->N <= 4 ? as_item(row_item(r)) : Item{r, 0, static_cast<int32_t>(b), -1});
+                    items.push_back(q->N <= 4 ? as_item(row_item(r)) : Item{r, 0, static_cast<int32_t>(b), -1});
                 } else if (b <= smax) {
                     md.fused_rows += 1;
                     md.chunk_fused += 1;
@@ -616,7 +618,7 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
             }
             md.n_group = static_cast<int32_t>(items.size());
             items.insert(items.end(), chunks.begin(), chunks.end());
-            if (h->N > 4) {  // the group kernel takes every item
+            if (q->N > 4) {  // the group kernel takes every item
                 md.row_samples += md.chunk_samples;
                 md.row_fused += md.chunk_fused;
                 md.chunk_samples = md.chunk_fused = 0;
@@ -659,41 +661,128 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
         md.n_partial = static_cast<int32_t>(items.size());
         items.insert(items.end(), whole.begin(), whole.end());
         md.n_tiny = static_cast<int32_t>(tiny.size());
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.tiny), tiny.size() * sizeof(ntc::RowItem),
-                              "tiny rows"));
-        if (!tiny.empty())
-            NTC_HIP(hipMemcpy(md.tiny, tiny.data(), tiny.size() * sizeof(ntc::RowItem), hipMemcpyHostToDevice));
         md.n_items = static_cast<int32_t>(items.size());
         md.n_split = static_cast<int32_t>(split.size());
         md.n_slots = slot;
-        max_slots = std::max(max_slots, slot);
         md.n_groups = static_cast<int32_t>(groups.size());
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.groups), groups.size() * sizeof(ntc::SlotGroup),
-                              "slot groups"));
-        if (!groups.empty())
-            NTC_HIP(hipMemcpy(md.groups, groups.data(), groups.size() * sizeof(ntc::SlotGroup),
-                              hipMemcpyHostToDevice));
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.items), items.size() * sizeof(Item), "items"));
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.split), split.size() * sizeof(SplitRow), "split"));
-        if (!items.empty())
-            NTC_HIP(hipMemcpy(md.items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
-        if (!split.empty())
-            NTC_HIP(hipMemcpy(md.split, split.data(), split.size() * sizeof(SplitRow), hipMemcpyHostToDevice));
+        q->max_slots = std::max(q->max_slots, slot);
     }
-    rec.clear();
-    rec.shrink_to_fit();
+
+    // held-out set and initial factors
+    if (p.n_test > 0) {
+        q->test_coords.assign(p.test_coords, p.test_coords + p.n_test * N);
+        q->test_values.assign(p.test_values, p.test_values + p.n_test);
+    }
+    if (p.init_factors) {
+        q->init.resize(N);
+        for (int m = 0; m < N; ++m)
+            q->init[m].assign(p.init_factors[m], p.init_factors[m] + dims[m] * R);
+    } else {
+        double sum = 0.0;
+        for (int64_t e = 0; e < nnz; ++e)
+            sum += static_cast<double>(values[e]);
+        double mean = nnz > 0 ? sum / static_cast<double>(nnz) : 0.0;
+        if (!(mean > 1e-30))
+            mean = 1e-30;
+        q->init_scale = static_cast<float>(
+            std::pow(mean / (static_cast<double>(R) * std::pow(2.0, -static_cast<double>(N))), 1.0 / static_cast<double>(N)));
+    }
+    return NTC_OK;
+}
+
+// Device side of ntc_create: allocations, uploads, default init.
+ntc_status commit_impl(ntc_problem *h, const ntc_prepared &q, const ntc_params &p)
+{
+    const int N = q.N, R = q.R;
+    const int64_t nnz = q.nnz;
+    h->N = N;
+    h->R = R;
+    h->RP = q.RP;
+    h->rw = q.rw;
+    h->nnz = nnz;
+    h->c = q.c;
+    h->lambda = q.lambda;
+    h->max_inner = q.max_inner;
+    h->power_iters = q.power_iters;
+    h->seed = q.seed;
+    h->bf16 = q.bf16;
+    h->stream = static_cast<hipStream_t>(p.stream);
+    h->alloc = p.dev_alloc;
+    h->dfree = p.dev_free;
+    h->actx = p.alloc_ctx;
+    h->tiny_max = q.tiny_max;
+    h->item_samples = q.item_samples;
+    h->group_max = q.group_max;
+    h->max_row = q.max_row;
+    h->row_word = q.row_word;
+    NTC_HIP(hipGetDevice(&h->device));
+    if (p.overlap) {
+        NTC_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        NTC_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        NTC_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
+    for (int m = 0; m < N; ++m)
+        h->dims[m] = q.dims[m];
+
+    // factors and shadows
+    int64_t maxI = 0;
+    // every factor has one extra all-zero row (index I_m): the gathers of a
+    // missing sample read it, so its Khatri-Rao row is exactly zero
+    for (int m = 0; m < N; ++m) {
+        const int64_t cntm = (q.dims[m] + 1) * R;
+        maxI = std::max(maxI, q.dims[m]);
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U[m]), cntm * sizeof(float), "factor"));
+        NTC_HIP(hipMemset(h->U[m], 0, cntm * sizeof(float)));
+        if (h->bf16) {
+            NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->U16[m]), cntm * sizeof(uint16_t), "bf16 shadow"));
+            NTC_HIP(hipMemset(h->U16[m], 0, cntm * sizeof(uint16_t)));
+        }
+    }
+    if (h->max_inner > 1)
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->Y), maxI * R * sizeof(float), "Y buffer"));
+    if (!q.row0.empty()) {
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->row0), static_cast<size_t>(nnz) * 4, "loss rows"));
+        NTC_HIP(hipMemcpy(h->row0, q.row0.data(), static_cast<size_t>(nnz) * 4, hipMemcpyHostToDevice));
+    }
+    for (int m = 0; m < N; ++m) {
+        const ntc_prepared::Mode &pm = q.md[m];
+        ModeState &md = h->md[m];
+        md = pm.st;
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.rowptr), (md.I + 1) * sizeof(int64_t), "rowptr"));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.records),
+                              static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw * 4, "records"));
+        NTC_HIP(hipMemcpy(md.rowptr, md.h_rowptr.data(), (md.I + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+        NTC_HIP(hipMemcpy(md.records, pm.rec.data(), static_cast<size_t>(nnz) * h->rw * 4, hipMemcpyHostToDevice));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.tiny), pm.tiny.size() * sizeof(ntc::RowItem),
+                              "tiny rows"));
+        if (!pm.tiny.empty())
+            NTC_HIP(hipMemcpy(md.tiny, pm.tiny.data(), pm.tiny.size() * sizeof(ntc::RowItem), hipMemcpyHostToDevice));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.groups), pm.groups.size() * sizeof(ntc::SlotGroup),
+                              "slot groups"));
+        if (!pm.groups.empty())
+            NTC_HIP(hipMemcpy(md.groups, pm.groups.data(), pm.groups.size() * sizeof(ntc::SlotGroup),
+                              hipMemcpyHostToDevice));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.items), pm.items.size() * sizeof(Item), "items"));
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.split), pm.split.size() * sizeof(SplitRow), "split"));
+        if (!pm.items.empty())
+            NTC_HIP(hipMemcpy(md.items, pm.items.data(), pm.items.size() * sizeof(Item), hipMemcpyHostToDevice));
+        if (!pm.split.empty())
+            NTC_HIP(hipMemcpy(md.split, pm.split.data(), pm.split.size() * sizeof(SplitRow), hipMemcpyHostToDevice));
+    }
+    const int rp = h->RP;
     NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->partials),
-                          static_cast<size_t>(std::max(max_slots, 1)) * (rp + rp * rp) * sizeof(double), "partials"));
+                          static_cast<size_t>(std::max(q.max_slots, 1)) * (rp + rp * rp) * sizeof(double), "partials"));
 
     // held-out set and loss buffers
-    h->n_test = p.n_test;
+    const int64_t n_test = static_cast<int64_t>(q.test_values.size());
+    h->n_test = n_test;
     NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->test_coords),
-                          static_cast<size_t>(std::max<int64_t>(p.n_test, 1)) * N * sizeof(int32_t), "test coords"));
+                          static_cast<size_t>(std::max<int64_t>(n_test, 1)) * N * sizeof(int32_t), "test coords"));
     NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->test_values),
-                          static_cast<size_t>(std::max<int64_t>(p.n_test, 1)) * sizeof(float), "test values"));
-    if (p.n_test > 0) {
-        NTC_HIP(hipMemcpy(h->test_coords, p.test_coords, p.n_test * N * sizeof(int32_t), hipMemcpyHostToDevice));
-        NTC_HIP(hipMemcpy(h->test_values, p.test_values, p.n_test * sizeof(float), hipMemcpyHostToDevice));
+                          static_cast<size_t>(std::max<int64_t>(n_test, 1)) * sizeof(float), "test values"));
+    if (n_test > 0) {
+        NTC_HIP(hipMemcpy(h->test_coords, q.test_coords.data(), n_test * N * sizeof(int32_t), hipMemcpyHostToDevice));
+        NTC_HIP(hipMemcpy(h->test_values, q.test_values.data(), n_test * sizeof(float), hipMemcpyHostToDevice));
     }
     NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->loss_part), 4 * ntc::kLossBlocks * sizeof(double),
                           "loss partials"));
@@ -715,23 +804,15 @@ ntc_status create_impl(ntc_problem *h, int32_t N, const int64_t *dims, int64_t n
     }
 
     // initial factors
-    if (p.init_factors) {
+    if (!q.init.empty()) {
         for (int m = 0; m < N; ++m) {
-            NTC_HIP(hipMemcpy(h->U[m], p.init_factors[m], dims[m] * R * sizeof(float), hipMemcpyHostToDevice));
+            NTC_HIP(hipMemcpy(h->U[m], q.init[m].data(), q.dims[m] * R * sizeof(float), hipMemcpyHostToDevice));
             if (h->bf16)
-                NTC_HIP(ntc::launch_to_bf16(h->U[m], h->U16[m], dims[m] * R, h->stream));
+                NTC_HIP(ntc::launch_to_bf16(h->U[m], h->U16[m], q.dims[m] * R, h->stream));
         }
     } else {
-        double sum = 0.0;
-        for (int64_t e = 0; e < nnz; ++e)
-            sum += static_cast<double>(values[e]);
-        double mean = nnz > 0 ? sum / static_cast<double>(nnz) : 0.0;
-        if (!(mean > 1e-30))
-            mean = 1e-30;
-        const float s = static_cast<float>(
-            std::pow(mean / (static_cast<double>(R) * std::pow(2.0, -static_cast<double>(N))), 1.0 / static_cast<double>(N)));
         for (int m = 0; m < N; ++m)
-            NTC_HIP(ntc::launch_init_factor(h->U[m], h->U16[m], dims[m] * R, m, h->seed, s, h->stream));
+            NTC_HIP(ntc::launch_init_factor(h->U[m], h->U16[m], q.dims[m] * R, m, h->seed, q.init_scale, h->stream));
     }
     return sync(h);
 }
@@ -801,7 +882,10 @@ ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int6
         return fail(NTC_ENOMEM, "host allocation failed");
     ntc_status s;
     try {
-        s = create_impl(h, nmodes, dims, nnz, coords, values, rank, p ? *p : def);
+        ntc_prepared q;
+        s = prepare_impl(&q, nmodes, dims, nnz, coords, values, rank, p ? *p : def);
+        if (s == NTC_OK)
+            s = commit_impl(h, q, p ? *p : def);
     } catch (const std::bad_alloc &) {
         s = fail(NTC_ENOMEM, "host allocation failed");
     }
@@ -810,6 +894,92 @@ ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int6
         return s;
     }
     *out = h;
+    return NTC_OK;
+}
+
+ntc_status ntc_prepare(ntc_prepared_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                       const int32_t *coords, const float *values, int32_t rank, const ntc_params *p)
+{
+    if (!out)
+        return fail(NTC_EINVAL, "out is null");
+    *out = nullptr;
+    ntc_params def;
+    ntc_params_default(&def);
+    ntc_prepared *q = new (std::nothrow) ntc_prepared();
+    if (!q)
+        return fail(NTC_ENOMEM, "host allocation failed");
+    ntc_status s;
+    try {
+        s = prepare_impl(q, nmodes, dims, nnz, coords, values, rank, p ? *p : def);
+    } catch (const std::bad_alloc &) {
+        s = fail(NTC_ENOMEM, "host allocation failed");
+    }
+    if (s != NTC_OK) {
+        delete q;
+        return s;
+    }
+    *out = q;
+    return NTC_OK;
+}
+
+ntc_status ntc_prepared_bytes(ntc_prepared_handle q, size_t *bytes)
+{
+    if (!q || !bytes)
+        return fail(NTC_EINVAL, "null argument");
+    auto up = [](int64_t b) { return static_cast<size_t>((std::max<int64_t>(b, 1) + 255) / 256 * 256); };
+    const int64_t N = q->N, R = q->R, rp = q->RP;
+    size_t t = 0;
+    int64_t maxI = 0;
+    for (int m = 0; m < N; ++m) {
+        const ntc_prepared::Mode &pm = q->md[m];
+        maxI = std::max(maxI, q->dims[m]);
+        t += up((q->dims[m] + 1) * R * 4) + (q->bf16 ? up((q->dims[m] + 1) * R * 2) : 0);
+        t += up((q->dims[m] + 1) * 8) + up(std::max<int64_t>(q->nnz, 1) * q->rw * 4);
+        t += up(static_cast<int64_t>(pm.tiny.size() * sizeof(ntc::RowItem)));
+        t += up(static_cast<int64_t>(pm.groups.size() * sizeof(ntc::SlotGroup)));
+        t += up(static_cast<int64_t>(pm.items.size() * sizeof(Item)));
+        t += up(static_cast<int64_t>(pm.split.size() * sizeof(SplitRow)));
+    }
+    if (q->max_inner > 1)
+        t += up(maxI * R * 4);
+    if (!q->row0.empty())
+        t += up(q->nnz * 4);
+    t += up(std::max<int64_t>(q->max_slots, 1) * (rp + rp * rp) * 8);
+    const int64_t nt = std::max<int64_t>(static_cast<int64_t>(q->test_values.size()), 1);
+    t += up(nt * N * 4) + up(nt * 4);
+    t += up(4 * ntc::kLossBlocks * 8) + up(32) + up((q->max_row + 1) * 4) + up(8);
+    t += up(N * q->max_inner * static_cast<int64_t>(sizeof(ntc::RowArgs)));
+    *bytes = t;
+    return NTC_OK;
+}
+
+ntc_status ntc_create_prepared(ntc_handle *out, ntc_prepared_handle q, const ntc_params *p)
+{
+    if (!out || !q)
+        return fail(NTC_EINVAL, "null argument");
+    *out = nullptr;
+    ntc_params def;
+    ntc_params_default(&def);
+    ntc_problem *h = new (std::nothrow) ntc_problem();
+    if (!h)
+        return fail(NTC_ENOMEM, "host allocation failed");
+    ntc_status s;
+    try {
+        s = commit_impl(h, *q, p ? *p : def);
+    } catch (const std::bad_alloc &) {
+        s = fail(NTC_ENOMEM, "host allocation failed");
+    }
+    if (s != NTC_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return NTC_OK;
+}
+
+ntc_status ntc_prepared_release(ntc_prepared_handle q)
+{
+    delete q;
     return NTC_OK;
 }
 

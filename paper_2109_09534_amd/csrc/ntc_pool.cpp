@@ -509,38 +509,38 @@ ntc_status ntc_pool_create(ntc_pool_handle *out, const ntc_pool_params *p)
     return NTC_OK;
 }
 
-ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *dims, int64_t nnz,
-                          const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
-                          int32_t *slot)
+namespace {
+
+int32_t free_slot_of(const ntc_pool *pool)
 {
-    if (!pool || !slot)
-        return fail(NTC_EINVAL, "null argument");
-    *slot = -1;
-    int32_t free_slot = -1;
     for (int32_t i = 0; i < static_cast<int32_t>(pool->slots.size()); ++i)
-        if (pool->slots[i].state == NTC_SLOT_FREE) {
-            free_slot = i;
-            break;
-        }
+        if (pool->slots[i].state == NTC_SLOT_FREE)
+            return i;
+    return -1;
+}
+
+// Device half of an admission: the prepared problem goes into the arena and
+// a free slot, with the stop-rule state of sweep 0.
+ntc_status admit_prepared(ntc_pool *pool, ntc_prepared_handle prep, int32_t *slot)
+{
+    *slot = -1;
+    const int32_t free_slot = free_slot_of(pool);
     if (free_slot < 0)
         return fail(NTC_ENOMEM, "no free slot");
-    ntc_params q;
-    if (p)
-        q = *p;
-    else
-        ntc_params_default(&q);
     size_t need = 0;
-    POOL_TRY(ntc_estimate_bytes(nmodes, dims, nnz, rank, &q, &need));
+    POOL_TRY(ntc_prepared_bytes(prep, &need));
     if (need > pool->arena.largest_free())
         return fail(NTC_ENOMEM, "arena cannot hold the problem now (" + std::to_string(need) + " bytes needed, " +
                                     std::to_string(pool->arena.largest_free()) + " in the largest free block)");
+    ntc_params q;
+    ntc_params_default(&q);
     q.stream = pool->stream;
     q.dev_alloc = arena_alloc;
     q.dev_free = arena_free;
     q.alloc_ctx = &pool->arena;
     q.overlap = 0;
     ntc_handle h = nullptr;
-    POOL_TRY(ntc_create(&h, nmodes, dims, nnz, coords, values, rank, &q));
+    POOL_TRY(ntc_create_prepared(&h, prep, &q));
     Slot &s = pool->slots[free_slot];
     s = Slot{};
     s.h = h;
@@ -577,6 +577,44 @@ ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *d
     pool->dirty = true;
     *slot = free_slot;
     return NTC_OK;
+}
+
+}  // namespace
+
+
+ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                          const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
+                          int32_t *slot)
+{
+    if (!pool || !slot)
+        return fail(NTC_EINVAL, "null argument");
+    *slot = -1;
+    if (free_slot_of(pool) < 0)
+        return fail(NTC_ENOMEM, "no free slot");
+    // refuse before the host work when even the upper bound cannot fit
+    ntc_params q;
+    if (p)
+        q = *p;
+    else
+        ntc_params_default(&q);
+    size_t bound = 0;
+    POOL_TRY(ntc_estimate_bytes(nmodes, dims, nnz, rank, &q, &bound));
+    if (bound > pool->arena.largest_free())
+        return fail(NTC_ENOMEM, "arena cannot hold the problem now (up to " + std::to_string(bound) +
+                                    " bytes needed, " + std::to_string(pool->arena.largest_free()) +
+                                    " in the largest free block)");
+    ntc_prepared_handle prep = nullptr;
+    POOL_TRY(ntc_prepare(&prep, nmodes, dims, nnz, coords, values, rank, &q));
+    const ntc_status st = admit_prepared(pool, prep, slot);
+    (void)ntc_prepared_release(prep);
+    return st;
+}
+
+ntc_status ntc_pool_admit_prepared(ntc_pool_handle pool, ntc_prepared_handle prepared, int32_t *slot)
+{
+    if (!pool || !prepared || !slot)
+        return fail(NTC_EINVAL, "null argument");
+    return admit_prepared(pool, prepared, slot);
 }
 
 ntc_status ntc_pool_step(ntc_pool_handle pool, int32_t nsweeps)

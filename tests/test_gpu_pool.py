@@ -192,3 +192,28 @@ def test_autotuned_schedule_keeps_parity_with_the_oracle():
         ref = o.factors(m)
         err = np.linalg.norm(g.factors(m) - ref) / np.linalg.norm(ref)
         assert err <= 1e-5, (m, err)
+
+
+def test_prepared_problems_match_direct_creation():
+    """ntc_prepare + ntc_create_prepared (and pool admission of a prepared
+    problem, built on a worker thread) give the same bits as ntc_create."""
+    import concurrent.futures as cf
+    mix = _mix(900)[:4]
+    with cf.ThreadPoolExecutor(max_workers=2) as ex:
+        futs = [ex.submit(ntc.Prepared, p.dims, p.coords, p.values, R, test_coords=p.test_coords,
+                          test_values=p.test_values, **kw) for p, R, kw in mix]
+        preps = [f.result() for f in futs]
+    with ntc.Pool(arena_bytes=1 << 30, max_slots=8, window=0, max_sweeps=1000) as pool:
+        slots = [pool.admit_prepared(q) for q in preps]
+        assert all(s is not None for s in slots)
+        pool.step(3)
+        for (p, R, kw), q, s in zip(mix, preps, slots):
+            ref, _ = _alone(p, R, kw, 3)
+            g = ntc.Problem.from_prepared(q, stream=0)
+            g.sweep(3)
+            for m in range(len(p.dims)):
+                assert np.array_equal(pool.factors(s, m), ref[m])
+                assert np.array_equal(g.factors(m), ref[m])
+            g.close()
+    for q in preps:
+        q.close()

@@ -123,3 +123,21 @@ def test_autotune_candidates_cover_both_kernel_families():
         assert set(c) <= allowed
         for v in c.values():
             assert isinstance(v, int)
+
+
+def test_prepare_runs_on_the_host_and_bounds_its_bytes():
+    """ntc_prepare needs no device: the CSR, schedule and copies are host work.
+    Its exact byte count stays under the admission upper bound."""
+    import paper_2109_09534_amd as ntc
+    for dims, nnz, R in [((100, 80, 60), 21600, 8), ((30, 20, 10, 8), 20000, 24), ((400, 300), 30000, 50)]:
+        p = synth.make_problem(dims, nnz, min(R, 8), seed=1, test_frac=0.1)
+        q = ntc.Prepared(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values)
+        exact = q.device_bytes
+        bound = ntc.estimate_bytes(p.dims, p.nnz, R, n_test=p.test_values.shape[0])
+        assert 0 < exact <= bound, (dims, exact, bound)
+        q.close()
+    bad = synth.tiny()
+    co = bad.coords.copy()
+    co[0, 0] = bad.dims[0]
+    with pytest.raises(ntc.NtcError):
+        ntc.Prepared(bad.dims, co, bad.values, 3)

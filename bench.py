@@ -37,7 +37,8 @@ def kernel_name(kind: str, nmodes: int, R: int, bf16: bool) -> str:
         return {"row_items": f"k_rows16<{nmodes}, 4, {b}>", "row_chunks": f"k_chunk16<{nmodes}, 4, {b}>",
                 "row_tiny": f"k_tiny16<{nmodes}, 4, {b}>", "row_finalize": f"k_finalize16<{b}>"}[kind]
     if R <= 32:
-        return {"row_items": f"k_rows32<{nmodes}, {b}>", "row_finalize": f"k_finalize32<{b}>",
+        pairs = "true" if R % 2 == 0 else "false"
+        return {"row_items": f"k_rows32<{nmodes}, {b}, {pairs}>", "row_finalize": f"k_finalize32<{b}>",
                 "row_reduce": "k_reduce_slots<32>"}[kind]
     return {"row_items": f"k_row_items<64, {nmodes}, {b}>", "row_finalize": f"k_row_finalize<64, {b}>",
             "row_reduce": "k_reduce_slots<64>"}[kind]

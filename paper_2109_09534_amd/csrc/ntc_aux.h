@@ -43,9 +43,6 @@ hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed
 int32_t test_blocks(int64_t n_test);
 hipError_t launch_test_sums(const LossArgs *args, const int32_t *start, const int32_t *owner, int32_t n,
                             int32_t blocks, double *part, double *out, hipStream_t s);
-// *k[t] += 1 for t < n
-hipError_t launch_advance_many(int64_t *const *k, int32_t n, hipStream_t s);
-
 // End of a pool sweep, per running problem j (device state indexed by slot):
 // unless it has already stopped, advance its sweep counters, record the
 // held-out RMSE of this sweep (test entry tidx[j] >= 0) and apply the stop

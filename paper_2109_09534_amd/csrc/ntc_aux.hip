@@ -254,13 +254,6 @@ __global__ void k_pool_rule(const PoolRuleArgs a)
         a.stop[slot] = 1;
 }
 
-__global__ void k_advance_many(int64_t *const *__restrict__ k, int32_t n)
-{
-    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (t < n)
-        *k[t] += 1;
-}
-
 }  // namespace
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s)
@@ -323,14 +316,6 @@ hipError_t launch_pool_rule(const PoolRuleArgs &a, hipStream_t s)
     if (a.n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_pool_rule, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_advance_many(int64_t *const *k, int32_t n, hipStream_t s)
-{
-    if (n <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_advance_many, dim3((n + 255) / 256), dim3(256), 0, s, k, n);
     return hipGetLastError();
 }
 

@@ -357,10 +357,16 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
         ntc::Launch L{};
         L.args = h->args_dev + mode * h->max_inner + l;
         L.n = 1;
-        // the one-row-per-lane rows are disjoint from the other rows: with a
-        // side stream they run concurrently (fork/join through events); a
-        // profiled sweep runs everything on one stream
-        const bool fork = !probe && h->side && md.n_tiny > 0 && (md.n_items > 0 || md.n_split > 0);
+        // With a side stream, work on disjoint rows runs concurrently
+        // (fork/join through events): the one-row-per-lane rows, and for
+        // R <= 16 with N <= 4 also the whole rows of the group kernel, go to
+        // the side stream while the chunks and the finalize of split rows
+        // (which reads only the chunks' partial slots) stay on the main
+        // stream.  A profiled sweep runs everything on one stream.
+        const bool rows_aside = kc.rp == 16 && kc.nmodes <= 4;
+        const int32_t n_aside = md.n_tiny + (rows_aside ? md.n_group : 0);
+        const int32_t n_main = (rows_aside ? md.n_items - md.n_group : md.n_items) + md.n_split;
+        const bool fork = !probe && h->side && n_aside > 0 && n_main > 0;
         if (fork) {
             NTC_HIP(hipEventRecord(h->ev_fork, h->stream));
             NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
@@ -370,7 +376,8 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
             L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny, md.n_groups);
             if (L.blocks <= 0)
                 continue;
-            hipStream_t st = (kern == ntc::kTiny && fork) ? h->side : h->stream;
+            const bool aside = kern == ntc::kTiny || (kern == ntc::kRows && rows_aside);
+            hipStream_t st = (aside && fork) ? h->side : h->stream;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (probe) {
                 NTC_HIP(hipEventCreate(&e0));

@@ -79,7 +79,7 @@ typedef struct ntc_params {
                                    stream concurrently with the other rows (default), 0 = serial */
     int32_t group_max;          /* schedule (R <= 16): rows with tiny_max < B_p <= group_max run
                                    one row per 16-lane group, longer ones as 256-thread chunks of
-                                   item_samples entries (0 = default 256) */
+                                   item_samples entries (0 = default 512) */
     int32_t reserved1;
 } ntc_params;
 

@@ -21,10 +21,10 @@ from . import Problem
 
 DEFAULT_CANDIDATES_16 = [
     {},  # the library's defaults
-    {"item_samples": 2048},
+    {"item_samples": 4096},
     {"item_samples": 8192},
-    {"group_max": 128},
-    {"group_max": 512},
+    {"group_max": 256},
+    {"group_max": 384},
     {"tiny_max": 2},
     {"tiny_max": 0},
     {"overlap": 0},

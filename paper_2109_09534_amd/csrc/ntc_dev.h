@@ -89,6 +89,45 @@ __device__ __forceinline__ double row_sum_f64(double x)
     return x;
 }
 
+// The T normalised products of the power method (Alg. 1, L_p) on an iterate
+// held one entry per lane: mv(x) returns this lane's entry of H v, sum(x) the
+// sum of x over the lanes of the row.  Normalising by ||H v|| only fixes the
+// length of the iterate, so the products are scaled by exact powers of two
+// instead, which round nothing: the first product fixes 2^-e with
+// 2^e <= ||H v_0|| < 2^(e+1), every later product takes the same 2^-e, and
+// the iterate is brought back near unit length once at the end.  H here is a
+// sampled Gram matrix of nonnegative rows plus lambda I, so its top
+// eigenvector u is nonnegative and ||H v_0|| >= L u.v_0 >= L / sqrt(R): each
+// later product scales the length by less than 2 sqrt(R), never shrinks the
+// component along u, and the iterate stays far inside FP64's range.  Returns
+// false if H v_0 vanishes (L = 0 by definition); else v is the final iterate
+// and vv = ||v||^2 exactly.
+template <class MV, class SUM>
+__device__ __forceinline__ bool power_iterate(double &v, double &vv, int T, MV mv, SUM sum)
+{
+    if (T <= 0)
+        return true;
+    const double w = mv(v);
+    double n2 = sum(w * w);
+    if (!(n2 > 0.0))
+        return false;
+    const int e = ilogb(n2) >> 1;
+    v = ldexp(w, -e);
+    if (T == 1) {
+        vv = ldexp(n2, -2 * e);
+        return true;
+    }
+    for (int t = 1; t < T; ++t)
+        v = ldexp(mv(v), -e);
+    n2 = sum(v * v);
+    if (!(n2 > 0.0))
+        return false;
+    const int k = ilogb(n2) >> 1;
+    v = ldexp(v, -k);
+    vv = ldexp(n2, -2 * k);
+    return true;
+}
+
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 

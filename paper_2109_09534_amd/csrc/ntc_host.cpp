@@ -57,11 +57,14 @@ int record_words(int nmodes)
     return nmodes <= 4 ? 4 : 8;
 }
 
-// Samples per work item: a fixed amount of work per wave (the wave consumes
-// 64/RP samples per step).
-int item_samples(int rp)
+// Samples per work item: R <= 16 with N <= 4, a chunk for a 256-thread block
+// (rows of more than group_max samples); otherwise a fixed amount of work per
+// wave (the wave consumes 64/RP samples per step).
+int item_samples(int rp, int nmodes)
 {
-    return rp == 16 ? 4096 : 512 * (64 / rp);
+    if (rp == 16)
+        return nmodes <= 4 ? 6144 : 4096;
+    return 512 * (64 / rp);
 }
 
 unsigned host_threads()
@@ -201,7 +204,7 @@ struct ntc_problem {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int tiny_max = ntc::kTinyB;
     int item_samples = 0;
-    int group_max = 256;
+    int group_max = 512;
     int device = 0;
     ntc_alloc_fn alloc = nullptr;
     ntc_free_fn dfree = nullptr;
@@ -447,7 +450,7 @@ struct ntc_prepared {
     int max_inner = 1, power_iters = 20;
     uint64_t seed = 0;
     bool bf16 = false;
-    int tiny_max = ntc::kTinyB, item_samples = 0, group_max = 256;
+    int tiny_max = ntc::kTinyB, item_samples = 0, group_max = 512;
     struct Mode {
         ModeState st;                      // counts of the schedule (device pointers unset)
         std::vector<uint32_t> rec;         // [nnz][rw]
@@ -542,13 +545,13 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
     q->bf16 = p.gather_bf16 != 0;
     q->tiny_max = p.tiny_max < 0 ? ntc::kTinyB : p.tiny_max;
     q->item_samples = p.item_samples;
-    q->group_max = p.group_max > 0 ? p.group_max : 256;
+    q->group_max = p.group_max > 0 ? p.group_max : 512;
     for (int m = 0; m < N; ++m)
         q->dims[m] = dims[m];
 
     // CSR per mode and the static schedule
     const int rp = q->RP;
-    const int smax = q->item_samples > 0 ? q->item_samples : item_samples(rp);
+    const int smax = q->item_samples > 0 ? q->item_samples : item_samples(rp, N);
     for (int m = 0; m < N; ++m) {
         ntc_prepared::Mode &pm = q->md[m];
         ModeState &md = pm.st;
@@ -1242,7 +1245,7 @@ ntc_status ntc_estimate_bytes(int32_t nmodes, const int64_t *dims, int64_t nnz, 
     ntc_params_default(&def);
     const ntc_params &q = p ? *p : def;
     const int64_t N = nmodes, R = rank, rp = padded_rank(rank), rw = record_words(nmodes);
-    const int64_t smax = q.item_samples > 0 ? q.item_samples : item_samples(static_cast<int>(rp));
+    const int64_t smax = q.item_samples > 0 ? q.item_samples : item_samples(static_cast<int>(rp), nmodes);
     const double c = (q.c > 0.0 && q.c <= 1.0) ? q.c : 1.0;
     const int64_t inner = std::max<int32_t>(q.max_inner, 1);
     auto up = [](int64_t b) { return static_cast<size_t>((std::max<int64_t>(b, 1) + 255) / 256 * 256); };

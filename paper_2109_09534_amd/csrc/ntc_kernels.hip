@@ -58,21 +58,9 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
         hd[0] += a.lambda;  // sigma_0 is the identity: the diagonal
     }
     double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
-    bool vanished = false;
     double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
-    for (int t = 0; t < a.power_iters; ++t) {
-        const double w = skew_matvec(hd, v);
-        const double n2 = row_sum_f64(w * w);
-        if (!(n2 > 0.0)) {
-            vanished = true;
-            break;
-        }
-        // scale by a power of two near 1/||w||: exact, so the iterate keeps
-        // the direction of the normalised one without a square root or a division
-        const int e = ilogb(n2) >> 1;
-        v = ldexp(w, -e);
-        vv = ldexp(n2, -2 * e);  // ||v||^2, exactly
-    }
+    const bool vanished = !power_iterate(v, vv, a.power_iters, [&](double x) { return skew_matvec(hd, x); },
+                                         [](double x) { return row_sum_f64(x); });
     double L = 0.0;
     if (!vanished) {
         const double w = skew_matvec(hd, v);
@@ -707,11 +695,12 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
                 u[i] = 0.0;
             break;
         }
-        const double inv = 1.0 / mx;
-        al = (al * lam) * inv;
+        // by the power of two at or below the largest magnitude: exact, no division
+        const int e = ilogb(mx);
+        al = ldexp(al * lam, -e);
 #pragma unroll
         for (int i = 0; i < kTinyB; ++i)
-            u[i] = un[i] * inv;
+            u[i] = ldexp(un[i], -e);
     }
     double x2 = al * al, kx2 = 0.0;
 #pragma unroll

@@ -39,45 +39,25 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
             if (q == lane)
                 h[q] += a.lambda;  // static register index; diagonal of row `lane`
     }
+    auto matvec = [&](double x) {
+        if (lane < RP)
+            s_v[lane] = x;
+        __syncthreads();
+        double w = 0.0;
+        if (lane < RP) {
+#pragma unroll
+            for (int q = 0; q < RP; ++q)
+                w += h[q] * s_v[q];
+        }
+        __syncthreads();
+        return w;
+    };
     double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
-    bool vanished = false;
     double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
-    for (int t = 0; t < a.power_iters; ++t) {
-        if (lane < RP)
-            s_v[lane] = v;
-        __syncthreads();
-        double w = 0.0;
-        if (lane < RP) {
-#pragma unroll
-            for (int q = 0; q < RP; ++q)
-                w += h[q] * s_v[q];
-        }
-        __syncthreads();
-        const double n2 = wave_sum(w * w);
-        if (!(n2 > 0.0)) {
-            vanished = true;
-            break;
-        }
-        // scale by a power of two near 1/||w||: exact, so the iterate keeps
-        // the direction of the normalised one without a square root or a division
-        const int e = ilogb(n2) >> 1;
-        v = ldexp(w, -e);
-        vv = ldexp(n2, -2 * e);  // ||v||^2, exactly
-    }
+    const bool vanished = !power_iterate(v, vv, a.power_iters, matvec, [](double x) { return wave_sum(x); });
     double L = 0.0;
-    if (!vanished) {
-        if (lane < RP)
-            s_v[lane] = v;
-        __syncthreads();
-        double w = 0.0;
-        if (lane < RP) {
-#pragma unroll
-            for (int q = 0; q < RP; ++q)
-                w += h[q] * s_v[q];
-        }
-        __syncthreads();
-        L = wave_sum(v * w) / vv;
-    }
+    if (!vanished)
+        L = wave_sum(v * matvec(v)) / vv;
     if (!live)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + lane;
@@ -274,13 +254,39 @@ __device__ __forceinline__ float group32_sum_f32(float x)
     return x + __shfl_xor(x, 16, 64);
 }
 
+// x[l] + x[l ^ 16] and x[l] + x[l ^ 32] through the gfx950 lane swaps (no
+// LDS round trip).  A swap of x with itself leaves the lower and the upper
+// partner's value in the two results, in either order, so their sum is the
+// same in every lane of the pair.
+__device__ __forceinline__ double swap16_sum(double x)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    const uint32_t lo = static_cast<uint32_t>(b), hi = static_cast<uint32_t>(b >> 32);
+    const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double x0 = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(ph[0]) << 32) | pl[0]));
+    const double x1 = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(ph[1]) << 32) | pl[1]));
+    return x0 + x1;
+}
+
+__device__ __forceinline__ double swap32_sum(double x)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    const uint32_t lo = static_cast<uint32_t>(b), hi = static_cast<uint32_t>(b >> 32);
+    const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double x0 = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(ph[0]) << 32) | pl[0]));
+    const double x1 = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(ph[1]) << 32) | pl[1]));
+    return x0 + x1;
+}
+
 __device__ __forceinline__ double group32_sum_f64(double x)
 {
     x += dpp_f64<kDppXor1>(x);
     x += dpp_f64<kDppXor2>(x);
     x += dpp_f64<kDppHalfMirror>(x);
     x += dpp_f64<kDppMirror>(x);
-    return x + __shfl_xor(x, 16, 64);
+    return swap16_sum(x);
 }
 
 constexpr int kSlot32 = 32 + 32 * 32;  // doubles per partial slot: g[32], row-major H[32][32]
@@ -323,24 +329,10 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
         for (int q = 0; q < 16; ++q)
             w4[q & 3] = fma(hd[q], s_v[16 * half + q], w4[q & 3]);
         __builtin_amdgcn_wave_barrier();
-        const double w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
-        return w + __shfl_xor(w, 32, 64);
+        return swap32_sum((w4[0] + w4[1]) + (w4[2] + w4[3]));
     };
-    bool vanished = false;
     double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
-    for (int t = 0; t < a.power_iters; ++t) {
-        const double w = matvec(v);
-        const double n2 = group32_sum_f64(w * w);
-        if (!(n2 > 0.0)) {
-            vanished = true;
-            break;
-        }
-        // scale by a power of two near 1/||w||: exact, so the iterate keeps
-        // the direction of the normalised one without a square root or a division
-        const int e = ilogb(n2) >> 1;
-        v = ldexp(w, -e);
-        vv = ldexp(n2, -2 * e);  // ||v||^2, exactly
-    }
+    const bool vanished = !power_iterate(v, vv, a.power_iters, matvec, [](double x) { return group32_sum_f64(x); });
     double L = 0.0;
     if (!vanished)
         L = group32_sum_f64(v * matvec(v)) / vv;

@@ -291,6 +291,25 @@ __device__ __forceinline__ double group32_sum_f64(double x)
 
 constexpr int kSlot32 = 32 + 32 * 32;  // doubles per partial slot: g[32], row-major H[32][32]
 
+// One entry summed over `count` consecutive partial slots of S doubles, in
+// slot order; the loads of eight slots are in flight together.
+template <int S>
+__device__ __forceinline__ double slot_sum(const double *p, int count)
+{
+    double acc = 0.0;
+    for (int q = 0; q < count; q += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            t[u] = q + u < count ? p[static_cast<int64_t>(q + u) * S] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (q + u < count)
+                acc += t[u];
+    }
+    return acc;
+}
+
 // Accumulator register v of lane l of v_mfma_f32_32x32x2f32 holds
 // H[(v % 4) + 8 (v / 4) + 4 (l / 32)][l % 32].
 __device__ __forceinline__ int mfma32_row(int v, int l)
@@ -556,7 +575,7 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
             hd[q] = half == 0 ? blk(1, q, i - 16) : blk(2, i - 16, q);
     }
     const double g = gsum(col);
-    const float y = col < R ? ysrc[roff + col] : 0.0f;
+    const float y = i < 16 ? y0 : y1;  // column col of the row, already in registers
     finish_row32<BF16>(a, it.row, lane, col, g, hd, y, s_v);
 }
 
@@ -572,12 +591,9 @@ __global__ __launch_bounds__(256) void k_finalize32(NTC_ROW_PARAMS)
     __shared__ double s_v[32];
     const SplitRow sr = a.split[blk_];
     const int tid = threadIdx.x;
-    for (int e = tid; e < kSlot32; e += 256) {
-        double acc = 0.0;
-        for (int q = 0; q < sr.nslots; ++q)
-            acc += a.partials[static_cast<int64_t>(sr.slot0 + q) * kSlot32 + e];
-        s_p[e] = acc;
-    }
+    const double *src = a.partials + static_cast<int64_t>(sr.slot0) * kSlot32;
+    for (int e = tid; e < kSlot32; e += 256)
+        s_p[e] = slot_sum<kSlot32>(src + e, sr.nslots);
     __syncthreads();
     if (tid >= 64)
         return;
@@ -605,12 +621,9 @@ __global__ __launch_bounds__(256) void k_reduce_slots(NTC_ROW_PARAMS)
     NTC_ROW_RESOLVE(a, blk_);
     constexpr int S = RP + RP * RP;
     const SlotGroup gr = a.groups[blk_];
-    for (int e = threadIdx.x; e < S; e += 256) {
-        double acc = 0.0;
-        for (int q = 0; q < gr.count; ++q)
-            acc += a.partials[static_cast<int64_t>(gr.src + q) * S + e];
-        a.partials[static_cast<int64_t>(gr.dst) * S + e] = acc;
-    }
+    const double *src = a.partials + static_cast<int64_t>(gr.src) * S;
+    for (int e = threadIdx.x; e < S; e += 256)
+        a.partials[static_cast<int64_t>(gr.dst) * S + e] = slot_sum<S>(src + e, gr.count);
 }
 
 #define NTC_GO(KERNEL, BLOCK) \

@@ -213,6 +213,18 @@ typedef struct ntc_launch_record {
  * order and the number of launches to *count.  Synchronising. */
 ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, int32_t *count);
 
+/* Run `nsweeps` sweeps exactly as ntc_sweep does, recording HIP events
+ * around every kernel launch on the stream that launch runs on.
+ * concurrent = 1 keeps ntc_sweep's side-stream overlap, so a duration
+ * includes sharing the GPU with the launches beside it (as a kernel trace
+ * shows it); 0 runs every launch on h's stream, one after another
+ * (ntc_profile_sweep is this with nsweeps = 1).  Writes up to `cap`
+ * records, in launch order sweep after sweep, and the number of launches to
+ * *count.  Synchronising.  Errors: NTC_EINVAL for a null handle or count,
+ * out == NULL with cap > 0, or nsweeps < 0. */
+ntc_status ntc_profile_sweeps(ntc_handle h, int32_t nsweeps, int32_t concurrent, ntc_launch_record *out,
+                              int32_t cap, int32_t *count);
+
 /* Upper bound of the device bytes ntc_create would allocate for this
  * problem (factors, BF16 shadows, CSR records and row pointers, the row
  * schedule, partial slots, held-out set, argument tables), computed on the

@@ -109,6 +109,8 @@ _SIGNATURES = [
     ("ntc_time_sweeps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p]),
     ("ntc_profile_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(LaunchRecord), ctypes.c_int32,
                                          _i32p]),
+    ("ntc_profile_sweeps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(LaunchRecord), ctypes.c_int32, _i32p]),
     ("ntc_release", ctypes.c_int, [ctypes.c_void_p]),
     ("ntc_estimate_bytes", ctypes.c_int, [ctypes.c_int32, _i64p, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)]),
@@ -367,11 +369,17 @@ class Problem:
         return ms.value
 
     def profile_sweep(self):
-        """One sweep with HIP events around every launch: list of dicts."""
-        cap = 4096
+        """One sweep with HIP events around every launch, all on one stream: list of dicts."""
+        return self.profile_sweeps(1, concurrent=False)
+
+    def profile_sweeps(self, nsweeps: int, concurrent: bool = True):
+        """`nsweeps` sweeps with HIP events around every launch on its own
+        stream (concurrent: with the side-stream overlap of a plain sweep):
+        list of dicts in launch order, sweep after sweep."""
+        cap = 4096 * max(nsweeps, 1)
         buf = (LaunchRecord * cap)()
         cnt = ctypes.c_int32(0)
-        _check(lib().ntc_profile_sweep(self._h, buf, cap, ctypes.byref(cnt)))
+        _check(lib().ntc_profile_sweeps(self._h, nsweeps, int(bool(concurrent)), buf, cap, ctypes.byref(cnt)))
         return [dict(kernel=("row_items", "row_finalize", "row_tiny", "row_chunks", "row_reduce")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
                      samples=r.samples, rows=r.rows, ms=r.ms) for r in buf[: min(cnt.value, cap)]]
 

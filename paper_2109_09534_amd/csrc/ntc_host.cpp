@@ -350,6 +350,7 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
 struct LaunchProbe {
     std::vector<ntc_launch_record> rec;
     std::vector<hipEvent_t> ev;  // two per launch
+    bool concurrent = false;     // keep the side-stream overlap of ntc_sweep
 };
 
 ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
@@ -365,11 +366,11 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
         // R <= 16 with N <= 4 also the whole rows of the group kernel, go to
         // the side stream while the chunks and the finalize of split rows
         // (which reads only the chunks' partial slots) stay on the main
-        // stream.  A profiled sweep runs everything on one stream.
+        // stream.  A serial profiled sweep runs everything on one stream.
         const bool rows_aside = kc.rp == 16 && kc.nmodes <= 4;
         const int32_t n_aside = md.n_tiny + (rows_aside ? md.n_group : 0);
         const int32_t n_main = (rows_aside ? md.n_items - md.n_group : md.n_items) + md.n_split;
-        const bool fork = !probe && h->side && n_aside > 0 && n_main > 0;
+        const bool fork = (!probe || probe->concurrent) && h->side && n_aside > 0 && n_main > 0;
         if (fork) {
             NTC_HIP(hipEventRecord(h->ev_fork, h->stream));
             NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
@@ -1204,16 +1205,27 @@ ntc_status ntc_time_sweeps(ntc_handle h, int32_t nsweeps, double *ms)
 
 ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, int32_t *count)
 {
+    return ntc_profile_sweeps(h, 1, 0, out, cap, count);
+}
+
+ntc_status ntc_profile_sweeps(ntc_handle h, int32_t nsweeps, int32_t concurrent, ntc_launch_record *out,
+                              int32_t cap, int32_t *count)
+{
     if (!h || !count || (cap > 0 && !out))
         return fail(NTC_EINVAL, "null argument");
+    if (nsweeps < 0)
+        return fail(NTC_EINVAL, "nsweeps must be >= 0");
     LaunchProbe probe;
+    probe.concurrent = concurrent != 0;
     ntc_status s = NTC_OK;
-    for (int m = 0; m < h->N && s == NTC_OK; ++m)
-        s = enqueue_mode(h, m, &probe);
-    if (s == NTC_OK) {
-        if (ntc::launch_advance(h->kdev, 1, h->stream) != hipSuccess)
-            s = fail(NTC_EDEVICE, "launch of the sweep-counter update failed");
-        h->k += 1;
+    for (int32_t k = 0; k < nsweeps && s == NTC_OK; ++k) {
+        for (int m = 0; m < h->N && s == NTC_OK; ++m)
+            s = enqueue_mode(h, m, &probe);
+        if (s == NTC_OK) {
+            if (ntc::launch_advance(h->kdev, 1, h->stream) != hipSuccess)
+                s = fail(NTC_EDEVICE, "launch of the sweep-counter update failed");
+            h->k += 1;
+        }
     }
     hipError_t se = hipStreamSynchronize(h->stream);
     if (se == hipSuccess && h->side)

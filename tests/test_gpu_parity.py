@@ -198,6 +198,32 @@ def test_runs_are_bit_identical_and_resumable():
         assert np.array_equal(fa, c.factors(m))
 
 
+def test_profiled_sweeps_are_ordinary_sweeps():
+    """ntc_profile_sweeps runs the sweeps ntc_sweep runs (serial or with the
+    side-stream overlap), so the factors match plain sweeps bit for bit; it
+    returns one record per launch, sweep after sweep, with a duration."""
+    p = synth.c1_small(seed=6)
+    init = synth.uniform_init(p.dims, 16, 4, synth.init_scale(p.values, 16, 3))
+    ref = ntc.Problem(p.dims, p.coords, p.values, 16, init=init, stream=0)
+    ref.sweep(3)
+    one = None
+    for concurrent in (False, True):
+        g = ntc.Problem(p.dims, p.coords, p.values, 16, init=init, stream=0)
+        first = g.profile_sweep()
+        rest = g.profile_sweeps(2, concurrent=concurrent)
+        assert len(rest) == 2 * len(first) and len(first) > 0
+        one = len(first)
+        for a, b in zip(rest[:one], rest[one:]):
+            assert (a["kernel"], a["mode"], a["blocks"], a["samples"]) == (b["kernel"], b["mode"], b["blocks"],
+                                                                           b["samples"])
+        assert all(r["ms"] > 0.0 for r in first + rest)
+        assert g.sweep_count == 3
+        for m in range(3):
+            assert np.array_equal(g.factors(m), ref.factors(m)), (concurrent, m)
+        g.close()
+    _say(f"  {one} launches per sweep; profiled sweeps identical to plain ones")
+
+
 def test_default_init_matches_oracle_bit_exactly():
     p = synth.c0(seed=1)
     g = ntc.Problem(p.dims, p.coords, p.values, 8, seed=99, stream=0)

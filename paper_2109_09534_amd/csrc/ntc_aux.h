@@ -28,6 +28,22 @@ struct LossArgs {
 
 constexpr int kLossBlocks = 2048;  // 32 waves per CU: enough loads in flight
 constexpr int kLossThreads = 256;
+constexpr int kMaxTestBlocks = 1024;  // held-out blocks per problem in a pool launch
+
+// Lanes that share one entry in the training and held-out sums.  With
+// R % 4 == 0 a lane reads four consecutive columns of each factor row as one
+// 16-byte load, and the group is the power of two >= R / 4 (at most 16);
+// otherwise 16 lanes read one column each.  A group is aligned within a
+// 16-lane DPP row, so it reads each factor row as one coalesced access.
+__host__ __device__ inline int entry_lanes(int R)
+{
+    if (R % 4 != 0)
+        return 16;
+    int g = 1;
+    while (g < 16 && 4 * g < R)
+        g <<= 1;
+    return g;
+}
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s);
 hipError_t launch_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale,
@@ -40,7 +56,7 @@ hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed
 // [start[j], start[j+1]) (start has n+1 entries, owner one per block; owner
 // may be null when n == 1); out[2j] = sum of squared test residuals,
 // out[2j+1] = sum of squared test values.  part holds 2 doubles per block.
-int32_t test_blocks(int64_t n_test);
+int32_t test_blocks(int64_t n_test, int32_t rank);
 hipError_t launch_test_sums(const LossArgs *args, const int32_t *start, const int32_t *owner, int32_t n,
                             int32_t blocks, double *part, double *out, hipStream_t s);
 // End of a pool sweep, per running problem j (device state indexed by slot):

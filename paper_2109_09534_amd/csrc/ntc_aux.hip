@@ -5,6 +5,7 @@
 
 #include "ntc_aux.h"
 #include "ntc_bf16.h"
+#include "ntc_dev.h"
 #include "ntc_rng.h"
 
 namespace ntc {
@@ -27,72 +28,155 @@ __device__ __forceinline__ double block_sum(double v, double *s)
     return r;
 }
 
-// Prediction sum_r prod_m U_m[i_m, r] in FP64 from row offsets off[m] = i_m * R.
-template <bool VEC4>
-__device__ __forceinline__ double cpd_predict(const LossArgs &a, const uint32_t *off, int nm, int R)
+// The predictions sum_r prod_m U_m[i_m, r] of UN entries in FP64, from row
+// offsets off[u][m] = i_m * R, by the G lanes of their group (this lane is
+// q): each lane multiplies out its columns, then the group sums by DPP.
+// The UN entries' row loads are independent, so they are in flight
+// together.  Every lane of the group gets the same sums.  NM > 0 fixes the
+// number of modes at compile time; NM = 0 takes nm.
+template <int UN, int NM, class A>
+__device__ __forceinline__ void group_predict(const A &a, const uint32_t (&off)[UN][kMaxModes], int nm, int R,
+                                              int G, int q, double (&pred)[UN])
 {
-    double pred = 0.0;
-    if (VEC4) {
-        for (int r = 0; r < R; r += 4) {
-            double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
-            for (int m = 0; m < nm; ++m) {
-                const float4 u = *reinterpret_cast<const float4 *>(a.U[m] + off[m] + r);
-                p0 *= static_cast<double>(u.x);
-                p1 *= static_cast<double>(u.y);
-                p2 *= static_cast<double>(u.z);
-                p3 *= static_cast<double>(u.w);
+    constexpr int MM = NM > 0 ? NM : kMaxModes;
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+        pred[u] = 0.0;
+    if (R % 4 == 0) {
+        for (int c = 4 * q; c < R; c += 4 * G) {
+            double p[UN][4];
+#pragma unroll
+            for (int m = 0; m < MM; ++m) {
+                if (NM == 0 && m >= nm)
+                    break;
+                float4 v[UN];
+#pragma unroll
+                for (int u = 0; u < UN; ++u)
+                    v[u] = *reinterpret_cast<const float4 *>(a.U[m] + off[u][m] + c);
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    const double x0 = v[u].x, x1 = v[u].y, x2 = v[u].z, x3 = v[u].w;
+                    p[u][0] = m == 0 ? x0 : p[u][0] * x0;
+                    p[u][1] = m == 0 ? x1 : p[u][1] * x1;
+                    p[u][2] = m == 0 ? x2 : p[u][2] * x2;
+                    p[u][3] = m == 0 ? x3 : p[u][3] * x3;
+                }
             }
-            pred += p0;
-            pred += p1;
-            pred += p2;
-            pred += p3;
+#pragma unroll
+            for (int u = 0; u < UN; ++u)
+                pred[u] += (p[u][0] + p[u][1]) + (p[u][2] + p[u][3]);
         }
     } else {
-        for (int r = 0; r < R; ++r) {
-            double prod = 1.0;
-            for (int m = 0; m < nm; ++m)
-                prod *= static_cast<double>(a.U[m][off[m] + r]);
-            pred += prod;
+        for (int c = q; c < R; c += 16) {
+            double p[UN];
+#pragma unroll
+            for (int m = 0; m < MM; ++m) {
+                if (NM == 0 && m >= nm)
+                    break;
+                float v[UN];
+#pragma unroll
+                for (int u = 0; u < UN; ++u)
+                    v[u] = a.U[m][off[u][m] + c];
+#pragma unroll
+                for (int u = 0; u < UN; ++u)
+                    p[u] = m == 0 ? static_cast<double>(v[u]) : p[u] * static_cast<double>(v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < UN; ++u)
+                pred[u] += p[u];
         }
     }
-    return pred;
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+        double acc = pred[u];
+        if (G >= 2)
+            acc += dpp_f64<kDppXor1>(acc);
+        if (G >= 4)
+            acc += dpp_f64<kDppXor2>(acc);
+        if (G >= 8)
+            acc += dpp_f64<kDppHalfMirror>(acc);
+        if (G >= 16)
+            acc += dpp_f64<kDppMirror>(acc);
+        pred[u] = acc;
+    }
+}
+
+// Held-out sums over entries grp, grp + ngroups, ... of a test set, UN
+// entries per group step; an index past the end repeats the step's first
+// entry and is not counted.  The group's first lane keeps the sums.
+template <int UN, int NM, class A>
+__device__ __forceinline__ void test_sums(const A &a, int64_t grp, int64_t ngroups, int nm, int R, int G, int q,
+                                          double &tse, double &tsx)
+{
+    for (int64_t e0 = grp; e0 < a.n_test; e0 += UN * ngroups) {
+        uint32_t off[UN][kMaxModes];
+        float x[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int64_t e = e0 + u * ngroups < a.n_test ? e0 + u * ngroups : e0;
+            const int32_t *cc = a.test_coords + e * nm;
+#pragma unroll
+            for (int m = 0; m < (NM > 0 ? NM : kMaxModes); ++m)
+                off[u][m] = (NM > 0 || m < nm) ? static_cast<uint32_t>(cc[m]) * static_cast<uint32_t>(R) : 0u;
+            x[u] = a.test_values[e];
+        }
+        double pred[UN];
+        group_predict<UN, NM>(a, off, nm, R, G, q, pred);
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const double xv = static_cast<double>(x[u]);
+            const double res = xv - pred[u];
+            if (q == 0 && e0 + u * ngroups < a.n_test) {
+                tse += res * res;
+                tsx += xv * xv;
+            }
+        }
+    }
 }
 
 // Training entries are walked in mode-0 CSR order; each record carries the
 // other coordinates (times R) and the row (times R, in a spare record word or
-// a side array), so an entry needs no search.  Fixed grid and per-thread
-// order: the sums are deterministic.
-template <bool VEC4>
+// a side array), so an entry needs no search.  A group of lanes takes UN
+// entries at a time (entry_lanes); the group's first lane keeps the sums.
+// Fixed grid and per-thread order: the sums are deterministic.
+template <int NM>
 __global__ __launch_bounds__(kLossThreads) void k_loss_partials(const LossArgs a)
 {
+    constexpr int UN = 4;
     __shared__ double s[kLossThreads];
     const int R = a.R;
-    const int nm = a.nmodes;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int nm = NM > 0 ? NM : a.nmodes;
+    const int G = entry_lanes(R);
+    const int q = threadIdx.x & (G - 1);
+    const int64_t ngroups = static_cast<int64_t>(gridDim.x) * (blockDim.x / G);
+    const int64_t grp = static_cast<int64_t>(blockIdx.x) * (blockDim.x / G) + threadIdx.x / G;
     double sse = 0.0;
-    for (int64_t e = tid; e < a.nnz; e += stride) {
-        const uint32_t *rec = a.records0 + e * a.rec_words;
-        uint32_t off[kMaxModes];
-        off[0] = a.row0 ? a.row0[e] : rec[a.row_word];
-        for (int m = 1; m < nm; ++m)
-            off[m] = rec[m - 1];
-        const double pred = cpd_predict<VEC4>(a, off, nm, R);
-        const double res = static_cast<double>(__uint_as_float(rec[nm - 1])) - pred;
-        sse += res * res;
+    for (int64_t e0 = grp; e0 < a.nnz; e0 += UN * ngroups) {
+        uint32_t off[UN][kMaxModes];
+        float x[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int64_t e = e0 + u * ngroups < a.nnz ? e0 + u * ngroups : e0;
+            const uint32_t *rec = a.records0 + e * a.rec_words;
+            off[u][0] = a.row0 ? a.row0[e] : rec[a.row_word];
+#pragma unroll
+            for (int m = 1; m < (NM > 0 ? NM : kMaxModes); ++m)
+                off[u][m] = (NM > 0 || m < nm) ? rec[m - 1] : 0u;
+            x[u] = __uint_as_float(rec[nm - 1]);
+        }
+        double pred[UN];
+        group_predict<UN, NM>(a, off, nm, R, G, q, pred);
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const double res = static_cast<double>(x[u]) - pred[u];
+            if (q == 0 && e0 + u * ngroups < a.nnz)
+                sse += res * res;
+        }
     }
     double tse = 0.0, tsx = 0.0;
-    for (int64_t e = tid; e < a.n_test; e += stride) {
-        const int32_t *cc = a.test_coords + e * nm;
-        uint32_t off[kMaxModes];
-        for (int m = 0; m < nm; ++m)
-            off[m] = static_cast<uint32_t>(cc[m]) * static_cast<uint32_t>(R);
-        const double pred = cpd_predict<VEC4>(a, off, nm, R);
-        const double x = static_cast<double>(a.test_values[e]);
-        const double res = x - pred;
-        tse += res * res;
-        tsx += x * x;
-    }
+    test_sums<UN, NM>(a, grp, ngroups, nm, R, G, q, tse, tsx);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     double reg = 0.0;
     for (int m = 0; m < nm; ++m) {
         const int64_t cntm = a.dims[m] * R;
@@ -184,22 +268,12 @@ __global__ __launch_bounds__(kLossThreads) void k_test_partials_b(const LossArgs
     CLossArgs &a = ((CLossArgs *)args)[j];
     const int R = a.R;
     const int nm = a.nmodes;
+    const int G = entry_lanes(R);  // uniform over the block: it belongs to one entry
+    const int q = threadIdx.x & (G - 1);
+    const int per = blockDim.x / G;
     double tse = 0.0, tsx = 0.0;
-    for (int64_t e = static_cast<int64_t>(b) * blockDim.x + threadIdx.x; e < a.n_test;
-         e += static_cast<int64_t>(nb) * blockDim.x) {
-        const int32_t *cc = a.test_coords + e * nm;
-        double pred = 0.0;
-        for (int r = 0; r < R; ++r) {
-            double prod = 1.0;
-            for (int m = 0; m < nm; ++m)
-                prod *= static_cast<double>(a.U[m][static_cast<int64_t>(cc[m]) * R + r]);
-            pred += prod;
-        }
-        const double x = static_cast<double>(a.test_values[e]);
-        const double res = x - pred;
-        tse += res * res;
-        tsx += x * x;
-    }
+    test_sums<2, 0>(a, static_cast<int64_t>(b) * per + threadIdx.x / G, static_cast<int64_t>(nb) * per, nm, R, G, q,
+                    tse, tsx);
     tse = block_sum(tse, s);
     tsx = block_sum(tsx, s);
     if (threadIdx.x == 0) {
@@ -258,10 +332,12 @@ __global__ void k_pool_rule(const PoolRuleArgs a)
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s)
 {
-    if (a.R % 4 == 0)
-        hipLaunchKernelGGL(k_loss_partials<true>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+    if (a.nmodes == 3)
+        hipLaunchKernelGGL(k_loss_partials<3>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+    else if (a.nmodes == 4)
+        hipLaunchKernelGGL(k_loss_partials<4>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_loss_partials<false>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
+        hipLaunchKernelGGL(k_loss_partials<0>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -294,11 +370,12 @@ hipError_t launch_debug_sample(const int64_t *rowptr, int64_t row, uint64_t seed
     return hipGetLastError();
 }
 
-int32_t test_blocks(int64_t n_test)
+int32_t test_blocks(int64_t n_test, int32_t rank)
 {
-    const int64_t per = 16 * kLossThreads;
+    // about eight group-steps per thread, at most kMaxTestBlocks blocks
+    const int64_t per = 8 * (kLossThreads / entry_lanes(rank));
     const int64_t nb = (n_test + per - 1) / per;
-    return static_cast<int32_t>(nb < 1 ? 1 : nb > 64 ? 64 : nb);
+    return static_cast<int32_t>(nb < 1 ? 1 : nb > kMaxTestBlocks ? kMaxTestBlocks : nb);
 }
 
 hipError_t launch_test_sums(const LossArgs *args, const int32_t *start, const int32_t *owner, int32_t n,

@@ -160,7 +160,7 @@ struct ntc_pool {
     const int32_t *t_owner = nullptr;
     int32_t n_t = 0, t_blocks = 0;
     std::vector<int32_t> t_slot;  // test entry -> slot
-    double *t_part = nullptr;     // [2 * 64 * max_slots]
+    double *t_part = nullptr;     // [2 * kMaxTestBlocks * max_slots]
     double *t_out = nullptr;      // [2 * max_slots]
     // device state of the stop rule, per slot, and its pinned host copy
     int32_t *st_stop = nullptr;
@@ -337,7 +337,7 @@ ntc_status rebuild(ntc_pool *pool)
         a.R = v.rank;
         targs.push_back(a);
         tstart.push_back(tb);
-        const int32_t nb = ntc::test_blocks(v.n_test);
+        const int32_t nb = ntc::test_blocks(v.n_test, v.rank);
         towner.insert(towner.end(), static_cast<size_t>(nb), static_cast<int32_t>(targs.size() - 1));
         tb += nb;
         pool->t_slot.push_back(i);
@@ -493,7 +493,8 @@ ntc_status ntc_pool_create(ntc_pool_handle *out, const ntc_pool_params *p)
     pool->arena.reset(pool->arena_mem, cap);
     const size_t ms = static_cast<size_t>(q.max_slots);
     const size_t W1 = static_cast<size_t>(q.window) + 1;
-    if (hipMalloc(reinterpret_cast<void **>(&pool->t_part), ms * 64 * 2 * sizeof(double)) != hipSuccess ||
+    const size_t part_bytes = ms * ntc::kMaxTestBlocks * 2 * sizeof(double);
+    if (hipMalloc(reinterpret_cast<void **>(&pool->t_part), part_bytes) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&pool->t_out), ms * 2 * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&pool->st_stop), ms * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&pool->st_sweeps), ms * sizeof(int64_t)) != hipSuccess ||

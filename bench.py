@@ -214,7 +214,7 @@ def main():
         q.time_sweeps(args.steps)
         q.synchronize()
         wall_q = time.perf_counter() - t1
-        q.time_sweeps(1)     # the same sweep count as the main problem before its loss
+        q.time_sweeps(args.steps)  # the main problem's profiled sweeps: the same count before its loss
         loss_q = q.loss()
         q.close()
         other = {"gather": "bf16" if alt else "f32", "value": round(upd_sweep * args.steps / wall_q, 1),
@@ -329,12 +329,20 @@ def run_batch(args):
     pool = ntc.Pool(max_slots=n, window=5, tol=1e-4, max_sweeps=500)
     t0 = time.perf_counter()
     slots = []
-    for (dims, _, R, sd), p in zip(shapes, probs):
-        s = pool.admit(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
-                       test_values=p.test_values, schedule=schedule_of(R), **kw)
-        if s is None:
-            raise RuntimeError("the pool could not hold every problem")
-        slots.append(s)
+    # host preparation (CSR build, schedule) on worker threads, admission in
+    # submission order on this thread
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=max(1, args.prepare_threads)) as ex:
+        futs = [ex.submit(ntc.Prepared, p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
+                          test_values=p.test_values, schedule=schedule_of(R), **kw)
+                for (dims, _, R, sd), p in zip(shapes, probs)]
+        for f in futs:
+            q = f.result()
+            s = pool.admit_prepared(q)
+            q.close()
+            if s is None:
+                raise RuntimeError("the pool could not hold every problem")
+            slots.append(s)
     admit_s = time.perf_counter() - t0
     log(f"admitted {n} problems in {admit_s:.2f} s; {pool.info()}")
     t0 = time.perf_counter()

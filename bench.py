@@ -87,10 +87,12 @@ def main():
     ap.add_argument("--bf16", action="store_true", help="BF16 shadow gathers (precision form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve"], default="c1",
+    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "scaling"], default="c1",
                     help="c1: one 100M-entry problem (default); c2: one 4-way 500M-entry R=32 problem; "
                          "batch: many small problems in one pool; "
-                         "serve: Poisson arrivals into a pool")
+                         "serve: Poisson arrivals into a pool; "
+                         "scaling: the twin of the paper's timing workload, time per epoch per rank")
+    ap.add_argument("--ranks", default="10,30,50", help="scaling: ranks R")
     ap.add_argument("--instances", type=int, default=256, help="batch/serve: number of problems")
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-at-a-time baseline")
     ap.add_argument("--no-autotune", action="store_true",
@@ -112,6 +114,8 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "scaling":
+        return run_scaling(args)
 
     import numpy as np
 
@@ -269,6 +273,84 @@ def main():
     }
     if other is not None:
         out["other_precision"] = other
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------ scaling twin
+def run_scaling(args):
+    """Twin of the paper's timing workload (Section IV-C): 4-way
+    183x24x1140x1717, 3,309,490 uniform cells of a noiseless rank-10 CPD,
+    c = 0.5, MAX_INNER = 1; one epoch is ceil(1/c) = 2 sweeps.  Per rank R:
+    the GPU's time per epoch (mean of 5 epochs after a warm-up epoch), the FP64
+    oracle's time per epoch against its thread count, and the largest
+    difference of the factors after the first epoch from identical initial
+    factors (relative to each mode's largest entry)."""
+    import math
+
+    import numpy as np
+
+    import oracle as O
+    import paper_2109_09534_amd as ntc
+    import synth
+
+    ntc.lib()
+    O.build(force=False)
+    c, lam = 0.5, 1e-3
+    epoch = int(math.ceil(1.0 / c))
+    ranks = [int(r) for r in args.ranks.split(",") if r]
+    tmax = args.cpu_threads or len(os.sched_getaffinity(0))
+    thread_sweep = sorted({t for t in (1, 2, 4, 8, 16) if t < tmax} | {tmax})
+    t0 = time.perf_counter()
+    p = synth.scaling_twin(seed=args.seed)
+    gen_s = time.perf_counter() - t0
+    upd_sweep = _updates_per_sweep(p, c)
+    log(f"generated the 183x24x1140x1717 twin, {p.nnz} cells, in {gen_s:.1f} s; {upd_sweep} updates per sweep")
+    per_rank = []
+    for R in ranks:
+        init = synth.uniform_init(p.dims, R, 1, synth.init_scale(p.values, R, len(p.dims)))
+        g = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, seed=args.seed, init=init, stream=0)
+        g.sweep(epoch)  # the first epoch, from init: compared with the oracle's below
+        gf = g.all_factors()
+        g.time_sweeps(epoch)  # warm-up epoch
+        trials = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            g.time_sweeps(epoch)  # ends with a synchronisation
+            trials.append(time.perf_counter() - t1)
+        g.close()
+        gpu_s = sum(trials) / len(trials)
+        o = O.Oracle(p.dims, p.coords, p.values, R, c=c, lam=lam, seed=args.seed, init=init)
+        O.set_threads(tmax)
+        o.sweep(epoch)
+        diff = max(float(np.max(np.abs(gf[m] - o.factors(m))) / max(float(np.max(np.abs(o.factors(m)))), 1e-30))
+                   for m in range(len(p.dims)))
+        cpu = {}
+        for t in (thread_sweep if R == ranks[0] else [tmax]):
+            used = O.set_threads(t)
+            t1 = time.perf_counter()
+            o.sweep(epoch)
+            cpu[str(used)] = round(time.perf_counter() - t1, 4)
+        o.close()
+        row = {"R": R, "gpu_s_per_epoch": round(gpu_s, 6), "gpu_updates_per_s": round(epoch * upd_sweep / gpu_s, 1),
+               "oracle_s_per_epoch_by_threads": cpu, "first_epoch_max_rel_diff": diff}
+        log(f"R={R}: GPU {gpu_s * 1e3:.2f} ms per epoch; oracle {cpu} s per epoch; "
+            f"first-epoch factors differ by {diff:.2e}")
+        per_rank.append(row)
+    head = per_rank[0]
+    out = {
+        "metric": "time per epoch", "value": head["gpu_s_per_epoch"], "unit": "s/epoch", "n_gpus": 1,
+        "steps": 5, "warmup": 1, "ms_per_step": round(head["gpu_s_per_epoch"] * 1e3, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "twin of the Section IV-C timing workload: 4-way 183x24x1140x1717, 3,309,490 "
+                               "uniform cells, noiseless rank-10 CPD with U[0,1] factors; c=0.5, MAX_INNER=1, "
+                               f"1 epoch = {epoch} sweeps; value is R={head['R']}",
+                   "nnz_train": p.nnz, "seed": args.seed, "updates_per_sweep": upd_sweep},
+        "ranks": per_rank,
+        "cpu_baseline": {"value": head["oracle_s_per_epoch_by_threads"][str(tmax)], "unit": "s/epoch",
+                         "cores": tmax, "kind": "oracle",
+                         "sample": f"one epoch of the same workload at R={head['R']}, FP64"},
+        "generate_s": round(gen_s, 2),
+    }
     print(json.dumps(out), flush=True)
 
 

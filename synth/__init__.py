@@ -293,6 +293,14 @@ def c2(seed: int = 0, scale: float = 1.0) -> Problem:
                         value_model="clip0", test_frac=0.05, seed=seed, name="c2")
 
 
+def scaling_twin(seed: int = 0) -> Problem:
+    """Synthetic twin of the timing workload of Section IV-C: a 4-way
+    183x24x1140x1717 tensor with 3,309,490 uniformly placed observed cells of a
+    noiseless rank-10 CPD with i.i.d. U[0,1] factors; no held-out set."""
+    return make_problem((183, 24, 1140, 1717), 3_309_490, 10, zipf_s=None, noise_var=0.0,
+                        value_model="exact", test_frac=0.0, seed=seed, name="scaling")
+
+
 def c3_shapes(n_instances: int = 256, base_seed: int = 1000):
     """Size mixture of the batching workload: per instance dims log-U[50,2000],
     nnz log-U[10k,2M] capped at half the grid, rank from {8,16,32}."""

@@ -6,6 +6,7 @@ one sweep from identical iterates within 1e-5 relative (Frobenius, per mode)
 and element-wise within 1e-5 relative to the factor scale; final test RMSE
 within 1e-3 of the oracle's.
 """
+import functools
 import os
 import subprocess
 import sys
@@ -76,6 +77,11 @@ def test_device_sampler_is_bit_exact():
 
 
 # ---------------------------------------------------------- one-sweep parity
+@functools.lru_cache(maxsize=1)
+def _twin():
+    return synth.scaling_twin(seed=0)
+
+
 CASES = {
     "cpu_sized_r8": lambda: (synth.c0(seed=0), 8, dict(c=0.1)),
     "cpu_sized_r8_inner2": lambda: (synth.c0(seed=0), 8, dict(c=0.1, max_inner=2)),
@@ -105,6 +111,11 @@ CASES = {
     # rows split into more than 64 items: partial slots summed in groups first
     "r24_slot_groups": lambda: (synth.make_problem((60, 50, 40), 70_000, 8, seed=14, zipf_s=1.1), 24,
                                 dict(c=0.8, schedule={"item_samples": 16})),
+    # the twin of the paper's timing workload at full size (3.3M cells, c = 0.5), every rank it uses:
+    # 24 to 1717 rows per mode, so every row of modes 0 and 1 is split over many items
+    "scaling_twin_r10": lambda: (_twin(), 10, dict(c=0.5)),
+    "scaling_twin_r30": lambda: (_twin(), 30, dict(c=0.5)),
+    "scaling_twin_r50": lambda: (_twin(), 50, dict(c=0.5)),
 }
 
 

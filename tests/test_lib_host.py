@@ -141,3 +141,20 @@ def test_prepare_runs_on_the_host_and_bounds_its_bytes():
     co[0, 0] = bad.dims[0]
     with pytest.raises(ntc.NtcError):
         ntc.Prepared(bad.dims, co, bad.values, 3)
+
+
+def test_scaling_twin_is_the_timing_workload_of_section_iv_c():
+    """The twin of the paper's timing workload: 183x24x1140x1717, 3,309,490
+    distinct cells, values the noiseless rank-10 CPD of U[0,1] factors."""
+    p = synth.scaling_twin(seed=0)
+    assert p.dims == [183, 24, 1140, 1717] and p.nnz == 3_309_490 and p.test_values.shape[0] == 0
+    co = p.coords.astype(np.int64)
+    assert np.all(co >= 0) and np.all(co < np.asarray(p.dims))
+    key = ((co[:, 0] * 24 + co[:, 1]) * 1140 + co[:, 2]) * 1717 + co[:, 3]
+    assert np.unique(key).shape[0] == p.nnz
+    assert len(p.planted) == 4 and all(f.shape[1] == 10 and f.min() >= 0 and f.max() <= 1 for f in p.planted)
+    idx = np.arange(0, p.nnz, 9973)
+    ref = np.ones((idx.shape[0], 10))
+    for m in range(4):
+        ref *= p.planted[m][co[idx, m]]
+    np.testing.assert_allclose(p.values[idx], ref.sum(axis=1).astype(np.float32), rtol=0, atol=0)

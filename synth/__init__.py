@@ -301,6 +301,21 @@ def scaling_twin(seed: int = 0) -> Problem:
                         value_model="exact", test_frac=0.0, seed=seed, name="scaling")
 
 
+# E[x^2] of one entry of a rank-10 3-way CPD with i.i.d. U[0,1] factors:
+# 10 (1/3)^3 + 90 (1/8)^2
+_CPD10_3WAY_MEAN_SQ = 10.0 / 27.0 + 90.0 / 64.0
+
+
+def convergence_twin(seed: int = 0, snr: float = 100.0, nnz: int = 10_000_054) -> Problem:
+    """Synthetic twin of the convergence experiment of Section IV-B: a
+    71567x65133x730 tensor (the MovieLens 10M shape) with nnz uniformly
+    placed observed cells of a rank-10 CPD with i.i.d. U[0,1] factors plus
+    N(0, sigma^2) noise, sigma^2 set for the given SNR (the paper's ratio of
+    squared norms over the observed cells); 5% held out."""
+    return make_problem((71_567, 65_133, 730), nnz, 10, zipf_s=None, noise_var=_CPD10_3WAY_MEAN_SQ / snr,
+                        value_model="exact", test_frac=0.05, seed=seed, name=f"conv_snr{snr:g}")
+
+
 def c3_shapes(n_instances: int = 256, base_seed: int = 1000):
     """Size mixture of the batching workload: per instance dims log-U[50,2000],
     nnz log-U[10k,2M] capped at half the grid, rank from {8,16,32}."""

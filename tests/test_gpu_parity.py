@@ -82,6 +82,11 @@ def _twin():
     return synth.scaling_twin(seed=0)
 
 
+@functools.lru_cache(maxsize=1)
+def _conv():
+    return synth.convergence_twin(seed=0, snr=2.0)
+
+
 CASES = {
     "cpu_sized_r8": lambda: (synth.c0(seed=0), 8, dict(c=0.1)),
     "cpu_sized_r8_inner2": lambda: (synth.c0(seed=0), 8, dict(c=0.1, max_inner=2)),
@@ -116,6 +121,10 @@ CASES = {
     "scaling_twin_r10": lambda: (_twin(), 10, dict(c=0.5)),
     "scaling_twin_r30": lambda: (_twin(), 30, dict(c=0.5)),
     "scaling_twin_r50": lambda: (_twin(), 50, dict(c=0.5)),
+    # the twin of the convergence experiment at full size (71567x65133x730, 10M cells, SNR 2), with the
+    # extrapolated inner steps of the MAX_INNER study
+    "convergence_twin_c005_inner2": lambda: (_conv(), 10, dict(c=0.05, max_inner=2)),
+    "convergence_twin_c05_inner2": lambda: (_conv(), 10, dict(c=0.5, max_inner=2)),
 }
 
 

@@ -40,7 +40,8 @@ def kernel_name(kind: str, nmodes: int, R: int, bf16: bool) -> str:
         pairs = "true" if R % 2 == 0 else "false"
         return {"row_items": f"k_rows32<{nmodes}, {b}, {pairs}>", "row_finalize": f"k_finalize32<{b}>",
                 "row_reduce": "k_reduce_slots<32>"}[kind]
-    return {"row_items": f"k_row_items<64, {nmodes}, {b}>", "row_finalize": f"k_row_finalize<64, {b}>",
+    vec = 4 if R % 4 == 0 else 2 if R % 2 == 0 else 1
+    return {"row_items": f"k_rows64<{nmodes}, {b}, {vec}>", "row_finalize": f"k_row_finalize<64, {b}>",
             "row_reduce": "k_reduce_slots<64>"}[kind]
 
 

@@ -292,7 +292,14 @@ ntc_status alloc_or_fail(ntc_problem *h, void **dst, size_t bytes, const char *w
 
 ntc::KernelClass kernel_class(const ntc_problem *h)
 {
-    return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0, (h->RP == 32 && h->R % 2 == 0) ? 1 : 0};
+    // pairs: R <= 32, a lane reads its two columns as one pair (R even); R <= 64,
+    // 2 = four columns per load (R % 4 == 0), 1 = two (R even), 0 = one
+    int32_t pairs = 0;
+    if (h->RP == 32)
+        pairs = h->R % 2 == 0 ? 1 : 0;
+    else if (h->RP == 64)
+        pairs = h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
+    return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0, pairs};
 }
 
 ntc::RowArgs row_args(ntc_problem *h, int mode, int l)

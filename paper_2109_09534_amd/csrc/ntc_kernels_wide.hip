@@ -579,6 +579,265 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
     finish_row32<BF16>(a, it.row, lane, col, g, hd, y, s_v);
 }
 
+// ------------------------------------------------- wave-per-item (R <= 64)
+//
+// Rows with 33 <= R <= 64 and N <= 4: one wave per item (a whole row of at
+// most item_samples samples, or a chunk of a split row).  Four 16-lane
+// groups take one sample each per step; lane j owns columns 4j .. 4j+3.
+// With the columns ordered by c mod 4 (position 16 (c mod 4) + c / 4), H
+// splits into 16x16 blocks B(q1, q2)[i][j] = sum_s k_s[4i+q1] k_s[4j+q2];
+// the ten with q1 <= q2 take one v_mfma_f32_16x16x4f32 each per step (the
+// step's four samples are the K = 4 of the product).  Block sums go into FP64
+// (LDS) every 32 samples.  A split item writes its partial slot (g[64], H
+// row-major) for the slot sums and the finalize; a whole row assembles its
+// FP64 H row per lane and runs the power method and the step.
+// VEC: columns a lane reads per load (4 when R % 4 == 0, 2 when R is even).
+constexpr int kSlot64 = 64 + 64 * 64;
+
+// block index of (q1, q2), q1 <= q2, in the order (0,0) (0,1) (0,2) (0,3) (1,1) ...
+__device__ __forceinline__ int blk64(int q1, int q2)
+{
+    return q1 * 4 - (q1 * (q1 - 1)) / 2 + (q2 - q1);
+}
+
+template <int NM, bool BF16, int VEC>
+__global__ __launch_bounds__(64) void k_rows64(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    __shared__ uint4 s_rec[2 * 64];
+    __shared__ double s_h[40 * 64];  // block b, register v of lane l at (4 b + v) * 64 + l
+    __shared__ double s_g[4 * 64];   // gradient partial of column 4 j + q of group g at q * 64 + 16 g + j
+    __shared__ double s_v[64];
+    const Item it = a.items[blk_];
+    const int lane = threadIdx.x;
+    const int j = lane & 15;
+    const int grp = lane >> 4;
+    const int R = a.R;
+    const int cb = 4 * j;
+    bool live[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        live[q] = cb + q < R;
+
+    const int64_t base = a.rowptr[it.row];
+    const int64_t n = a.rowptr[it.row + 1] - base;
+    const Prp prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, it.row));
+    const float *ysrc = (a.l == 0) ? a.A : a.Y;
+    const int64_t roff = static_cast<int64_t>(it.row) * R;
+    float yq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        yq[q] = live[q] ? ysrc[roff + cb + q] : 0.0f;
+#pragma unroll
+    for (int v = 0; v < 40; ++v)
+        s_h[v * 64 + lane] = 0.0;
+    // columns past R read column 0 of the same row (never past its end: the
+    // zero row is the last row of the table) and are masked afterwards.
+    // VEC = 4 (R % 4 == 0): cb < R implies cb + 3 < R; VEC = 2 (R even): a
+    // pair starting below R ends below R.
+    uint32_t off[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        off[q] = live[q] ? cb + q : 0;
+    const uint32_t off4 = live[0] ? cb : 0;
+    const uint32_t off2[2] = {live[0] ? cb : 0u, live[2] ? cb + 2u : 0u};
+
+    struct Sub {
+        float f[NM - 1][2][4];
+    };
+    auto fetch = [&](int jb) {
+        uint4 w = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+        if (lane < it.j1 - jb) {
+            const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
+            w = *reinterpret_cast<const uint4 *>(a.records + (base + q) * 4);
+        }
+        return w;
+    };
+    // gathers of steps [s0, s0 + ns), ns <= 2, of a staged block (a missing sample reads the zero rows)
+    auto issue = [&](const uint4 *buf, int s0, int ns, Sub &S) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t < ns) {
+                const uint4 rec = buf[4 * (s0 + t) + grp];
+                const uint32_t rw[3] = {rec.x, rec.y, rec.z};
+#pragma unroll
+                for (int mm = 0; mm < NM - 1; ++mm) {
+                    float *d = S.f[mm][t];
+                    if (BF16) {
+                        const uint16_t *src = a.gath16[mm] + rw[mm];
+                        if (VEC == 4) {
+                            const uint2 w = *reinterpret_cast<const uint2 *>(src + off4);
+                            d[0] = __uint_as_float(w.x << 16);
+                            d[1] = __uint_as_float(w.x & 0xFFFF0000u);
+                            d[2] = __uint_as_float(w.y << 16);
+                            d[3] = __uint_as_float(w.y & 0xFFFF0000u);
+                        } else if (VEC == 2) {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const uint32_t w = *reinterpret_cast<const uint32_t *>(src + off2[h]);
+                                d[2 * h] = __uint_as_float(w << 16);
+                                d[2 * h + 1] = __uint_as_float(w & 0xFFFF0000u);
+                            }
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                d[q] = bf16_to_f32(src[off[q]]);
+                        }
+                    } else {
+                        const float *src = a.gath[mm] + rw[mm];
+                        if (VEC == 4) {
+                            const float4 w = *reinterpret_cast<const float4 *>(src + off4);
+                            d[0] = w.x;
+                            d[1] = w.y;
+                            d[2] = w.z;
+                            d[3] = w.w;
+                        } else if (VEC == 2) {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const float2 w = *reinterpret_cast<const float2 *>(src + off2[h]);
+                                d[2 * h] = w.x;
+                                d[2 * h + 1] = w.y;
+                            }
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                d[q] = src[off[q]];
+                        }
+                    }
+                }
+            }
+        }
+    };
+    float gf[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 acc[10];
+#pragma unroll
+    for (int b = 0; b < 10; ++b)
+        acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    auto compute = [&](const uint4 *buf, int s0, int ns, const Sub &S) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t < ns) {  // wave-uniform
+                float k[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float v = S.f[0][t][q];
+#pragma unroll
+                    for (int mm = 1; mm < NM - 1; ++mm)
+                        v *= S.f[mm][t][q];
+                    k[q] = live[q] ? v : 0.0f;
+                }
+                const uint4 rec = buf[4 * (s0 + t) + grp];
+                const uint32_t xw[4] = {rec.x, rec.y, rec.z, rec.w};
+                const float x = __uint_as_float(xw[NM - 1]);  // 0 for a missing sample
+                const float pred = row_sum_f32(fmaf(k[0], yq[0], fmaf(k[1], yq[1], fmaf(k[2], yq[2], k[3] * yq[3]))));
+                const float res = pred - x;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    gf[q] = fmaf(res, k[q], gf[q]);
+#pragma unroll
+                for (int q1 = 0; q1 < 4; ++q1)
+#pragma unroll
+                    for (int q2 = q1; q2 < 4; ++q2)
+                        acc[blk64(q1, q2)] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(k[q1], k[q2], acc[blk64(q1, q2)], 0, 0, 0);
+            }
+        }
+    };
+    // FP32 block sums of 32 samples go into FP64
+    auto flush = [&]() {
+#pragma unroll
+        for (int b = 0; b < 10; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                s_h[(4 * b + v) * 64 + lane] += static_cast<double>(acc[b][v]);
+                acc[b][v] = 0.0f;
+            }
+    };
+    auto nsteps = [&](int jb, int sub) {  // valid steps of sub-batch `sub` (2 steps) of the block at jb
+        const int steps = (min(64, it.j1 - jb) + 3) >> 2;
+        return max(0, min(2, steps - 2 * sub));
+    };
+
+    // software pipeline: records of the next block of 64 samples in flight
+    // during this one, gathers of the next sub-batch during this one
+    Sub SA, SB;
+    int buf = 0;
+    if (it.j0 < it.j1) {
+        const uint4 w = fetch(it.j0);
+        s_rec[lane] = w;
+        __builtin_amdgcn_wave_barrier();
+        issue(s_rec, 0, nsteps(it.j0, 0), SA);
+    }
+    for (int jb = it.j0; jb < it.j1; jb += 64) {
+        const bool more = jb + 64 < it.j1;
+        uint4 wn = make_uint4(0u, 0u, 0u, 0u);
+        if (more)
+            wn = fetch(jb + 64);
+        const uint4 *cur = s_rec + 64 * buf;
+#pragma unroll
+        for (int sp = 0; sp < 8; sp += 2) {
+            issue(cur, 2 * (sp + 1), nsteps(jb, sp + 1), SB);
+            compute(cur, 2 * sp, nsteps(jb, sp), SA);
+            if (sp + 2 < 8) {
+                issue(cur, 2 * (sp + 2), nsteps(jb, sp + 2), SA);
+            } else if (more) {
+                uint4 *nxt = s_rec + 64 * (buf ^ 1);
+                nxt[lane] = wn;
+                __builtin_amdgcn_wave_barrier();
+                issue(nxt, 0, nsteps(jb + 64, 0), SA);
+            }
+            compute(cur, 2 * (sp + 1), nsteps(jb, sp + 1), SB);
+            if (sp == 2 || sp == 6)
+                flush();
+        }
+        __builtin_amdgcn_wave_barrier();  // this block's reads of s_rec come before its next staging
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        s_g[q * 64 + lane] = static_cast<double>(gf[q]);
+    __builtin_amdgcn_wave_barrier();
+    // gradient of column c: the four groups' partials in group order
+    auto gsum = [&](int c) {
+        const int q = c & 3, jj = c >> 2;
+        return ((s_g[q * 64 + jj] + s_g[q * 64 + 16 + jj]) + s_g[q * 64 + 32 + jj]) + s_g[q * 64 + 48 + jj];
+    };
+
+    if (it.slot >= 0) {
+        // partial slot, row-major: this lane's block entries D[4 (l / 16) + v][l % 16] of B(q1, q2)
+        // are H[4 (4 grp + v) + q1][4 j + q2], and their transposes
+        double *P = a.partials + static_cast<int64_t>(it.slot) * kSlot64;
+        P[lane] = gsum(lane);
+#pragma unroll
+        for (int q1 = 0; q1 < 4; ++q1)
+#pragma unroll
+            for (int q2 = q1; q2 < 4; ++q2)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double val = s_h[(4 * blk64(q1, q2) + v) * 64 + lane];
+                    const int r = 4 * (4 * grp + v) + q1, c = cb + q2;
+                    P[64 + r * 64 + c] = val;
+                    if (q1 != q2)
+                        P[64 + c * 64 + r] = val;
+                }
+        return;
+    }
+    // whole row: lane r takes row r of H (position (q1, i) with r = 4 i + q1)
+    const int r = lane, q1 = r & 3, i = r >> 2;
+    double h[64];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+        const int q2 = c & 3, jj = c >> 2;
+        // q1 <= q2: B(q1, q2)[i][jj]; else the transpose B(q2, q1)[jj][i]
+        const int lo = q1 <= q2 ? q1 : q2, hi = q1 <= q2 ? q2 : q1;
+        const int ri = q1 <= q2 ? i : jj, ci = q1 <= q2 ? jj : i;
+        h[c] = s_h[(4 * blk64(lo, hi) + (ri & 3)) * 64 + 16 * (ri >> 2) + ci];
+    }
+    const double g = gsum(r);
+    const float y = r < R ? ysrc[roff + r] : 0.0f;
+    finish_row<64, BF16>(a, it.row, lane, g, h, y, s_v);
+}
+
 // Split rows with 17 <= R <= 32: a 256-thread block sums the row's partial
 // slots, thread t taking entries t, t + 256, ... of the slot in slot order
 // (coalesced, a fixed order per entry), then its first wave runs the power
@@ -641,6 +900,18 @@ hipError_t go_rows32(const KernelClass &kc, const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
+template <bool BF16, int VEC>
+hipError_t go_rows64(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.nmodes == 3)
+        NTC_GO((k_rows64<3, BF16, VEC>), 64);
+    else if (kc.nmodes == 4)
+        NTC_GO((k_rows64<4, BF16, VEC>), 64);
+    else
+        NTC_GO((k_rows64<2, BF16, VEC>), 64);
+    return hipGetLastError();
+}
+
 template <bool BF16>
 hipError_t go_rows(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
@@ -652,12 +923,14 @@ hipError_t go_rows(const KernelClass &kc, const Launch &L, hipStream_t s)
         else
             return go_rows32<BF16, false>(kc, L, s);
     } else if (kc.rp == 64) {
-        if (kc.nmodes == 3)
-            NTC_GO((k_row_items<64, 3, BF16>), 64);
-        else if (kc.nmodes == 4)
-            NTC_GO((k_row_items<64, 4, BF16>), 64);
-        else
+        if (kc.nmodes > 4)
             NTC_GO((k_row_items<64, 0, BF16>), 64);
+        else if (kc.pairs == 2)
+            return go_rows64<BF16, 4>(kc, L, s);
+        else if (kc.pairs == 1)
+            return go_rows64<BF16, 2>(kc, L, s);
+        else
+            return go_rows64<BF16, 1>(kc, L, s);
     } else {
         return hipErrorInvalidValue;
     }

@@ -116,6 +116,15 @@ CASES = {
     # rows split into more than 64 items: partial slots summed in groups first
     "r24_slot_groups": lambda: (synth.make_problem((60, 50, 40), 70_000, 8, seed=14, zipf_s=1.1), 24,
                                 dict(c=0.8, schedule={"item_samples": 16})),
+    # 33 <= R <= 64, N <= 4: four columns per lane (one load of four, two pairs, or four singles),
+    # whole rows finished in the kernel, heavy rows through partial slots
+    "r40_3way_quads": lambda: (synth.make_problem((300, 200, 100), 150_000, 10, seed=15, zipf_s=1.1), 40,
+                               dict(c=0.3)),
+    "r64_4way_inner2": lambda: (synth.make_problem((80, 60, 50, 40), 100_000, 12, seed=16), 64,
+                                dict(c=0.4, max_inner=2)),
+    "r33_matrix_singles": lambda: (synth.make_problem((400, 300), 60_000, 8, seed=17), 33, dict(c=0.3)),
+    "r46_slot_groups": lambda: (synth.make_problem((60, 50, 40), 70_000, 8, seed=18, zipf_s=1.1), 46,
+                                dict(c=0.8, schedule={"item_samples": 16})),
     # the twin of the paper's timing workload at full size (3.3M cells, c = 0.5), every rank it uses:
     # 24 to 1717 rows per mode, so every row of modes 0 and 1 is split over many items
     "scaling_twin_r10": lambda: (_twin(), 10, dict(c=0.5)),
@@ -181,6 +190,16 @@ def test_bf16_gathers_final_rmse_within_1e3_of_oracle():
     o.sweep(19)
     lg, lo = g.loss(), o.loss()
     _say(f"  BF16 GPU loss {lg}, oracle {lo}")
+    assert abs(lg[2] - lo[2]) <= 1e-3
+
+
+def test_bf16_gathers_at_r_above_32_stay_within_1e3_of_oracle():
+    p = synth.make_problem((200, 150, 100), 120_000, 10, seed=19, test_frac=0.1)
+    g, o, init = _pair(p, 48, c=0.2, gather_bf16=True)
+    g.sweep(10)
+    o.sweep(10)
+    lg, lo = g.loss(), o.loss()
+    _say(f"  R=48 BF16 GPU loss {lg}, oracle {lo}")
     assert abs(lg[2] - lo[2]) <= 1e-3
 
 

@@ -81,6 +81,9 @@ def lib():
                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _i32p]
         L.ora_power_lmax.restype = ctypes.c_double
         L.ora_power_lmax.argtypes = [_f64p, ctypes.c_int, ctypes.c_int]
+        L.ora_lmax_cw.restype = ctypes.c_double
+        L.ora_lmax_cw.argtypes = [_f64p, ctypes.c_int, ctypes.c_int]
+        L.ora_set_lp_bound.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.ora_row_step.restype = ctypes.c_int64
         L.ora_row_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _f64p, _f64p,
                                    _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -145,6 +148,13 @@ def power_lmax(H: np.ndarray, iters: int = 20) -> float:
     return float(lib().ora_power_lmax(_p(H, _f64p), H.shape[0], iters))
 
 
+def lmax_cw(H: np.ndarray, iters: int = 20) -> float:
+    """Collatz-Wielandt upper bound max_i (H v)_i / v_i at the power method's
+    `iters`-th normalised iterate (v_0 = ones / sqrt(R))."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    return float(lib().ora_lmax_cw(_p(H, _f64p), H.shape[0], iters))
+
+
 def set_threads(n: int) -> int:
     return int(lib().ora_set_threads(n))
 
@@ -156,7 +166,8 @@ class Oracle:
     def __init__(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *,
                  c: float = 0.1, lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20,
                  seed: int = 0, test_coords: Optional[np.ndarray] = None,
-                 test_values: Optional[np.ndarray] = None, init: Optional[Sequence[np.ndarray]] = None):
+                 test_values: Optional[np.ndarray] = None, init: Optional[Sequence[np.ndarray]] = None,
+                 lp_bound: int = 0):
         L = lib()
         self.dims = [int(d) for d in dims]
         self.N = len(self.dims)
@@ -182,7 +193,9 @@ class Oracle:
         if not h:
             raise ValueError("oracle rejected the problem")
         self._h = ctypes.c_void_p(h)
+        L.ora_set_lp_bound(self._h, int(lp_bound))
         self.c, self.lam, self.max_inner, self.power_iters, self.seed = c, lam, max_inner, power_iters, seed
+        self.lp_bound = int(lp_bound)
 
     def close(self):
         if getattr(self, "_h", None):

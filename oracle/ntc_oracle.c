@@ -29,6 +29,12 @@
  *     the permutation's first B_{l,p} images, summed in that order;
  *   - the power method starts at 1/sqrt(R) * ones, runs T_pow normalised
  *     products and returns the Rayleigh quotient;
+ *   - optional estimator (the paper leaves better L_p estimates open,
+ *     Section III): the Collatz-Wielandt upper bound of the same iterate,
+ *     L_p = max_i (H v)_i / v_i over the i with v_i > 0.  H is entrywise
+ *     nonnegative here (a Gram matrix of nonnegative rows plus lambda I), so
+ *     by the Collatz-Wielandt formula this is >= lambda_max(H) for every
+ *     positive v, and it is the largest row sum of H when T_pow = 0;
  *   - lambda is not scaled by c; rows with B_{l,p} = 0, or with L_p <= 0,
  *     keep A and Y unchanged;
  *   - Nesterov restarts at every S_NMC call; Y is discarded on return;
@@ -67,6 +73,7 @@ typedef struct ora {
     double *U[ORA_MAXN];     /* factors, row-major [I_m][R] */
     double c, lambda;
     int max_inner, power_iters;
+    int lp_bound; /* 0: Rayleigh quotient of the power iterate; 1: Collatz-Wielandt bound */
     uint64_t seed;
     int64_t k; /* AO sweep counter */
     int64_t n_test;
@@ -249,6 +256,43 @@ double ora_power_lmax(const double *H, int R, int T)
     return rq;
 }
 
+/* L as the Collatz-Wielandt upper bound max_i (H v)_i / v_i at the power
+ * method's T-th normalised iterate (v_0 = ones/sqrt(R)), over the i with
+ * v_i > 0; 0 if H v vanishes. */
+double ora_lmax_cw(const double *H, int R, int T)
+{
+    double v[ORA_MAXR], w[ORA_MAXR];
+    for (int r = 0; r < R; ++r)
+        v[r] = 1.0 / sqrt((double)R);
+    for (int t = 0; t < T; ++t) {
+        double nrm2 = 0.0;
+        for (int r = 0; r < R; ++r) {
+            double s = 0.0;
+            for (int q = 0; q < R; ++q)
+                s += H[r * R + q] * v[q];
+            w[r] = s;
+            nrm2 += s * s;
+        }
+        if (!(nrm2 > 0.0))
+            return 0.0;
+        double nrm = sqrt(nrm2);
+        for (int r = 0; r < R; ++r)
+            v[r] = w[r] / nrm;
+    }
+    double best = 0.0;
+    for (int r = 0; r < R; ++r) {
+        if (!(v[r] > 0.0))
+            continue;
+        double s = 0.0;
+        for (int q = 0; q < R; ++q)
+            s += H[r * R + q] * v[q];
+        double ratio = s / v[r];
+        if (ratio > best)
+            best = ratio;
+    }
+    return best;
+}
+
 /* ----------------------------------------------------------------- set-up */
 static void build_csr(ora_t *o, int m)
 {
@@ -418,7 +462,7 @@ int64_t ora_row_step(const ora_t *o, int i, int l, int64_t p, const double *y, c
         g[r] += o->lambda * y[r];
         H[r * R + r] += o->lambda;
     }
-    double L = ora_power_lmax(H, R, o->power_iters);
+    double L = o->lp_bound ? ora_lmax_cw(H, R, o->power_iters) : ora_power_lmax(H, R, o->power_iters);
     double beta = 0.0;
     if (g_out)
         memcpy(g_out, g, sizeof(double) * (size_t)R);
@@ -583,6 +627,10 @@ void ora_set_factors(ora_t *o, int m, const double *in)
 }
 int64_t ora_get_sweep(const ora_t *o) { return o->k; }
 void ora_set_sweep(ora_t *o, int64_t k) { o->k = k; }
+
+/* 0: L_p is the Rayleigh quotient of the power iterate; 1: the
+ * Collatz-Wielandt upper bound of the same iterate. */
+void ora_set_lp_bound(ora_t *o, int bound) { o->lp_bound = bound ? 1 : 0; }
 void ora_get_csr(const ora_t *o, int m, int64_t *rowptr_out, int64_t *perm_out)
 {
     memcpy(rowptr_out, o->rowptr[m], (size_t)(o->dims[m] + 1) * sizeof(int64_t));

@@ -231,6 +231,47 @@ def test_power_method_matches_eigvalsh_and_closed_forms():
     assert O.power_lmax(H, 0) == pytest.approx(np.ones(2) @ H @ np.ones(2) / 2)
 
 
+def test_collatz_wielandt_bound_brackets_lambda_max():
+    """For entrywise nonnegative H and any positive v, lambda_max <= max_r
+    (H v)_r / v_r (Collatz-Wielandt); at v = ones it is the largest row sum,
+    and along the power iterates it converges to lambda_max."""
+    rng = np.random.default_rng(1)
+    for R in [1, 2, 3, 8, 16, 33, 50, 64]:
+        for b in [1, 3, 20, 200]:
+            K = rng.random((b, R)) * rng.random((b, R))
+            H = K.T @ K + 1e-3 * np.eye(R)
+            ev = np.linalg.eigvalsh(H).max()
+            assert O.lmax_cw(H, 0) == pytest.approx(H.sum(axis=1).max(), rel=1e-14)
+            for T in [0, 1, 2, 5, 20]:
+                assert O.lmax_cw(H, T) >= ev * (1 - 1e-13), (R, b, T)
+            # with a spectral gap the bound meets lambda_max along the iterates
+            if b >= 20 or R == 1:
+                assert O.lmax_cw(H, 400) == pytest.approx(ev, rel=1e-9), (R, b)
+    # a diagonal H: every iterate has ratio d_r in coordinate r, the bound is max d exactly
+    d = np.array([0.5, 4.0, 2.0, 3.5])
+    for T in [0, 3, 20]:
+        assert O.lmax_cw(np.diag(d), T) == pytest.approx(4.0, rel=1e-15)
+    assert O.lmax_cw(np.zeros((3, 3)), 5) == 0.0
+
+
+def test_collatz_wielandt_steps_meet_the_rayleigh_steps_when_the_iterate_converges():
+    """With many power iterations both estimators give lambda_max, so one sweep
+    with either is the same up to rounding; with few iterations the bound is
+    larger, so every step is a shorter (safe) projected step."""
+    p = synth.c0(seed=2)
+    init = synth.uniform_init(p.dims, 8, 3, synth.init_scale(p.values, 8, 3))
+    runs = {}
+    for bound, T in [(0, 400), (1, 400), (0, 2), (1, 2)]:
+        o = O.Oracle(p.dims, p.coords, p.values, 8, c=0.5, power_iters=T, init=init, lp_bound=bound)
+        o.sweep(1)
+        runs[(bound, T)] = [o.factors(m) for m in range(3)]
+        o.close()
+    for m in range(3):
+        a, b = runs[(0, 400)][m], runs[(1, 400)][m]
+        assert np.max(np.abs(a - b)) <= 1e-9 * np.max(np.abs(a))
+    assert any(np.max(np.abs(runs[(0, 2)][m] - runs[(1, 2)][m])) > 1e-6 for m in range(3))
+
+
 def test_beta_and_step_closed_form_on_one_row():
     p, o, U = _row_setup(c=1.0)
     mode, row = 1, 2

@@ -96,6 +96,13 @@ def main():
                          "convergence: the twin of the paper's convergence experiment, RRE per epoch")
     ap.add_argument("--epochs", type=int, default=100, help="convergence: epochs per run")
     ap.add_argument("--oracle-epochs", type=int, default=4, help="convergence: epochs the oracle repeats")
+    ap.add_argument("--estimators", default="rq20",
+                    help="convergence: L_p estimators, comma separated: rqT = Rayleigh quotient after T power "
+                         "iterations (the paper's), cwT = Collatz-Wielandt bound of the same iterate")
+    ap.add_argument("--inner", default="1,2", help="convergence: MAX_INNER values")
+    ap.add_argument("--lp-bound", type=int, default=0,
+                    help="c1/c2: 1 = L_p as the Collatz-Wielandt bound of the power iterate")
+    ap.add_argument("--power-iters", type=int, default=20, help="c1/c2: power iterations T_pow")
     ap.add_argument("--ranks", default="10,30,50", help="scaling: ranks R")
     ap.add_argument("--instances", type=int, default=256, help="batch/serve: number of problems")
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-at-a-time baseline")
@@ -149,7 +156,8 @@ def main():
 
     t0 = time.perf_counter()
     prob = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=max_inner, seed=args.seed,
-                       gather_bf16=args.bf16, test_coords=p.test_coords, test_values=p.test_values, stream=0)
+                       gather_bf16=args.bf16, test_coords=p.test_coords, test_values=p.test_values, stream=0,
+                       power_iters=args.power_iters, lp_bound=args.lp_bound)
     create_s = time.perf_counter() - t0
     upd_sweep, rows_sweep = prob.work()
     log(f"ntc_create {create_s:.1f} s; {upd_sweep} sampled entries and {rows_sweep} row steps per sweep")
@@ -216,7 +224,8 @@ def main():
         prob.close()
         alt = not args.bf16
         q = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=max_inner, seed=args.seed,
-                        gather_bf16=alt, test_coords=p.test_coords, test_values=p.test_values, stream=0)
+                        gather_bf16=alt, test_coords=p.test_coords, test_values=p.test_values, stream=0,
+                        power_iters=args.power_iters, lp_bound=args.lp_bound)
         if args.warmup > 0:
             q.time_sweeps(args.warmup)
         q.synchronize()
@@ -262,7 +271,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if not args.bf16 else "bf16-gather/f32",
         "data": "synthetic",
-        "config": {"workload": wl + (" (BF16 gathers)" if args.bf16 else ""),
+        "config": {"workload": wl + (" (BF16 gathers)" if args.bf16 else "")
+                   + ("" if (args.lp_bound, args.power_iters) == (0, 20) else
+                      f" (L_p: {'Collatz-Wielandt bound' if args.lp_bound else 'Rayleigh quotient'}, "
+                      f"T_pow={args.power_iters})"),
                    "nnz_train": p.nnz, "scale": args.scale, "seed": args.seed,
                    "updates_per_sweep": upd_sweep, "row_steps_per_sweep": rows_sweep},
         "pct_hbm_peak": round(100 * hbm_frac, 2),
@@ -382,8 +394,15 @@ def run_convergence(args):
     R, lam = 10, 1e-3
     snrs = {"S1": 100.0, "S2": 2.0}
     cs = (0.05, 0.2, 0.5)
-    inners = (1, 2)
-    checks = {("S1", 0.5, 1), ("S2", 0.05, 2)}
+    inners = tuple(int(x) for x in args.inner.split(",") if x)
+    ests = []
+    for e in args.estimators.split(","):
+        e = e.strip()
+        if e[:2] not in ("rq", "cw"):
+            raise SystemExit(f"unknown estimator {e}")
+        ests.append((e, 1 if e[:2] == "cw" else 0, int(e[2:])))
+    checks = {("S1", 0.5, 1, ests[0][0]), ("S2", 0.05, 2, ests[0][0])} | {("S1", 0.2, inners[0], e[0])
+                                                                             for e in ests[1:]}
     runs, oracle_checks = [], []
     gen_s = 0.0
     for name, snr in snrs.items():
@@ -391,48 +410,53 @@ def run_convergence(args):
         p = synth.convergence_twin(seed=args.seed, snr=snr)
         gen_s += time.perf_counter() - t0
         log(f"{name}: generated {p.nnz} train / {p.test_values.shape[0]} test entries, SNR {p.snr:.2f}")
-        for c in cs:
+        for (est, lpb, T), c, mi in [(e, c, mi) for e in ests for c in cs for mi in inners]:
             spe = int(math.ceil(1.0 / c))
-            for mi in inners:
-                g = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=mi, seed=args.seed,
-                                test_coords=p.test_coords, test_values=p.test_values, stream=0)
-                rre = [float(g.loss()[3])]
-                t1 = time.perf_counter()
-                sweep_s = 0.0
-                for _ in range(args.epochs):
-                    t2 = time.perf_counter()
-                    g.sweep(spe)
-                    g.synchronize()
-                    sweep_s += time.perf_counter() - t2
-                    rre.append(float(g.loss()[3]))
-                wall = time.perf_counter() - t1
-                g.close()
-                run = {"data": name, "snr": round(p.snr, 3), "c": c, "max_inner": mi, "sweeps_per_epoch": spe,
-                       "gpu_s_per_epoch": round(sweep_s / args.epochs, 6), "wall_s": round(wall, 3),
-                       "rre": [round(x, 6) for x in rre]}
-                runs.append(run)
-                log(f"{name} c={c} MAX_INNER={mi}: RRE {rre[0]:.4f} -> {rre[min(10, args.epochs)]:.4f} (10 epochs) "
-                    f"-> {rre[-1]:.4f} ({args.epochs} epochs); {run['gpu_s_per_epoch'] * 1e3:.2f} ms per epoch")
-                if (name, c, mi) in checks and args.oracle_epochs > 0:
-                    o = O.Oracle(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=mi, seed=args.seed,
-                                 test_coords=p.test_coords, test_values=p.test_values)
-                    orre = [float(o.loss()[3])]
-                    t2 = time.perf_counter()
-                    for _ in range(args.oracle_epochs):
-                        o.sweep(spe)
-                        orre.append(float(o.loss()[3]))
-                    o_s = time.perf_counter() - t2
-                    o.close()
-                    diff = max(abs(a - b) for a, b in zip(orre, rre))
-                    oracle_checks.append({"data": name, "c": c, "max_inner": mi, "epochs": args.oracle_epochs,
-                                          "oracle_rre": [round(x, 6) for x in orre], "max_abs_rre_diff": diff,
-                                          "oracle_s_per_epoch": round(o_s / args.oracle_epochs, 3),
-                                          "threads": tmax})
-                    log(f"  oracle, {args.oracle_epochs} epochs: max |RRE difference| {diff:.2e}, "
-                        f"{o_s / args.oracle_epochs:.2f} s per epoch on {tmax} threads")
+            g = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=mi, seed=args.seed,
+                            test_coords=p.test_coords, test_values=p.test_values, stream=0,
+                            power_iters=T, lp_bound=lpb)
+            rre = [float(g.loss()[3])]
+            t1 = time.perf_counter()
+            sweep_s = 0.0
+            for _ in range(args.epochs):
+                t2 = time.perf_counter()
+                g.sweep(spe)
+                g.synchronize()
+                sweep_s += time.perf_counter() - t2
+                rre.append(float(g.loss()[3]))
+            wall = time.perf_counter() - t1
+            g.close()
+            run = {"data": name, "snr": round(p.snr, 3), "estimator": est, "c": c, "max_inner": mi,
+                   "sweeps_per_epoch": spe,
+                   "gpu_s_per_epoch": round(sweep_s / args.epochs, 6), "wall_s": round(wall, 3),
+                   "rre": [round(x, 6) for x in rre]}
+            runs.append(run)
+            log(f"{name} {est} c={c} MAX_INNER={mi}: RRE {rre[0]:.4f} -> {rre[min(10, args.epochs)]:.4f} "
+                f"(10 epochs) -> {rre[-1]:.4f} ({args.epochs} epochs); "
+                f"{run['gpu_s_per_epoch'] * 1e3:.2f} ms per epoch")
+            if (name, c, mi, est) in checks and args.oracle_epochs > 0:
+                o = O.Oracle(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=mi, seed=args.seed,
+                             test_coords=p.test_coords, test_values=p.test_values, power_iters=T,
+                             lp_bound=lpb)
+                orre = [float(o.loss()[3])]
+                t2 = time.perf_counter()
+                for _ in range(args.oracle_epochs):
+                    o.sweep(spe)
+                    orre.append(float(o.loss()[3]))
+                o_s = time.perf_counter() - t2
+                o.close()
+                diff = max(abs(a - b) for a, b in zip(orre, rre))
+                oracle_checks.append({"data": name, "estimator": est, "c": c, "max_inner": mi,
+                                      "epochs": args.oracle_epochs,
+                                      "oracle_rre": [round(x, 6) for x in orre], "max_abs_rre_diff": diff,
+                                      "oracle_s_per_epoch": round(o_s / args.oracle_epochs, 3),
+                                      "threads": tmax})
+                log(f"  oracle, {args.oracle_epochs} epochs: max |RRE difference| {diff:.2e}, "
+                    f"{o_s / args.oracle_epochs:.2f} s per epoch on {tmax} threads")
+
     def final(name, c, mi, e):
         for r in runs:
-            if r["data"] == name and r["c"] == c and r["max_inner"] == mi:
+            if r["data"] == name and r["c"] == c and r["max_inner"] == mi and r["estimator"] == ests[0][0]:
                 return r["rre"][min(e, len(r["rre"]) - 1)]
         return None
     # the paper's reading of its figure: small c pays at high SNR, not at low SNR

@@ -80,7 +80,10 @@ typedef struct ntc_params {
     int32_t group_max;          /* schedule (R <= 16): rows with tiny_max < B_p <= group_max run
                                    one row per 16-lane group, longer ones as 256-thread chunks of
                                    item_samples entries (0 = default 512) */
-    int32_t reserved1;
+    int32_t lp_bound;           /* L_p estimator: 0 = Rayleigh quotient of the T_pow-th power iterate
+                                   (default); 1 = Collatz-Wielandt upper bound max_i (H v)_i / v_i of
+                                   the same iterate (>= lambda_max for the nonnegative H here, so a
+                                   shorter, safe step; with power_iters = 0 the largest row sum of H) */
 } ntc_params;
 
 /* Fill *p with defaults: c = 0.1, lambda = 1e-3, max_inner = 1,

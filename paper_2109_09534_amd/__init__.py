@@ -68,7 +68,7 @@ class _Params(ctypes.Structure):
         ("item_samples", ctypes.c_int32),
         ("overlap", ctypes.c_int32),
         ("group_max", ctypes.c_int32),
-        ("reserved1", ctypes.c_int32),
+        ("lp_bound", ctypes.c_int32),
     ]
 
 
@@ -206,12 +206,14 @@ def host_csr(dims: Sequence[int], coords: np.ndarray, mode: int):
     return rp, perm[:nnz]
 
 
-def _make_params(N, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords, test_values, init, schedule):
+def _make_params(N, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords, test_values, init, schedule,
+                 lp_bound=0):
     """ntc_params for ntc_create / ntc_pool_admit, plus the arrays it points into."""
     prm = _Params()
     lib().ntc_params_default(ctypes.byref(prm))
     prm.c, prm.lam, prm.max_inner, prm.power_iters, prm.seed = c, lam, max_inner, power_iters, seed
     prm.gather_bf16 = 1 if gather_bf16 else 0
+    prm.lp_bound = int(lp_bound)
     for key, val in (schedule or {}).items():
         if key not in ("tiny_max", "item_samples", "overlap", "group_max"):
             raise ValueError(f"unknown schedule field {key}")
@@ -279,7 +281,8 @@ class Problem:
                  c: float = 0.1, lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
                  gather_bf16: bool = False, test_coords: Optional[np.ndarray] = None,
                  test_values: Optional[np.ndarray] = None, init: Optional[Sequence[np.ndarray]] = None,
-                 stream=None, torch_allocator: bool = False, schedule: Optional[dict] = None):
+                 stream=None, torch_allocator: bool = False, schedule: Optional[dict] = None,
+                 lp_bound: int = 0):
         L = lib()
         self.dims = [int(d) for d in dims]
         self.N = len(self.dims)
@@ -290,7 +293,7 @@ class Problem:
         if co.ndim != 2 or co.shape[1] != self.N or co.shape[0] != va.shape[0]:
             raise ValueError("coords must be [nnz, nmodes] and values [nnz]")
         prm, keep = _make_params(self.N, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords,
-                                 test_values, init, schedule)
+                                 test_values, init, schedule, lp_bound)
         keep += [d, co, va]
         if torch_allocator or (stream is not None and not isinstance(stream, int)):
             _require_single_runtime()
@@ -449,14 +452,14 @@ class Prepared:
     def __init__(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *, c: float = 0.1,
                  lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
                  gather_bf16: bool = False, test_coords=None, test_values=None, init=None,
-                 schedule: Optional[dict] = None):
+                 schedule: Optional[dict] = None, lp_bound: int = 0):
         d = np.asarray([int(x) for x in dims], dtype=np.int64)
         co = np.ascontiguousarray(coords, dtype=np.int32)
         va = np.ascontiguousarray(values, dtype=np.float32)
         if co.ndim != 2 or co.shape[1] != d.size or co.shape[0] != va.shape[0]:
             raise ValueError("coords must be [nnz, nmodes] and values [nnz]")
         prm, keep = _make_params(d.size, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords,
-                                 test_values, init, schedule)
+                                 test_values, init, schedule, lp_bound)
         h = ctypes.c_void_p()
         _check(lib().ntc_prepare(ctypes.byref(h), d.size, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
                                  int(rank), ctypes.byref(prm)))
@@ -518,7 +521,7 @@ class Pool:
     def admit(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *, c: float = 0.1,
               lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
               gather_bf16: bool = False, test_coords=None, test_values=None, init=None,
-              schedule: Optional[dict] = None) -> Optional[int]:
+              schedule: Optional[dict] = None, lp_bound: int = 0) -> Optional[int]:
         """Slot index, or None when the pool cannot hold the problem now."""
         d = np.asarray([int(x) for x in dims], dtype=np.int64)
         co = np.ascontiguousarray(coords, dtype=np.int32)
@@ -526,7 +529,7 @@ class Pool:
         if co.ndim != 2 or co.shape[1] != d.size or co.shape[0] != va.shape[0]:
             raise ValueError("coords must be [nnz, nmodes] and values [nnz]")
         prm, keep = _make_params(d.size, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords,
-                                 test_values, init, schedule)
+                                 test_values, init, schedule, lp_bound)
         slot = ctypes.c_int32(-1)
         st = lib().ntc_pool_admit(self._h, d.size, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
                                   int(rank), ctypes.byref(prm), ctypes.byref(slot))

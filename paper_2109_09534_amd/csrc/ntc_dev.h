@@ -89,6 +89,31 @@ __device__ __forceinline__ double row_sum_f64(double x)
     return x;
 }
 
+__device__ __forceinline__ double row_max_f64(double x)
+{
+    x = fmax(x, dpp_f64<kDppXor1>(x));
+    x = fmax(x, dpp_f64<kDppXor2>(x));
+    x = fmax(x, dpp_f64<kDppHalfMirror>(x));
+    x = fmax(x, dpp_f64<kDppMirror>(x));
+    return x;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// This lane's term of the Collatz-Wielandt bound max_i (H v)_i / v_i (the
+// optional L_p estimator): (H v)_i / v_i where v_i > 0, else 0.  H >= 0 and
+// lambda > 0 keep every live entry of the iterate positive.
+__device__ __forceinline__ double cw_ratio(bool live, double v, double w)
+{
+    return (live && v > 0.0) ? w / v : 0.0;
+}
+
 // The T normalised products of the power method (Alg. 1, L_p) on an iterate
 // held one entry per lane: mv(x) returns this lane's entry of H v, sum(x) the
 // sum of x over the lanes of the row.  Normalising by ||H v|| only fixes the

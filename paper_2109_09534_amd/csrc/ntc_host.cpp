@@ -195,7 +195,7 @@ struct ntc_problem {
     int64_t dims[ntc::kMaxModes] = {};
     int64_t nnz = 0;
     double c = 0.1, lambda = 1e-3;
-    int max_inner = 1, power_iters = 20;
+    int max_inner = 1, power_iters = 20, lp_bound = 0;
     uint64_t seed = 0;
     bool bf16 = false;
     int64_t k = 0;
@@ -346,6 +346,7 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.R = h->R;
     a.max_inner = h->max_inner;
     a.power_iters = h->power_iters;
+    a.lp_bound = h->lp_bound;
     a.n_items = m.n_items;
     a.n_partial = m.n_partial;
     a.n_group = m.n_group;
@@ -455,7 +456,7 @@ struct ntc_prepared {
     int64_t dims[ntc::kMaxModes] = {};
     int64_t nnz = 0;
     double c = 0.1, lambda = 1e-3;
-    int max_inner = 1, power_iters = 20;
+    int max_inner = 1, power_iters = 20, lp_bound = 0;
     uint64_t seed = 0;
     bool bf16 = false;
     int tiny_max = ntc::kTinyB, item_samples = 0, group_max = 512;
@@ -500,6 +501,8 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
         return fail(NTC_EINVAL, "max_inner must be in [1, 65535]");
     if (p.power_iters < 0)
         return fail(NTC_EINVAL, "power_iters must be >= 0");
+    if (p.lp_bound != 0 && p.lp_bound != 1)
+        return fail(NTC_EINVAL, "lp_bound must be 0 or 1");
     if (p.tiny_max < -1 || p.tiny_max > ntc::kTinyB)
         return fail(NTC_EINVAL, "tiny_max must be -1 or in [0, 4]");
     if (p.item_samples < 0 || (p.item_samples > 0 && p.item_samples < 16))
@@ -549,6 +552,7 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
     q->lambda = p.lambda;
     q->max_inner = p.max_inner;
     q->power_iters = p.power_iters;
+    q->lp_bound = p.lp_bound;
     q->seed = p.seed;
     q->bf16 = p.gather_bf16 != 0;
     q->tiny_max = p.tiny_max < 0 ? ntc::kTinyB : p.tiny_max;
@@ -722,6 +726,7 @@ ntc_status commit_impl(ntc_problem *h, const ntc_prepared &q, const ntc_params &
     h->lambda = q.lambda;
     h->max_inner = q.max_inner;
     h->power_iters = q.power_iters;
+    h->lp_bound = q.lp_bound;
     h->seed = q.seed;
     h->bf16 = q.bf16;
     h->stream = static_cast<hipStream_t>(p.stream);

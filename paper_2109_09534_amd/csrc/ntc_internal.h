@@ -77,6 +77,7 @@ struct RowArgs {
     int32_t R;
     int32_t max_inner;
     int32_t power_iters;
+    int32_t lp_bound;             // 0: Rayleigh quotient; 1: Collatz-Wielandt bound of the power iterate
     int32_t n_items;
     int32_t n_partial;            // (wave-per-item kernels) items [0, n_partial) write partial slots
     int32_t n_group;              // (R <= 16) items [0, n_group) are whole rows for the group kernel,

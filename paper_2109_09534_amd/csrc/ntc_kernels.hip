@@ -64,7 +64,7 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
     double L = 0.0;
     if (!vanished) {
         const double w = skew_matvec(hd, v);
-        L = row_sum_f64(v * w) / vv;
+        L = a.lp_bound ? row_max_f64(cw_ratio(live, v, w)) : row_sum_f64(v * w) / vv;
     }
     if (!live)
         return;
@@ -703,6 +703,7 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
             u[i] = ldexp(un[i], -e);
     }
     double x2 = al * al, kx2 = 0.0;
+    double kx[kTinyB];
 #pragma unroll
     for (int i = 0; i < kTinyB; ++i) {
         double gu = 0.0;
@@ -710,10 +711,29 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
         for (int j = 0; j < kTinyB; ++j)
             gu = fma(G[i][j], u[j], gu);
         x2 = fma(u[i], fma(2.0 * al, c[i], gu), x2);   // a^2 + 2 a u.c + u^T G u
-        const double kxi = fma(al, c[i], gu);          // (K x)_i = a c_i + (G u)_i
-        kx2 = fma(kxi, kxi, kx2);
+        kx[i] = fma(al, c[i], gu);                     // (K x)_i = a c_i + (G u)_i
+        kx2 = fma(kx[i], kx[i], kx2);
     }
-    const double L = (x2 > 0.0) ? kx2 / x2 + lam : 0.0;
+    double L = (x2 > 0.0) ? kx2 / x2 + lam : 0.0;
+    if (a.lp_bound) {
+        // Collatz-Wielandt bound: x_r = a v0 + (K^T u)_r, (H x)_r = (K^T K x)_r + lambda x_r
+        L = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r < R) {
+                double xr = al * v0, hx = 0.0;
+#pragma unroll
+                for (int i = 0; i < kTinyB; ++i) {
+                    const double kir = static_cast<double>(kk[i][r]);
+                    xr = fma(kir, u[i], xr);
+                    hx = fma(kir, kx[i], hx);
+                }
+                hx = fma(lam, xr, hx);
+                if (xr > 0.0)
+                    L = fmax(L, hx / xr);
+            }
+        }
+    }
 
     const bool more = a.l + 1 < a.max_inner;
     if (L > 0.0) {

@@ -56,8 +56,10 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
     double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
     const bool vanished = !power_iterate(v, vv, a.power_iters, matvec, [](double x) { return wave_sum(x); });
     double L = 0.0;
-    if (!vanished)
-        L = wave_sum(v * matvec(v)) / vv;
+    if (!vanished) {
+        const double w = matvec(v);
+        L = a.lp_bound ? wave_max(cw_ratio(live, v, w)) : wave_sum(v * w) / vv;
+    }
     if (!live)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + lane;
@@ -280,6 +282,22 @@ __device__ __forceinline__ double swap32_sum(double x)
     return x0 + x1;
 }
 
+__device__ __forceinline__ double swap16_max(double x)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    const uint32_t lo = static_cast<uint32_t>(b), hi = static_cast<uint32_t>(b >> 32);
+    const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double x0 = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(ph[0]) << 32) | pl[0]));
+    const double x1 = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(ph[1]) << 32) | pl[1]));
+    return fmax(x0, x1);
+}
+
+__device__ __forceinline__ double group32_max_f64(double x)
+{
+    return swap16_max(row_max_f64(x));
+}
+
 __device__ __forceinline__ double group32_sum_f64(double x)
 {
     x += dpp_f64<kDppXor1>(x);
@@ -353,8 +371,10 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
     double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
     const bool vanished = !power_iterate(v, vv, a.power_iters, matvec, [](double x) { return group32_sum_f64(x); });
     double L = 0.0;
-    if (!vanished)
-        L = group32_sum_f64(v * matvec(v)) / vv;
+    if (!vanished) {
+        const double w = matvec(v);
+        L = a.lp_bound ? group32_max_f64(cw_ratio(live, v, w)) : group32_sum_f64(v * w) / vv;
+    }
     if (!live || half != 0)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + col;

@@ -125,6 +125,16 @@ CASES = {
     "r33_matrix_singles": lambda: (synth.make_problem((400, 300), 60_000, 8, seed=17), 33, dict(c=0.3)),
     "r46_slot_groups": lambda: (synth.make_problem((60, 50, 40), 70_000, 8, seed=18, zipf_s=1.1), 46,
                                 dict(c=0.8, schedule={"item_samples": 16})),
+    # L_p as the Collatz-Wielandt bound of the power iterate, in every finishing path: one lane per
+    # row (Krylov form), 16-lane groups, chunks and split rows, R <= 32, R <= 64, and the generic kernel
+    "cw_r8_tiny_and_groups": lambda: (synth.c0(seed=4), 8, dict(c=0.1, lp_bound=1)),
+    "cw_zipf_r16_rowsum": lambda: (synth.c1_small(seed=8), 16, dict(c=0.1, lp_bound=1, power_iters=0)),
+    "cw_r32_inner2": lambda: (synth.make_problem((200, 150, 80), 100_000, 16, seed=20), 32,
+                              dict(c=0.3, max_inner=2, lp_bound=1)),
+    "cw_r50_power3": lambda: (synth.make_problem((183, 24, 114, 171), 150_000, 10, seed=21), 50,
+                              dict(c=0.5, lp_bound=1, power_iters=3)),
+    "cw_r24_5way_generic": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=22), 24,
+                                    dict(c=0.3, lp_bound=1)),
     # the twin of the paper's timing workload at full size (3.3M cells, c = 0.5), every rank it uses:
     # 24 to 1717 rows per mode, so every row of modes 0 and 1 is split over many items
     "scaling_twin_r10": lambda: (_twin(), 10, dict(c=0.5)),

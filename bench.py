@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--lp-bound", type=int, default=0,
                     help="c1/c2: 1 = L_p as the Collatz-Wielandt bound of the power iterate")
     ap.add_argument("--power-iters", type=int, default=20, help="c1/c2: power iterations T_pow")
+    ap.add_argument("--device-csr", action="store_true",
+                    help="c1/c2: build the per-mode CSR on the GPU (ntc_create_device_csr)")
     ap.add_argument("--ranks", default="10,30,50", help="scaling: ranks R")
     ap.add_argument("--instances", type=int, default=256, help="batch/serve: number of problems")
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-at-a-time baseline")
@@ -157,7 +159,7 @@ def main():
     t0 = time.perf_counter()
     prob = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=max_inner, seed=args.seed,
                        gather_bf16=args.bf16, test_coords=p.test_coords, test_values=p.test_values, stream=0,
-                       power_iters=args.power_iters, lp_bound=args.lp_bound)
+                       power_iters=args.power_iters, lp_bound=args.lp_bound, device_csr=args.device_csr)
     create_s = time.perf_counter() - t0
     upd_sweep, rows_sweep = prob.work()
     log(f"ntc_create {create_s:.1f} s; {upd_sweep} sampled entries and {rows_sweep} row steps per sweep")
@@ -283,6 +285,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "create_s": round(create_s, 2),
+        "create": "device CSR build" if args.device_csr else "host CSR build",
         "generate_s": round(gen_s, 2),
         "loss_ms": round(loss_ms, 2),
         "test_rmse": round(float(loss[2]), 6),

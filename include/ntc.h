@@ -107,6 +107,18 @@ void ntc_params_default(ntc_params *p);
 ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
                       const int32_t *coords, const float *values, int32_t rank, const ntc_params *p);
 
+/* ntc_create with the CSR built on the device: the COO entries (host
+ * arrays, as for ntc_create) are copied to the GPU once and checked there,
+ * and each mode's entries are sorted by i_m with a stable radix sort, so the
+ * records, row pointers and every later result are bit-identical to
+ * ntc_create's.  Only the row schedule is built on the host, from the row
+ * pointers.  Temporaries (about 24 bytes per entry) come from hipMalloc and
+ * are freed before return; what the problem keeps goes through dev_alloc as
+ * in ntc_create.  Errors as ntc_create (the first bad entry is reported with
+ * the same message); NTC_EDEVICE if the device build fails. */
+ntc_status ntc_create_device_csr(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                                 const int32_t *coords, const float *values, int32_t rank, const ntc_params *p);
+
 /* ntc_create in two steps, for callers that build problems on other host
  * threads while the GPU works (serving):
  *   ntc_prepare      validates the arguments and does all host work (CSR of

@@ -91,6 +91,9 @@ _SIGNATURES = [
     ("ntc_params_default", None, [ctypes.POINTER(_Params)]),
     ("ntc_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, _i64p, ctypes.c_int64, _i32p,
                                   _f32p, ctypes.c_int32, ctypes.POINTER(_Params)]),
+    ("ntc_create_device_csr", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, _i64p,
+                                             ctypes.c_int64, _i32p, _f32p, ctypes.c_int32,
+                                             ctypes.POINTER(_Params)]),
     ("ntc_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ntc_update_mode", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ntc_loss", ctypes.c_int, [ctypes.c_void_p, _f64p]),
@@ -275,6 +278,8 @@ class Problem:
     ``stream``: None or 0 for the null stream, a raw hipStream_t int, or a
     ``torch.cuda.Stream`` (torch must share libntc's HIP runtime).
     ``torch_allocator``: route device memory through torch's caching allocator.
+    ``device_csr``: build the per-mode CSR on the GPU (ntc_create_device_csr);
+    every result is bit-identical to the host build.
     """
 
     def __init__(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *,
@@ -282,7 +287,7 @@ class Problem:
                  gather_bf16: bool = False, test_coords: Optional[np.ndarray] = None,
                  test_values: Optional[np.ndarray] = None, init: Optional[Sequence[np.ndarray]] = None,
                  stream=None, torch_allocator: bool = False, schedule: Optional[dict] = None,
-                 lp_bound: int = 0):
+                 lp_bound: int = 0, device_csr: bool = False):
         L = lib()
         self.dims = [int(d) for d in dims]
         self.N = len(self.dims)
@@ -305,8 +310,9 @@ class Problem:
             prm.dev_alloc = self._allocator.alloc
             prm.dev_free = self._allocator.free
         h = ctypes.c_void_p()
-        _check(L.ntc_create(ctypes.byref(h), self.N, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
-                            self.R, ctypes.byref(prm)))
+        create = L.ntc_create_device_csr if device_csr else L.ntc_create
+        _check(create(ctypes.byref(h), self.N, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
+                      self.R, ctypes.byref(prm)))
         self._h = h
         self.c, self.lam, self.max_inner, self.power_iters, self.seed = c, lam, max_inner, power_iters, seed
         self.gather_bf16 = gather_bf16

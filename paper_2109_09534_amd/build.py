@@ -18,7 +18,8 @@ LIB = os.path.join(PKG, "libntc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["ntc_host.cpp", "ntc_pool.cpp", "ntc_kernels.hip", "ntc_kernels_wide.hip", "ntc_aux.hip"]
+SOURCES = ["ntc_host.cpp", "ntc_pool.cpp", "ntc_kernels.hip", "ntc_kernels_wide.hip", "ntc_aux.hip",
+           "ntc_csr.hip"]
 
 
 def build(verbose: bool = False, out_path: str = LIB, defines=()) -> str:

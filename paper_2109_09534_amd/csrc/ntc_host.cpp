@@ -12,6 +12,7 @@
 
 #include "ntc.h"
 #include "ntc_aux.h"
+#include "ntc_csr.h"
 #include "ntc_internal.h"
 #include "ntc_problem.h"
 #include "ntc_rng.h"
@@ -467,8 +468,10 @@ struct ntc_prepared {
         std::vector<Item> items;
         std::vector<SplitRow> split;
         std::vector<ntc::SlotGroup> groups;
+        uint32_t *dev_rec = nullptr;       // records already built on the device (ntc_create_device_csr)
     } md[ntc::kMaxModes];
     std::vector<uint32_t> row0;            // row * R of every mode-0 record (N = 4 or 8)
+    uint32_t *dev_row0 = nullptr;          // the same, built on the device
     int32_t row_word = -1;
     int32_t max_slots = 0;
     int64_t max_row = 0;
@@ -480,8 +483,22 @@ struct ntc_prepared {
 
 namespace {
 
-ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t nnz, const int32_t *coords,
-                        const float *values, int32_t R, const ntc_params &p)
+// The host's check of one COO entry: coordinates in range, a finite value.
+ntc_status check_entry(const int32_t *coords, const float *values, int N, const int64_t *dims, int64_t e)
+{
+    for (int m = 0; m < N; ++m) {
+        const int32_t x = coords[e * N + m];
+        if (x < 0 || x >= dims[m])
+            return fail(NTC_EINVAL, "coordinate out of range at entry " + std::to_string(e));
+    }
+    if (!std::isfinite(values[e]))
+        return fail(NTC_EINVAL, "non-finite value at entry " + std::to_string(e));
+    return NTC_OK;
+}
+
+// Every check of ntc_create's arguments except the per-entry one.
+ntc_status check_params(int32_t N, const int64_t *dims, int64_t nnz, const int32_t *coords, const float *values,
+                        int32_t R, const ntc_params &p)
 {
     if (N < 2 || N > ntc::kMaxModes)
         return fail(NTC_EINVAL, "nmodes must be in [2, 8]");
@@ -518,15 +535,7 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
             return fail(NTC_EUNSUPPORTED, "factor of mode " + std::to_string(m) +
                                               " would exceed 4 GiB (gathers use 32-bit byte offsets)");
     }
-    for (int64_t e = 0; e < nnz; ++e) {
-        for (int m = 0; m < N; ++m) {
-            const int32_t x = coords[e * N + m];
-            if (x < 0 || x >= dims[m])
-                return fail(NTC_EINVAL, "coordinate out of range at entry " + std::to_string(e));
-        }
-        if (!std::isfinite(values[e]))
-            return fail(NTC_EINVAL, "non-finite value at entry " + std::to_string(e));
-    }
+
     for (int64_t e = 0; e < p.n_test; ++e) {
         for (int m = 0; m < N; ++m) {
             const int32_t x = p.test_coords[e * N + m];
@@ -542,6 +551,19 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
                 return fail(NTC_EINVAL, "init_factors[" + std::to_string(m) + "] is null");
             NTC_TRY(validate_factor(p.init_factors[m], dims[m] * R, m));
         }
+    return NTC_OK;
+}
+
+// dev_rowptr (N of them): the row pointers of a CSR already built on the
+// device, whose entries were checked there; the host then builds only the
+// schedule.
+ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t nnz, const int32_t *coords,
+                        const float *values, int32_t R, const ntc_params &p,
+                        const std::vector<int64_t> *dev_rowptr = nullptr)
+{
+    NTC_TRY(check_params(N, dims, nnz, coords, values, R, p));
+    for (int64_t e = 0; e < (dev_rowptr ? 0 : nnz); ++e)
+        NTC_TRY(check_entry(coords, values, N, dims, e));
 
     q->N = N;
     q->R = R;
@@ -568,13 +590,17 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
         ntc_prepared::Mode &pm = q->md[m];
         ModeState &md = pm.st;
         md.I = dims[m];
-        pm.rec.assign(static_cast<size_t>(std::max<int64_t>(nnz, 1)) * q->rw, 0u);
         // mode 0's records also carry the row (times R) for the loss: in the
         // padding word when there is one, else in a separate array
         const int own = (m == 0 && N < q->rw) ? N : -1;
-        csr_build(N, dims, nnz, coords, values, m, q->rw, md.h_rowptr, pm.rec.data(), nullptr,
-                  static_cast<uint32_t>(R), own);
-        if (m == 0 && own < 0 && nnz > 0) {
+        if (dev_rowptr) {
+            md.h_rowptr = dev_rowptr[m];
+        } else {
+            pm.rec.assign(static_cast<size_t>(std::max<int64_t>(nnz, 1)) * q->rw, 0u);
+            csr_build(N, dims, nnz, coords, values, m, q->rw, md.h_rowptr, pm.rec.data(), nullptr,
+                      static_cast<uint32_t>(R), own);
+        }
+        if (m == 0 && own < 0 && nnz > 0 && !dev_rowptr) {
             q->row0.assign(static_cast<size_t>(nnz), 0u);
             for (int64_t r = 0; r < md.I; ++r)
                 for (int64_t e = md.h_rowptr[r]; e < md.h_rowptr[r + 1]; ++e)
@@ -763,7 +789,9 @@ ntc_status commit_impl(ntc_problem *h, const ntc_prepared &q, const ntc_params &
     }
     if (h->max_inner > 1)
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->Y), maxI * R * sizeof(float), "Y buffer"));
-    if (!q.row0.empty()) {
+    if (q.dev_row0) {
+        h->row0 = q.dev_row0;  // built on the device, already owned by h
+    } else if (!q.row0.empty()) {
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&h->row0), static_cast<size_t>(nnz) * 4, "loss rows"));
         NTC_HIP(hipMemcpy(h->row0, q.row0.data(), static_cast<size_t>(nnz) * 4, hipMemcpyHostToDevice));
     }
@@ -772,10 +800,15 @@ ntc_status commit_impl(ntc_problem *h, const ntc_prepared &q, const ntc_params &
         ModeState &md = h->md[m];
         md = pm.st;
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.rowptr), (md.I + 1) * sizeof(int64_t), "rowptr"));
-        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.records),
-                              static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw * 4, "records"));
         NTC_HIP(hipMemcpy(md.rowptr, md.h_rowptr.data(), (md.I + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-        NTC_HIP(hipMemcpy(md.records, pm.rec.data(), static_cast<size_t>(nnz) * h->rw * 4, hipMemcpyHostToDevice));
+        if (pm.dev_rec) {
+            md.records = pm.dev_rec;  // built on the device, already owned by h
+        } else {
+            NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.records),
+                                  static_cast<size_t>(std::max<int64_t>(nnz, 1)) * h->rw * 4, "records"));
+            NTC_HIP(hipMemcpy(md.records, pm.rec.data(), static_cast<size_t>(nnz) * h->rw * 4,
+                              hipMemcpyHostToDevice));
+        }
         NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&md.tiny), pm.tiny.size() * sizeof(ntc::RowItem),
                               "tiny rows"));
         if (!pm.tiny.empty())
@@ -877,6 +910,101 @@ void ntc::note_sweeps(ntc_handle h, int64_t n)
 }
 
 // ======================================================================= ABI
+// The mode-sorted CSR of every mode built on the device (ntc_create_device_csr):
+// the COO is uploaded once and checked there; per mode a stable radix sort
+// by coordinate gives the same entry order as the host's counting sort.  The
+// records (and mode 0's row array when the record has no spare word) are
+// allocated through h and handed to commit; the row pointers come back for
+// the host-side schedule.  Temporaries use hipMalloc and are freed here.
+struct DeviceTemps {
+    std::vector<void *> p;
+    ~DeviceTemps()
+    {
+        for (void *x : p)
+            (void)hipFree(x);
+    }
+    hipError_t get(void **dst, size_t bytes)
+    {
+        *dst = nullptr;
+        const hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 256));
+        if (e == hipSuccess)
+            p.push_back(*dst);
+        return e;
+    }
+};
+
+ntc_status device_csr(ntc_problem *h, ntc_prepared &q, std::vector<int64_t> (&rowptr)[ntc::kMaxModes], int32_t N,
+                      const int64_t *dims, int64_t nnz, const int32_t *coords, const float *values, int32_t R)
+{
+    DeviceTemps t;
+    int32_t *d_coords = nullptr;
+    float *d_values = nullptr;
+    uint32_t *keys_in = nullptr, *keys_out = nullptr, *ids_in = nullptr, *ids_out = nullptr;
+    unsigned long long *bad = nullptr;
+    int64_t *d_rowptr = nullptr;
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+    int64_t maxI = 0;
+    for (int m = 0; m < N; ++m)
+        maxI = std::max(maxI, dims[m]);
+    const size_t n = static_cast<size_t>(std::max<int64_t>(nnz, 1));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&d_coords), n * N * 4));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&d_values), n * 4));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&keys_in), n * 4));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&keys_out), n * 4));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&ids_in), n * 4));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&ids_out), n * 4));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&bad), sizeof(unsigned long long)));
+    NTC_HIP(t.get(reinterpret_cast<void **>(&d_rowptr), static_cast<size_t>(maxI + 1) * 8));
+    NTC_HIP(ntc::csr_sort_bytes(nnz, &temp_bytes));
+    NTC_HIP(t.get(&temp, temp_bytes));
+    if (nnz > 0) {
+        NTC_HIP(hipMemcpy(d_coords, coords, static_cast<size_t>(nnz) * N * 4, hipMemcpyHostToDevice));
+        NTC_HIP(hipMemcpy(d_values, values, static_cast<size_t>(nnz) * 4, hipMemcpyHostToDevice));
+    }
+    // the first bad entry, reported with the host's message for it
+    const unsigned long long none = ~0ull;
+    NTC_HIP(hipMemcpy(bad, &none, sizeof(none), hipMemcpyHostToDevice));
+    ntc::CsrDims cd{};
+    for (int m = 0; m < N; ++m)
+        cd.d[m] = dims[m];
+    NTC_HIP(ntc::csr_validate(d_coords, d_values, nnz, N, cd, bad, nullptr));
+    unsigned long long first = none;
+    NTC_HIP(hipMemcpy(&first, bad, sizeof(first), hipMemcpyDeviceToHost));
+    if (first != none)
+        return check_entry(coords, values, N, dims, static_cast<int64_t>(first));
+    const int rw = record_words(N);
+    for (int m = 0; m < N; ++m) {
+        ntc::CsrMode c{};
+        c.coords = d_coords;
+        c.values = d_values;
+        c.nnz = nnz;
+        c.nmodes = N;
+        c.mode = m;
+        c.I = dims[m];
+        c.rw = rw;
+        c.R = static_cast<uint32_t>(R);
+        c.own_word = (m == 0 && N < rw) ? N : -1;
+        c.keys_in = keys_in;
+        c.keys_out = keys_out;
+        c.ids_in = ids_in;
+        c.ids_out = ids_out;
+        c.temp = temp;
+        c.temp_bytes = temp_bytes;
+        c.rowptr = d_rowptr;
+        NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&c.records), n * rw * 4, "records"));
+        if (m == 0 && c.own_word < 0 && nnz > 0) {
+            NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&c.row0), static_cast<size_t>(nnz) * 4, "loss rows"));
+            q.dev_row0 = c.row0;
+        }
+        NTC_HIP(ntc::csr_mode(c, nullptr));
+        rowptr[m].resize(static_cast<size_t>(dims[m]) + 1);
+        NTC_HIP(hipMemcpy(rowptr[m].data(), d_rowptr, (dims[m] + 1) * 8, hipMemcpyDeviceToHost));
+        q.md[m].dev_rec = c.records;
+    }
+    return NTC_OK;
+}
+
 extern "C" {
 
 void ntc_params_default(ntc_params *p)
@@ -909,6 +1037,44 @@ ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int6
         s = prepare_impl(&q, nmodes, dims, nnz, coords, values, rank, p ? *p : def);
         if (s == NTC_OK)
             s = commit_impl(h, q, p ? *p : def);
+    } catch (const std::bad_alloc &) {
+        s = fail(NTC_ENOMEM, "host allocation failed");
+    }
+    if (s != NTC_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return NTC_OK;
+}
+
+ntc_status ntc_create_device_csr(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                                 const int32_t *coords, const float *values, int32_t rank, const ntc_params *p)
+{
+    if (!out)
+        return fail(NTC_EINVAL, "out is null");
+    *out = nullptr;
+    ntc_params def;
+    ntc_params_default(&def);
+    const ntc_params &pp = p ? *p : def;
+    NTC_TRY(check_params(nmodes, dims, nnz, coords, values, rank, pp));
+    ntc_problem *h = new (std::nothrow) ntc_problem();
+    if (!h)
+        return fail(NTC_ENOMEM, "host allocation failed");
+    // device memory the problem keeps goes through the caller's allocator, as in commit
+    h->stream = static_cast<hipStream_t>(pp.stream);
+    h->alloc = pp.dev_alloc;
+    h->dfree = pp.dev_free;
+    h->actx = pp.alloc_ctx;
+    ntc_status s;
+    try {
+        ntc_prepared q;
+        std::vector<int64_t> rowptr[ntc::kMaxModes];
+        s = device_csr(h, q, rowptr, nmodes, dims, nnz, coords, values, rank);
+        if (s == NTC_OK)
+            s = prepare_impl(&q, nmodes, dims, nnz, coords, values, rank, pp, rowptr);
+        if (s == NTC_OK)
+            s = commit_impl(h, q, pp);
     } catch (const std::bad_alloc &) {
         s = fail(NTC_ENOMEM, "host allocation failed");
     }

@@ -75,8 +75,10 @@ typedef struct ntc_params {
     void *alloc_ctx;
     int32_t item_samples;       /* schedule: sampled entries per work item; longer minibatches
                                    are split over several items (0 = default) */
-    int32_t overlap;            /* schedule: 1 = run the one-row-per-lane launch on a second
-                                   stream concurrently with the other rows (default), 0 = serial */
+    int32_t overlap;            /* schedule: 1 = run the one-row-per-lane launch (and, for R <= 16,
+                                   N <= 4, the one-row-per-group launch) on a second stream
+                                   concurrently with the chunks (default); 2 = only the
+                                   one-row-per-group launch on the second stream; 0 = serial */
     int32_t group_max;          /* schedule (R <= 16): rows with tiny_max < B_p <= group_max run
                                    one row per 16-lane group, longer ones as 256-thread chunks of
                                    item_samples entries (0 = default 512) */

@@ -28,6 +28,7 @@ DEFAULT_CANDIDATES_16 = [
     {"tiny_max": 2},
     {"tiny_max": 0},
     {"overlap": 0},
+    {"overlap": 2},
 ]
 DEFAULT_CANDIDATES_WIDE = [
     {},

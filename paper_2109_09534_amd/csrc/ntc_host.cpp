@@ -206,6 +206,7 @@ struct ntc_problem {
     int tiny_max = ntc::kTinyB;
     int item_samples = 0;
     int group_max = 512;
+    int overlap = 1;
     int device = 0;
     ntc_alloc_fn alloc = nullptr;
     ntc_free_fn dfree = nullptr;
@@ -376,9 +377,12 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
         // the side stream while the chunks and the finalize of split rows
         // (which reads only the chunks' partial slots) stay on the main
         // stream.  A serial profiled sweep runs everything on one stream.
+        // overlap = 2 keeps the one-row-per-lane rows on the main stream, ahead of the chunks.
         const bool rows_aside = kc.rp == 16 && kc.nmodes <= 4;
-        const int32_t n_aside = md.n_tiny + (rows_aside ? md.n_group : 0);
-        const int32_t n_main = (rows_aside ? md.n_items - md.n_group : md.n_items) + md.n_split;
+        const bool tiny_aside = h->overlap != 2;
+        const int32_t n_aside = (tiny_aside ? md.n_tiny : 0) + (rows_aside ? md.n_group : 0);
+        const int32_t n_main = (rows_aside ? md.n_items - md.n_group : md.n_items) + md.n_split +
+                               (tiny_aside ? 0 : md.n_tiny);
         const bool fork = (!probe || probe->concurrent) && h->side && n_aside > 0 && n_main > 0;
         if (fork) {
             NTC_HIP(hipEventRecord(h->ev_fork, h->stream));
@@ -389,7 +393,7 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
             L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny, md.n_groups);
             if (L.blocks <= 0)
                 continue;
-            const bool aside = kern == ntc::kTiny || (kern == ntc::kRows && rows_aside);
+            const bool aside = (kern == ntc::kTiny && tiny_aside) || (kern == ntc::kRows && rows_aside);
             hipStream_t st = (aside && fork) ? h->side : h->stream;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (probe) {
@@ -526,6 +530,8 @@ ntc_status check_params(int32_t N, const int64_t *dims, int64_t nnz, const int32
         return fail(NTC_EINVAL, "item_samples must be 0 or >= 16");
     if (p.group_max < 0)
         return fail(NTC_EINVAL, "group_max must be >= 0");
+    if (p.overlap < 0 || p.overlap > 2)
+        return fail(NTC_EINVAL, "overlap must be 0, 1 or 2");
     if (p.n_test < 0 || (p.n_test > 0 && (!p.test_coords || !p.test_values)))
         return fail(NTC_EINVAL, "test set pointers are null");
     for (int m = 0; m < N; ++m) {
@@ -765,6 +771,7 @@ ntc_status commit_impl(ntc_problem *h, const ntc_prepared &q, const ntc_params &
     h->max_row = q.max_row;
     h->row_word = q.row_word;
     NTC_HIP(hipGetDevice(&h->device));
+    h->overlap = p.overlap;
     if (p.overlap) {
         NTC_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
         NTC_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));

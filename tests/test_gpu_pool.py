@@ -24,7 +24,8 @@ def _say(*a):
 
 def _mix(seed0=500):
     """Small instances of the batching mixture: mixed dims, nnz and R, one
-    4-way, one BF16, one MAX_INNER = 2, one with Zipf heads (split rows)."""
+    4-way, one BF16, one MAX_INNER = 2, one with Zipf heads (split rows), one
+    with R > 32 and the Collatz-Wielandt L_p bound."""
     out = []
     shapes = [((60, 50, 40), 12000, 8, {}),
               ((200, 90, 70), 40000, 16, {}),
@@ -32,7 +33,8 @@ def _mix(seed0=500):
               ((30, 25, 20, 12), 20000, 10, {}),
               ((150, 80, 60), 35000, 16, {"gather_bf16": True}),
               ((90, 70, 50), 25000, 12, {"max_inner": 2}),
-              ((400, 300, 40), 150000, 16, {"zipf": 1.1})]
+              ((400, 300, 40), 150000, 16, {"zipf": 1.1}),
+              ((100, 80, 60), 30000, 48, {"lp_bound": 1})]
     for i, (dims, nnz, R, kw) in enumerate(shapes):
         kw = dict(kw)
         z = kw.pop("zipf", None)

@@ -68,6 +68,8 @@ def test_host_csr_is_bit_identical_to_the_oracle_csr():
 @pytest.mark.parametrize("kw,msg", [
     (dict(rank=0), "rank"), (dict(rank=65), "rank"), (dict(c=0.0), "c must"), (dict(c=1.5), "c must"),
     (dict(lam=-1.0), "lambda"), (dict(max_inner=0), "max_inner"), (dict(power_iters=-1), "power_iters"),
+    (dict(lp_bound=2), "lp_bound"), (dict(schedule={"overlap": 3}), "overlap"),
+    (dict(device_csr=True, c=0.0), "c must"), (dict(device_csr=True, rank=65), "rank"),
 ])
 def test_create_rejects_invalid_parameters_before_touching_a_device(kw, msg):
     p = synth.tiny(seed=0)

@@ -145,31 +145,36 @@ __device__ __forceinline__ GroupItem load_group_item(const Args &a, int id)
     return g;
 }
 
-// Record of sample jb + r of the item (zeros past its end).
+// Record of sample jb + r of the item; returns whether the sample exists.
+// Every lane loads, whatever the item's length: a lane past its end reads
+// entry 0 of the records (in bounds whenever a row kernel runs) and
+// stage_record puts the zero record in its place.  With no load under a
+// branch the compiler can count the loads in flight, so a later wait for
+// older loads leaves this one outstanding.
 template <int RW, class Args>
-__device__ __forceinline__ void fetch_record(const Args &a, const GroupItem &g, int jb, int r, uint4 &w0,
+__device__ __forceinline__ bool fetch_record(const Args &a, const GroupItem &g, int jb, int r, uint4 &w0,
                                              uint4 &w1)
 {
-    w0 = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
-    w1 = make_uint4(a.zrec[4], a.zrec[5], a.zrec[6], a.zrec[7]);
-    if (jb + r < g.len) {
-        const uint32_t q = prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r));
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.records + (g.base + q) * RW);
-        w0 = src[0];
-        if (RW == 8)
-            w1 = src[1];
-    }
+    const bool live = jb + r < g.len;
+    int64_t e = 0;
+    if (live)
+        e = g.base + prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r));
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.records + e * RW);
+    w0 = src[0];
+    w1 = (RW == 8) ? src[1] : w0;
+    return live;
 }
 
 // LDS accesses of one wave are performed in order, so staging needs only a
 // compiler barrier, not a fence (a fence would also wait for the gathers in
 // flight).
-template <int RW>
-__device__ __forceinline__ void stage_record(uint4 *buf, int lane, const uint4 &w0, const uint4 &w1)
+template <int RW, class Args>
+__device__ __forceinline__ void stage_record(const Args &a, uint4 *buf, int lane, bool live, const uint4 &w0,
+                                             const uint4 &w1)
 {
-    buf[lane * (RW / 4)] = w0;
+    buf[lane * (RW / 4)] = live ? w0 : make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
     if (RW == 8)
-        buf[lane * (RW / 4) + 1] = w1;
+        buf[lane * (RW / 4) + 1] = live ? w1 : make_uint4(a.zrec[4], a.zrec[5], a.zrec[6], a.zrec[7]);
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -233,13 +238,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
     uint4 w0, w1;
     float f[NM - 1][16];  // gathered factor values of the next batch to reduce
     if (nb > 0) {
-        fetch_record<RW>(a, g, 0, r, w0, w1);
-        stage_record<RW>(s_rec[0], lane, w0, w1);
-        if (nb > 1) {
-            fetch_record<RW>(a, g, 16, r, w0, w1);
-            stage_record<RW>(s_rec[1], lane, w0, w1);
-        }
+        // both batches' records in flight together; batch 1 is staged after
+        // batch 0's gathers are issued (all zero records when nb == 1)
+        uint4 v0, v1;
+        const bool l0 = fetch_record<RW>(a, g, 0, r, w0, w1);
+        const bool l1 = fetch_record<RW>(a, g, 16, r, v0, v1);
+        stage_record<RW>(a, s_rec[0], lane, l0, w0, w1);
         gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(s_rec[0]) + grp * 16 * RW, rr, f);
+        stage_record<RW>(a, s_rec[1], lane, l1, v0, v1);
     }
     for (int bi = 0; bi < nb; ++bi) {
         const int jb = bi * 16;
@@ -256,8 +262,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
         }
         // issue order: records of batch b+2, then gathers of batch b+1, so
         // that staging the records later waits only for the record loads
-        if (bi + 2 < nb)
-            fetch_record<RW>(a, g, jb + 32, r, w0, w1);
+        // (fetched in every iteration: past the end they are zero records)
+        const bool lv2 = fetch_record<RW>(a, g, jb + 32, r, w0, w1);
         if (bi + 1 < nb)
             gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(s_rec[(bi + 1) & 1]) + grp * 16 * RW,
                                        rr, f);
@@ -281,7 +287,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
             s_h[v * 64 + lane] += static_cast<double>(acc[v]);
         __builtin_amdgcn_wave_barrier();  // the compute above read s_rec[bi & 1]
         if (bi + 2 < nb)
-            stage_record<RW>(s_rec[bi & 1], lane, w0, w1);
+            stage_record<RW>(a, s_rec[bi & 1], lane, lv2, w0, w1);
     }
 
     // register v of lane l holds block v/4, row 4*(l/16) + v%4, column l%16:
@@ -348,13 +354,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
     uint4 *rb0 = s_rec[wave][0];
     uint4 *rb1 = s_rec[wave][1];
     if (nit > 0) {
-        fetch_record<RW>(a, g, 16 * G, r, w0, w1);
-        stage_record<RW>(rb0, lane, w0, w1);
-        if (nit > 1) {
-            fetch_record<RW>(a, g, 16 * (G + 16), r, w0, w1);
-            stage_record<RW>(rb1, lane, w0, w1);
-        }
+        uint4 v0, v1;
+        const bool l0 = fetch_record<RW>(a, g, 16 * G, r, w0, w1);
+        const bool l1 = fetch_record<RW>(a, g, 16 * (G + 16), r, v0, v1);
+        stage_record<RW>(a, rb0, lane, l0, w0, w1);
         gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(rb0) + grp * 16 * RW, rr, f);
+        stage_record<RW>(a, rb1, lane, l1, v0, v1);
     }
     for (int i = 0; i < nit; ++i) {
         float kc[16];
@@ -366,8 +371,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
                 k *= f[mm][t];
             kc[t] = rlive ? k : 0.0f;  // a missing sample gathered the zero rows
         }
-        if (i + 2 < nit)
-            fetch_record<RW>(a, g, 16 * (G + 16 * (i + 2)), r, w0, w1);
+        const bool lv2 = fetch_record<RW>(a, g, 16 * (G + 16 * (i + 2)), r, w0, w1);
         if (i + 1 < nit)
             gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>((i & 1) ? rb0 : rb1) + grp * 16 * RW,
                                        rr, f);
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
             hd[v] += static_cast<double>(acc[v]);
         __builtin_amdgcn_wave_barrier();  // the compute above read this buffer
         if (i + 2 < nit)
-            stage_record<RW>((i & 1) ? rb1 : rb0, lane, w0, w1);
+            stage_record<RW>(a, (i & 1) ? rb1 : rb0, lane, lv2, w0, w1);
     }
 
     // fixed-order combination over the four waves and the 16 groups
@@ -461,8 +465,8 @@ __global__ __launch_bounds__(64) void k_rows16_nm(NTC_ROW_PARAMS)
         const int cnt = min(16, max(0, g.len - jb));
         const int tmax = min(16, maxlen - jb);
         uint4 w0, w1;
-        fetch_record<8>(a, g, jb, r, w0, w1);
-        stage_record<8>(s_rec, lane, w0, w1);
+        const bool lv = fetch_record<8>(a, g, jb, r, w0, w1);
+        stage_record<8>(a, s_rec, lane, lv, w0, w1);
         const uint32_t *srec = reinterpret_cast<const uint32_t *>(s_rec) + grp * 16 * 8;
         float kp[16];
 #pragma unroll
@@ -537,52 +541,60 @@ __global__ __launch_bounds__(64) void k_rows16_nm(NTC_ROW_PARAMS)
 // One factor row of up to 16 columns into registers (zeros past R).  When
 // R % 4 == 0 every row starts on a 16-byte (FP32) or 8-byte (BF16) boundary
 // and is read with vector loads.
-__device__ __forceinline__ void load_row16(const float *p, int R, bool v4, float (&out)[16])
+// The loads are branch-free: a part past R reads the start of the same row
+// again and is zeroed afterwards, so no load sits under a branch and the
+// compiler's wait counts stay exact across the rows of a sample.
+template <bool V4>
+__device__ __forceinline__ void load_row16(const float *p, int R, float (&out)[16])
 {
-    if (v4) {
+    if (V4) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 t = 4 * q < R ? reinterpret_cast<const float4 *>(p)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-            out[4 * q] = t.x;
-            out[4 * q + 1] = t.y;
-            out[4 * q + 2] = t.z;
-            out[4 * q + 3] = t.w;
+            const bool in = q == 0 || 4 * q < R;  // R >= 4 here
+            const float4 t = reinterpret_cast<const float4 *>(p)[in ? q : 0];
+            out[4 * q] = in ? t.x : 0.0f;
+            out[4 * q + 1] = in ? t.y : 0.0f;
+            out[4 * q + 2] = in ? t.z : 0.0f;
+            out[4 * q + 3] = in ? t.w : 0.0f;
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            out[r] = r < R ? p[r] : 0.0f;
+        for (int r = 0; r < 16; ++r) {
+            const bool in = r == 0 || r < R;  // R >= 1
+            const float t = p[in ? r : 0];
+            out[r] = in ? t : 0.0f;
+        }
     }
 }
 
-__device__ __forceinline__ void load_row16(const uint16_t *p, int R, bool v4, float (&out)[16])
+template <bool V4>
+__device__ __forceinline__ void load_row16(const uint16_t *p, int R, float (&out)[16])
 {
-    if (v4) {
+    if (V4) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const uint2 t = 4 * q < R ? reinterpret_cast<const uint2 *>(p)[q] : make_uint2(0u, 0u);
-            out[4 * q] = __uint_as_float(t.x << 16);
-            out[4 * q + 1] = __uint_as_float(t.x & 0xFFFF0000u);
-            out[4 * q + 2] = __uint_as_float(t.y << 16);
-            out[4 * q + 3] = __uint_as_float(t.y & 0xFFFF0000u);
+            const bool in = q == 0 || 4 * q < R;
+            const uint2 t = reinterpret_cast<const uint2 *>(p)[in ? q : 0];
+            out[4 * q] = in ? __uint_as_float(t.x << 16) : 0.0f;
+            out[4 * q + 1] = in ? __uint_as_float(t.x & 0xFFFF0000u) : 0.0f;
+            out[4 * q + 2] = in ? __uint_as_float(t.y << 16) : 0.0f;
+            out[4 * q + 3] = in ? __uint_as_float(t.y & 0xFFFF0000u) : 0.0f;
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            out[r] = r < R ? bf16_to_f32(p[r]) : 0.0f;
+        for (int r = 0; r < 16; ++r) {
+            const bool in = r == 0 || r < R;
+            const uint16_t t = p[in ? r : 0];
+            out[r] = in ? bf16_to_f32(t) : 0.0f;
+        }
     }
 }
 
-template <int NM, int RW, bool BF16>
-__global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
+template <int NM, int RW, bool BF16, bool V4>
+__device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
 {
-    NTC_ROW_RESOLVE(a, blk_);
-    const int id = blk_ * 256 + threadIdx.x;
-    if (id >= a.n_tiny)
-        return;
     const int nm = (NM > 0) ? NM : a.nmodes;
     const int R = a.R;
-    const bool v4 = (R & 3) == 0;  // uniform over the block (one problem per block)
     const RowItem ri = a.tiny[id];
     const int row = ri.row;
     const int64_t base = ri.base;
@@ -592,29 +604,37 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const int64_t roff = static_cast<int64_t>(row) * R;
     float y[16];
-    load_row16(ysrc + roff, R, v4, y);
+    load_row16<V4>(ysrc + roff, R, y);
 
-    // sampled records first (all in flight), then the factor rows
+    // the sample positions, then every record load at once (no load under
+    // a branch: a missing sample reads entry 0 of the row and takes the
+    // zero record, whose rows are zero and whose value is 0), then the
+    // factor rows
+    int64_t at[kTinyB];
+#pragma unroll
+    for (int j = 0; j < kTinyB; ++j) {
+        at[j] = base;
+        if (j < b)
+            at[j] = base + prp_index(prp, static_cast<uint32_t>(j));
+    }
     uint32_t rec[kTinyB][RW];
 #pragma unroll
     for (int j = 0; j < kTinyB; ++j) {
-        if (j < b) {
-            const uint32_t q = prp_index(prp, static_cast<uint32_t>(j));
-            const uint4 *src = reinterpret_cast<const uint4 *>(a.records + (base + q) * RW);
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.records + at[j] * RW);
 #pragma unroll
-            for (int w4 = 0; w4 < RW / 4; ++w4) {
-                const uint4 t = src[w4];
-                rec[j][4 * w4] = t.x;
-                rec[j][4 * w4 + 1] = t.y;
-                rec[j][4 * w4 + 2] = t.z;
-                rec[j][4 * w4 + 3] = t.w;
-            }
-        } else {
-#pragma unroll
-            for (int w = 0; w < RW; ++w)
-                rec[j][w] = a.zrec[w];  // the zero rows, value 0
+        for (int w4 = 0; w4 < RW / 4; ++w4) {
+            const uint4 t = src[w4];
+            rec[j][4 * w4] = t.x;
+            rec[j][4 * w4 + 1] = t.y;
+            rec[j][4 * w4 + 2] = t.z;
+            rec[j][4 * w4 + 3] = t.w;
         }
     }
+#pragma unroll
+    for (int j = 0; j < kTinyB; ++j)
+#pragma unroll
+        for (int w = 0; w < RW; ++w)
+            rec[j][w] = (j < b) ? rec[j][w] : a.zrec[w];
     float kk[kTinyB][16];
     float gf[16];
 #pragma unroll
@@ -628,16 +648,14 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
         for (int mm = 0; mm < nm - 1; ++mm) {
             float f[16];
             if (BF16)
-                load_row16(a.gath16[mm] + rec[j][mm], R, v4, f);  // coordinate * R
+                load_row16<V4>(a.gath16[mm] + rec[j][mm], R, f);  // coordinate * R
             else
-                load_row16(a.gath[mm] + rec[j][mm], R, v4, f);
+                load_row16<V4>(a.gath[mm] + rec[j][mm], R, f);
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 kk[j][r] *= f[r];
         }
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            kk[j][r] = r < R ? kk[j][r] : 0.0f;
+        // (columns past R are zero: load_row16 zeroes them in every row)
         // a missing sample has k = 0 (zero rows) and x = 0: it adds nothing
         const float x = __uint_as_float(rec[j][nm - 1]);
         float pred = 0.0f;
@@ -739,6 +757,15 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
     if (L > 0.0) {
         const double sl = sqrt(L), sm = sqrt(lam);
         const double beta = (sl - sm) / (sl + sm);
+        // A_l: the row read for y when l == 0, else the whole row in one go
+        float al16[16];
+        if (a.l == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                al16[r] = y[r];
+        } else {
+            load_row16<V4>(a.A + roff, R, al16);
+        }
         // A_{l+1} = (y - g/L)_+ and Y_{l+1} = A_{l+1} + beta (A_{l+1} - A_l), four columns at a time
         auto step4 = [&](int r0, float (&an4)[4], float (&yn4)[4]) {
 #pragma unroll
@@ -747,7 +774,7 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
                 const double g = static_cast<double>(gf[r]) + lam * static_cast<double>(y[r]);
                 double an = static_cast<double>(y[r]) - g / L;
                 an = an > 0.0 ? an : 0.0;
-                const float ap = (a.l == 0) ? y[r] : (r < R ? a.A[roff + r] : 0.0f);
+                const float ap = al16[r];
                 an4[u] = static_cast<float>(an);
                 yn4[u] = static_cast<float>(an + beta * (an - static_cast<double>(ap)));
             }
@@ -758,7 +785,7 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
                 continue;
             float an4[4], yn4[4];
             step4(4 * q, an4, yn4);
-            if (v4) {
+            if (V4) {
                 reinterpret_cast<float4 *>(a.A + roff)[q] = make_float4(an4[0], an4[1], an4[2], an4[3]);
                 if (BF16)
                     reinterpret_cast<uint2 *>(a.A16 + roff)[q] =
@@ -788,6 +815,20 @@ __global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
             if (r < R)
                 a.Y[roff + r] = y[r];
     }
+}
+
+template <int NM, int RW, bool BF16>
+__global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    const int id = blk_ * 256 + threadIdx.x;
+    if (id >= a.n_tiny)
+        return;
+    // R % 4 is uniform over the block (one problem per block)
+    if ((a.R & 3) == 0)
+        tiny_row<NM, RW, BF16, true>(a, id);
+    else
+        tiny_row<NM, RW, BF16, false>(a, id);
 }
 
 // Rows split over several items: one 256-thread block per row; its 16

@@ -30,6 +30,13 @@ typedef const __attribute__((address_space(4))) RowArgs CRowArgs;
     if (a.stop != nullptr && *a.stop != 0)                   \
         return
 
+// c ? u : v for a 16-byte record, one component at a time (a select of the
+// whole vector can be lowered through private memory).
+__device__ __forceinline__ uint4 pick4(bool c, const uint4 &u, const uint4 &v)
+{
+    return make_uint4(c ? u.x : v.x, c ? u.y : v.y, c ? u.z : v.z, c ? u.w : v.w);
+}
+
 template <int W>
 __device__ __forceinline__ float group_sum(float v)
 {

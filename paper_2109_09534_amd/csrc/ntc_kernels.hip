@@ -172,9 +172,9 @@ template <int RW, class Args>
 __device__ __forceinline__ void stage_record(const Args &a, uint4 *buf, int lane, bool live, const uint4 &w0,
                                              const uint4 &w1)
 {
-    buf[lane * (RW / 4)] = live ? w0 : make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+    buf[lane * (RW / 4)] = pick4(live, w0, make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]));
     if (RW == 8)
-        buf[lane * (RW / 4) + 1] = live ? w1 : make_uint4(a.zrec[4], a.zrec[5], a.zrec[6], a.zrec[7]);
+        buf[lane * (RW / 4) + 1] = pick4(live, w1, make_uint4(a.zrec[4], a.zrec[5], a.zrec[6], a.zrec[7]));
     __builtin_amdgcn_wave_barrier();
 }
 

@@ -432,23 +432,27 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
     // Software pipeline over blocks of 64 samples (one record per lane,
     // double-buffered in LDS) and sub-batches of 4 steps (16 samples): the
     // records of block k+1 are in flight while block k is reduced, and the
-    // gathers of sub-batch s+1 while sub-batch s is.
+    // gathers of sub-batch s+1 while sub-batch s is.  No load sits under a
+    // branch (a record past the item's end is read from entry 0 and staged
+    // as the zero record; the gathers of a missing step read the zero rows),
+    // so the compiler counts the loads in flight and a wait for sub-batch s
+    // leaves the loads issued after it outstanding.
     struct Sub {
         float f0[NM - 1][4], f1[NM - 1][4];
     };
-    auto fetch = [&](int jb) {
-        uint4 w = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
-        if (lane < it.j1 - jb) {
-            const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
-            w = *reinterpret_cast<const uint4 *>(a.records + (base + q) * 4);
-        }
-        return w;
+    const uint4 zr = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+    auto fetch = [&](int jb, bool &live) {
+        live = lane < it.j1 - jb;
+        int64_t e = 0;
+        if (live)
+            e = base + prp_index(prp, static_cast<uint32_t>(jb + lane));
+        return *reinterpret_cast<const uint4 *>(a.records + e * 4);
     };
-    // gathers of steps [s0, s0 + ns) of a staged block (a missing sample reads the zero rows)
-    auto issue = [&](const uint4 *buf, int s0, int ns, Sub &S) {
+    // gathers of the four steps from s0 of a staged block
+    auto issue = [&](const uint4 *buf, int s0, Sub &S) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            if (t < ns) {
+            {
                 const uint4 rec = buf[4 * (s0 + t) + grp];
                 const uint32_t rw[3] = {rec.x, rec.y, rec.z};
 #pragma unroll
@@ -525,30 +529,31 @@ __global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
 
     Sub SA, SB;
     int buf = 0;
-    if (it.j0 < it.j1) {
-        const uint4 w = fetch(it.j0);
-        s_rec[lane] = w;
+    {
+        bool lv;
+        const uint4 w = fetch(it.j0, lv);
+        s_rec[lane] = pick4(lv, w, zr);
         __builtin_amdgcn_wave_barrier();
-        issue(s_rec, 0, nsteps(it.j0, 0), SA);
+        issue(s_rec, 0, SA);
     }
     for (int jb = it.j0; jb < it.j1; jb += 64) {
-        const bool more = jb + 64 < it.j1;
-        uint4 wn = make_uint4(0u, 0u, 0u, 0u);
-        if (more)
-            wn = fetch(jb + 64);  // in flight during this block
+        // the next block's records, in flight during this block (all zero
+        // records after the last block: staged and gathered, never reduced)
+        bool lvn;
+        const uint4 wn = fetch(jb + 64, lvn);
         const uint4 *cur = s_rec + 64 * buf;
-        issue(cur, 4, nsteps(jb, 1), SB);
+        issue(cur, 4, SB);
         compute(cur, 0, nsteps(jb, 0), SA);
-        issue(cur, 8, nsteps(jb, 2), SA);
+        issue(cur, 8, SA);
         compute(cur, 4, nsteps(jb, 1), SB);
         flush();
-        issue(cur, 12, nsteps(jb, 3), SB);
+        issue(cur, 12, SB);
         compute(cur, 8, nsteps(jb, 2), SA);
-        if (more) {
+        {
             uint4 *nxt = s_rec + 64 * (buf ^ 1);
-            nxt[lane] = wn;
+            nxt[lane] = pick4(lvn, wn, zr);
             __builtin_amdgcn_wave_barrier();
-            issue(nxt, 0, nsteps(jb + 64, 0), SA);
+            issue(nxt, 0, SA);
         }
         compute(cur, 12, nsteps(jb, 3), SB);
         flush();

@@ -670,19 +670,22 @@ __global__ __launch_bounds__(64) void k_rows64(NTC_ROW_PARAMS)
     struct Sub {
         float f[NM - 1][2][4];
     };
-    auto fetch = [&](int jb) {
-        uint4 w = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
-        if (lane < it.j1 - jb) {
-            const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
-            w = *reinterpret_cast<const uint4 *>(a.records + (base + q) * 4);
-        }
-        return w;
+    // no load under a branch, so the compiler counts the loads in flight: a
+    // record past the item's end is read from entry 0 and staged as the zero
+    // record, and the gathers of a missing step read the zero rows
+    const uint4 zr = make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]);
+    auto fetch = [&](int jb, bool &lv) {
+        lv = lane < it.j1 - jb;
+        int64_t e = 0;
+        if (lv)
+            e = base + prp_index(prp, static_cast<uint32_t>(jb + lane));
+        return *reinterpret_cast<const uint4 *>(a.records + e * 4);
     };
-    // gathers of steps [s0, s0 + ns), ns <= 2, of a staged block (a missing sample reads the zero rows)
-    auto issue = [&](const uint4 *buf, int s0, int ns, Sub &S) {
+    // gathers of the two steps from s0 of a staged block
+    auto issue = [&](const uint4 *buf, int s0, Sub &S) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            if (t < ns) {
+            {
                 const uint4 rec = buf[4 * (s0 + t) + grp];
                 const uint32_t rw[3] = {rec.x, rec.y, rec.z};
 #pragma unroll
@@ -787,29 +790,30 @@ __global__ __launch_bounds__(64) void k_rows64(NTC_ROW_PARAMS)
     // during this one, gathers of the next sub-batch during this one
     Sub SA, SB;
     int buf = 0;
-    if (it.j0 < it.j1) {
-        const uint4 w = fetch(it.j0);
-        s_rec[lane] = w;
+    {
+        bool lv;
+        const uint4 w = fetch(it.j0, lv);
+        s_rec[lane] = pick4(lv, w, zr);
         __builtin_amdgcn_wave_barrier();
-        issue(s_rec, 0, nsteps(it.j0, 0), SA);
+        issue(s_rec, 0, SA);
     }
     for (int jb = it.j0; jb < it.j1; jb += 64) {
-        const bool more = jb + 64 < it.j1;
-        uint4 wn = make_uint4(0u, 0u, 0u, 0u);
-        if (more)
-            wn = fetch(jb + 64);
+        // the next block's records (all zero records after the last block:
+        // staged and gathered, never reduced)
+        bool lvn;
+        const uint4 wn = fetch(jb + 64, lvn);
         const uint4 *cur = s_rec + 64 * buf;
 #pragma unroll
         for (int sp = 0; sp < 8; sp += 2) {
-            issue(cur, 2 * (sp + 1), nsteps(jb, sp + 1), SB);
+            issue(cur, 2 * (sp + 1), SB);
             compute(cur, 2 * sp, nsteps(jb, sp), SA);
             if (sp + 2 < 8) {
-                issue(cur, 2 * (sp + 2), nsteps(jb, sp + 2), SA);
-            } else if (more) {
+                issue(cur, 2 * (sp + 2), SA);
+            } else {
                 uint4 *nxt = s_rec + 64 * (buf ^ 1);
-                nxt[lane] = wn;
+                nxt[lane] = pick4(lvn, wn, zr);
                 __builtin_amdgcn_wave_barrier();
-                issue(nxt, 0, nsteps(jb + 64, 0), SA);
+                issue(nxt, 0, SA);
             }
             compute(cur, 2 * (sp + 1), nsteps(jb, sp + 1), SB);
             if (sp == 2 || sp == 6)

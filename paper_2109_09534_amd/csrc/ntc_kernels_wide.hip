@@ -397,13 +397,18 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
 }
 
 template <int NM, bool BF16, bool PAIRS>
-__global__ __launch_bounds__(64) void k_rows32(NTC_ROW_PARAMS)
+// Five waves per SIMD: at most 96 registers, no spills, with the 8 KB of
+// LDS below that is 20 waves per CU.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_rows32(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
     __shared__ uint4 s_rec[2 * 64];
     __shared__ double s_h[12 * 64];  // FP64 sums of the EE, EO, OO blocks: register v of lane l at v*64 + l
-    __shared__ double s_g[2 * 64];
-    __shared__ double s_v[32];
+    // after the sample loop the record buffers are free: the gradient
+    // partials (2 x 64) and the power method's vector (32) reuse them, which
+    // keeps the wave at 8 KB of LDS (20 waves per CU)
+    double *const s_g = reinterpret_cast<double *>(s_rec);
+    double *const s_v = s_g + 2 * 64;
     const Item it = a.items[blk_];
     const int lane = threadIdx.x;
     const int j = lane & 15;    // columns 2j (even) and 2j + 1 (odd)

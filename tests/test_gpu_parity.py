@@ -135,6 +135,14 @@ CASES = {
                               dict(c=0.5, lp_bound=1, power_iters=3)),
     "cw_r24_5way_generic": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=22), 24,
                                     dict(c=0.3, lp_bound=1)),
+    # items that end exactly on a block boundary (64 samples for R > 16, 16 batches of 16 for the
+    # chunks): the prefetch of the block after the last one has no sample and reads zero records
+    "r32_items_of_64": lambda: (synth.make_problem((200, 150, 80), 100_000, 16, seed=23), 32,
+                                dict(c=0.5, schedule={"item_samples": 64})),
+    "r48_items_of_64": lambda: (synth.make_problem((120, 100, 60), 100_000, 12, seed=24), 48,
+                                dict(c=0.5, schedule={"item_samples": 64})),
+    "zipf_r16_chunks_of_256": lambda: (synth.c1_small(seed=9), 16,
+                                       dict(c=0.2, schedule={"item_samples": 256, "group_max": 64})),
     # the twin of the paper's timing workload at full size (3.3M cells, c = 0.5), every rank it uses:
     # 24 to 1717 rows per mode, so every row of modes 0 and 1 is split over many items
     "scaling_twin_r10": lambda: (_twin(), 10, dict(c=0.5)),

@@ -636,8 +636,12 @@ __global__ __launch_bounds__(64) void k_rows64(NTC_ROW_PARAMS)
     NTC_ROW_RESOLVE(a, blk_);
     __shared__ uint4 s_rec[2 * 64];
     __shared__ double s_h[40 * 64];  // block b, register v of lane l at (4 b + v) * 64 + l
-    __shared__ double s_g[4 * 64];   // gradient partial of column 4 j + q of group g at q * 64 + 16 g + j
-    __shared__ double s_v[64];
+    // After the sample loop the record buffers are free and hold the gradient
+    // partials (column 4 j + q of group g at q * 64 + 16 g + j); the power
+    // method's vector reuses the start of s_h once every lane has read its
+    // row of H.  22 KB of LDS per wave: seven waves per CU instead of six.
+    double *const s_g = reinterpret_cast<double *>(s_rec);
+    double *const s_v = s_h;
     const Item it = a.items[blk_];
     const int lane = threadIdx.x;
     const int j = lane & 15;

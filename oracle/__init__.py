@@ -84,6 +84,9 @@ def lib():
         L.ora_lmax_cw.restype = ctypes.c_double
         L.ora_lmax_cw.argtypes = [_f64p, ctypes.c_int, ctypes.c_int]
         L.ora_set_lp_bound.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.ora_set_gather_bf16.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.ora_bf16.restype = ctypes.c_double
+        L.ora_bf16.argtypes = [ctypes.c_double]
         L.ora_row_step.restype = ctypes.c_int64
         L.ora_row_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _f64p, _f64p,
                                    _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -155,6 +158,12 @@ def lmax_cw(H: np.ndarray, iters: int = 20) -> float:
     return float(lib().ora_lmax_cw(_p(H, _f64p), H.shape[0], iters))
 
 
+def bf16(x: float) -> float:
+    """The BF16 copy of a factor value (via its FP32 rounding), as the
+    precision form gathers it."""
+    return float(lib().ora_bf16(float(x)))
+
+
 def set_threads(n: int) -> int:
     return int(lib().ora_set_threads(n))
 
@@ -167,7 +176,7 @@ class Oracle:
                  c: float = 0.1, lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20,
                  seed: int = 0, test_coords: Optional[np.ndarray] = None,
                  test_values: Optional[np.ndarray] = None, init: Optional[Sequence[np.ndarray]] = None,
-                 lp_bound: int = 0):
+                 lp_bound: int = 0, gather_bf16: bool = False):
         L = lib()
         self.dims = [int(d) for d in dims]
         self.N = len(self.dims)
@@ -194,8 +203,10 @@ class Oracle:
             raise ValueError("oracle rejected the problem")
         self._h = ctypes.c_void_p(h)
         L.ora_set_lp_bound(self._h, int(lp_bound))
+        L.ora_set_gather_bf16(self._h, int(bool(gather_bf16)))
         self.c, self.lam, self.max_inner, self.power_iters, self.seed = c, lam, max_inner, power_iters, seed
         self.lp_bound = int(lp_bound)
+        self.gather_bf16 = bool(gather_bf16)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -35,6 +35,10 @@
  *     nonnegative here (a Gram matrix of nonnegative rows plus lambda I), so
  *     by the Collatz-Wielandt formula this is >= lambda_max(H) for every
  *     positive v, and it is the largest row sum of H when T_pow = 0;
+ *   - optional precision form (an option of this implementation, not of the
+ *     paper): the other modes' factor values enter the Khatri-Rao rows as
+ *     bfloat16 copies of their FP32 values (ora_bf16); everything else,
+ *     including the row's own y, stays binary64;
  *   - lambda is not scaled by c; rows with B_{l,p} = 0, or with L_p <= 0,
  *     keep A and Y unchanged;
  *   - Nesterov restarts at every S_NMC call; Y is discarded on return;
@@ -74,6 +78,7 @@ typedef struct ora {
     double c, lambda;
     int max_inner, power_iters;
     int lp_bound; /* 0: Rayleigh quotient of the power iterate; 1: Collatz-Wielandt bound */
+    int gather_bf16; /* 1: the other modes' factor values enter the Khatri-Rao rows as BF16 copies */
     uint64_t seed;
     int64_t k; /* AO sweep counter */
     int64_t n_test;
@@ -410,6 +415,33 @@ void ora_free(ora_t *o)
     free(o);
 }
 
+/* ---------------------------------------------------------- BF16 copies */
+/* The precision form (not the paper's: an option of this implementation)
+ * keeps FP32 factors and gathers the other modes' rows from BF16 copies of
+ * them.  The copy of a factor value x is defined here from the two formats:
+ * x is first the FP32 factor entry (round to nearest, ties to even, as a C
+ * conversion does), then the bfloat16 number nearest to it (1 sign bit,
+ * 8 exponent bits, 7 fraction bits: the FP32 numbers whose low 16 bits are
+ * zero), ties to the one with an even last fraction bit.  Only finite values
+ * below the largest bfloat16 occur (factors are finite and >= 0). */
+double ora_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    uint32_t lo_bits = u & 0xFFFF0000u;             /* the bfloat16 toward zero */
+    uint32_t hi_bits = lo_bits + 0x00010000u;        /* the next one away from zero */
+    float lo, hi;
+    memcpy(&lo, &lo_bits, sizeof lo);
+    memcpy(&hi, &hi_bits, sizeof hi);
+    double dl = fabs((double)f - (double)lo), dh = fabs((double)hi - (double)f);
+    if (dl < dh)
+        return (double)lo;
+    if (dh < dl)
+        return (double)hi;
+    return (lo_bits & 0x00010000u) ? (double)hi : (double)lo; /* tie: even last bit */
+}
+
 /* ------------------------------------------------------------ one row step */
 /* Alg. 1 for row p of mode i at inner step l, with the other modes' factors
  * as they are now.  y, a are Y_l(p,:), A_l(p,:); writes A_{l+1}(p,:) and
@@ -446,7 +478,7 @@ int64_t ora_row_step(const ora_t *o, int i, int l, int64_t p, const double *y, c
                 continue;
             const double *row = o->U[m] + (int64_t)o->coords[e * N + m] * R;
             for (int r = 0; r < R; ++r)
-                ks[r] *= row[r];
+                ks[r] *= o->gather_bf16 ? ora_bf16(row[r]) : row[r];
         }
         double pred = 0.0;
         for (int r = 0; r < R; ++r)
@@ -631,6 +663,7 @@ void ora_set_sweep(ora_t *o, int64_t k) { o->k = k; }
 /* 0: L_p is the Rayleigh quotient of the power iterate; 1: the
  * Collatz-Wielandt upper bound of the same iterate. */
 void ora_set_lp_bound(ora_t *o, int bound) { o->lp_bound = bound ? 1 : 0; }
+void ora_set_gather_bf16(ora_t *o, int on) { o->gather_bf16 = on ? 1 : 0; }
 void ora_get_csr(const ora_t *o, int m, int64_t *rowptr_out, int64_t *perm_out)
 {
     memcpy(rowptr_out, o->rowptr[m], (size_t)(o->dims[m] + 1) * sizeof(int64_t));

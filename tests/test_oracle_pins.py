@@ -451,3 +451,60 @@ def test_planted_recovery_on_the_cpu_sized_workload():
     after = o.loss()[3]
     assert after < before
     assert after <= 1e-2, after
+
+
+# ------------------------------------------------------ BF16 precision form
+def test_bf16_copy_is_the_nearest_bfloat16_of_the_fp32_value():
+    """ora_bf16 against torch's float32 -> bfloat16 conversion (round to
+    nearest, ties to even), on random magnitudes and on exact ties."""
+    import torch
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.uniform(0, 1, 4000), rng.uniform(0, 40, 2000),
+                        np.exp(rng.uniform(-60, 60, 2000)), [0.0, 1.0, 2.0 ** -130]])
+    # exact ties between two neighbouring bfloat16 numbers, both parities
+    ties = [1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 2 + 2.0 ** -7, 0.5 + 3 * 2.0 ** -9]
+    x = np.concatenate([x, ties, -np.asarray(ties)])
+    ref = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([O.bf16(v) for v in x])
+    assert np.array_equal(got, ref)
+    assert O.bf16(1 + 2.0 ** -8) == 1.0 and O.bf16(1 + 3 * 2.0 ** -8) == 1 + 2.0 ** -6
+    assert O.bf16(2 + 2.0 ** -7) == 2.0 and O.bf16(0.5 + 3 * 2.0 ** -9) == 0.5 + 2.0 ** -7
+    # the FP32 rounding comes first: a value just above a tie in binary64 but
+    # equal to the tie in FP32 rounds to even
+    assert O.bf16(1 + 2.0 ** -8 + 2.0 ** -40) == 1.0
+
+
+def test_bf16_gathers_change_nothing_when_the_factors_are_bfloat16_numbers():
+    """Factors with at most 8 significant bits are their own bfloat16 copies,
+    so a mode update is bit-identical with and without BF16 gathers; with
+    ordinary FP32 factors the option does change the result."""
+    p = synth.make_problem((14, 12, 10), 900, 3, seed=31, test_frac=0.0)
+    rng = np.random.default_rng(3)
+    exact = [(rng.integers(0, 256, (d, 5)) * 2.0 ** -8).astype(np.float32) for d in p.dims]
+    plain = [rng.uniform(0, 1, (d, 5)).astype(np.float32) for d in p.dims]
+    for init, same in [(exact, True), (plain, False)]:
+        a = O.Oracle(p.dims, p.coords, p.values, 5, c=0.5, init=init)
+        b = O.Oracle(p.dims, p.coords, p.values, 5, c=0.5, init=init, gather_bf16=True)
+        a.update_mode(0)
+        b.update_mode(0)
+        assert np.array_equal(a.factors(0), b.factors(0)) == same
+
+
+@pytest.mark.parametrize("max_inner", [1, 2])
+def test_bf16_full_batch_mode_update_matches_dense_algorithm_on_rounded_factors(max_inner):
+    """c = 1 with BF16 gathers equals the dense Alg. 1 whose Khatri-Rao matrix
+    is built from the bfloat16 copies (torch's conversion) of the other
+    modes' FP32 factors, while the row's own iterate stays unrounded."""
+    import torch
+    p, o, U = _row_setup(c=1.0, lam=0.01)
+    init = [u.astype(np.float32) for u in U]
+    o2 = O.Oracle(p.dims, p.coords, p.values, o.R, c=1.0, lam=0.01, max_inner=max_inner, seed=o.seed,
+                  init=init, gather_bf16=True)
+    X, M = brute.dense_data(p.dims, p.coords, p.values)
+    Ud = [o2.factors(m) for m in range(3)]
+    for mode in range(3):
+        rounded = [torch.tensor(u.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+                   if m != mode else u for m, u in enumerate(Ud)]
+        o2.update_mode(mode)
+        Ud[mode] = brute.full_batch_mode_update(X, M, rounded, mode, 0.01, max_inner)
+        np.testing.assert_allclose(o2.factors(mode), Ud[mode], rtol=1e-9, atol=1e-12)

@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--bf16", action="store_true", help="BF16 shadow gathers (precision form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-errors", action="store_true",
+                    help="c2: skip the FP32/BF16 error statement against the FP64 oracle (1/10-nnz instance)")
+    ap.add_argument("--oracle-sweeps", type=int, default=4,
+                    help="c2: sweeps of the precision check against the oracle")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "scaling", "convergence"], default="c1",
                     help="c1: one 100M-entry problem (default); c2: one 4-way 500M-entry R=32 problem; "
@@ -107,7 +111,10 @@ def main():
                     help="c1/c2: build the per-mode CSR on the GPU (ntc_create_device_csr)")
     ap.add_argument("--ranks", default="10,30,50", help="scaling: ranks R")
     ap.add_argument("--instances", type=int, default=256, help="batch/serve: number of problems")
-    ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-at-a-time baseline")
+    ap.add_argument("--no-plain", action="store_true", help="batch/serve: skip the one-at-a-time FP32 baseline")
+    ap.add_argument("--oracle-instances", type=int, default=32,
+                    help="batch/serve: problems (evenly spread over the stream) whose final held-out RMSE is "
+                         "checked against the FP64 oracle run to the same plateau rule (0 = none)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch: library default schedule instead of one tuned per kernel family")
     ap.add_argument("--rates", default="0.25,0.5,1,2", help="serve: arrival rates as fractions of saturation")
@@ -146,7 +153,7 @@ def main():
         p = synth.c2(seed=args.seed, scale=args.scale)
         wl = ("4-way 1000000x500000x1000x100, 500M Zipf(1.05) entries, rank-32 CPD + N(0,0.05) clipped at 0, "
               "5% test; R=32, c=0.1, lambda=1e-3, MAX_INNER=1")
-        args.no_cpu_baseline = True     # the FP64 oracle baseline is taken on the default workload
+        args.no_cpu_baseline = True     # the oracle is timed on the 1/10-nnz instance of the precision check
     else:
         R = 16
         log(f"generating the 480000x18000x2000 Zipf(1.1) workload, scale {args.scale} ...")
@@ -243,6 +250,9 @@ def main():
         log(f"{other['gather']} gathers: {other['ms_per_step']} ms per sweep, test RMSE {other['test_rmse']}")
 
     cpu = None
+    precision = None
+    if args.workload == "c2" and not args.no_oracle_errors:
+        precision, cpu = c2_precision_vs_oracle(args, c, lam, max_inner)
     if not args.no_cpu_baseline:
         import oracle as O
         threads = args.cpu_threads or len(os.sched_getaffinity(0))
@@ -294,7 +304,65 @@ def main():
     }
     if other is not None:
         out["other_precision"] = other
+    if precision is not None:
+        out["precision_vs_oracle"] = precision
     print(json.dumps(out), flush=True)
+
+
+def c2_precision_vs_oracle(args, c, lam, max_inner):
+    """The precision form's error against the FP64 oracle, on a 1/10-nnz
+    instance of the 4-way workload (same dims and distributions, 50M
+    entries, so the oracle finishes in seconds): from the same default
+    initial factors, the relative Frobenius error of every factor after one
+    sweep for FP32 and for BF16 gathers, and the held-out RMSE of both after
+    `oracle_sweeps` sweeps beside the oracle's.  The oracle's first sweep is
+    also the CPU baseline of this workload."""
+    import numpy as np
+
+    import oracle as O
+    import paper_2109_09534_amd as ntc
+    import synth
+
+    R, K = 32, args.oracle_sweeps
+    t0 = time.perf_counter()
+    p = synth.c2(seed=args.seed, scale=0.1)
+    log(f"precision check: 1/10-nnz instance, {p.nnz} train entries, generated in {time.perf_counter() - t0:.1f} s")
+    res = {}
+    for bf in (False, True):
+        g = ntc.Problem(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=max_inner, seed=args.seed,
+                        gather_bf16=bf, test_coords=p.test_coords, test_values=p.test_values, stream=0)
+        g.sweep(1)
+        res[bf] = {"f1": g.all_factors()}
+        g.sweep(K - 1)
+        res[bf]["loss"] = g.loss()
+        g.close()
+    threads = args.cpu_threads or len(os.sched_getaffinity(0))
+    used = O.set_threads(threads)
+    o = O.Oracle(p.dims, p.coords, p.values, R, c=c, lam=lam, max_inner=max_inner, seed=args.seed,
+                 test_coords=p.test_coords, test_values=p.test_values)
+    upd = _updates_per_sweep(p, c)
+    t0 = time.perf_counter()
+    o.sweep(1)
+    cpu_s = time.perf_counter() - t0
+    f1 = [o.factors(m) for m in range(p.nmodes)]
+    log(f"oracle: first sweep {cpu_s:.2f} s on {used} threads; {K - 1} more sweeps")
+    o.sweep(K - 1)
+    lo = o.loss()
+    o.close()
+    out = {"instance": f"4-way 1000000x500000x1000x100, {p.nnz} Zipf(1.05) train entries (1/10 of the "
+                       f"workload's, same dims and distributions), {p.test_values.shape[0]} held out",
+           "sweeps": K, "oracle_test_rmse": round(float(lo[2]), 6)}
+    for bf in (False, True):
+        errs = [float(np.linalg.norm(res[bf]["f1"][m] - f1[m]) / np.linalg.norm(f1[m])) for m in range(p.nmodes)]
+        tr = float(res[bf]["loss"][2])
+        out["bf16" if bf else "f32"] = {"one_sweep_rel_err_per_mode": [float(f"{e:.3e}") for e in errs],
+                                        "test_rmse": round(tr, 6), "test_rmse_minus_oracle": float(f"{tr - lo[2]:.3e}")}
+        log(f"{'BF16' if bf else 'FP32'} gathers: one-sweep error vs FP64 per mode {errs}; test RMSE after {K} "
+            f"sweeps {tr:.6f} (oracle {lo[2]:.6f})")
+    cpu = {"value": round(upd / cpu_s, 1), "unit": "updates/s", "cores": used, "kind": "oracle",
+           "sample": f"one full AO sweep ({upd} sampled entries, all 4 modes) of the 1/10-nnz instance, FP64, "
+                     f"{cpu_s:.2f} s"}
+    return out, cpu
 
 
 # ------------------------------------------------------------ scaling twin
@@ -518,6 +586,7 @@ def run_batch(args):
     nnz = sum(p.nnz for p in probs)
     log(f"generated {n} problems, {nnz} train entries in {gen_s:.1f} s")
     kw = dict(c=0.1, lam=1e-3, gather_bf16=args.bf16)
+    kw_plain = dict(c=0.1, lam=1e-3, gather_bf16=False)   # the plain method: FP32 gathers
 
     # one schedule per kernel family (R <= 16, R <= 32), tuned on its largest problem
     sched = {}
@@ -564,24 +633,41 @@ def run_batch(args):
     pool.close()
 
     plain = None
+    plain_rmse = None
     if not args.no_plain:
         t0 = time.perf_counter()
         diffs = []
+        plain_rmse = []
         for (dims, _, R, sd), p, q in zip(shapes, probs, per):
             g = ntc.Problem(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
-                            test_values=p.test_values, stream=0, schedule=schedule_of(R), **kw)
+                            test_values=p.test_values, stream=0, schedule=schedule_of(R), **kw_plain)
             hist = [g.loss()[2]]
             while _stop_at(hist) is None:
                 g.sweep(1)
                 hist.append(g.loss()[2])
             g.close()
+            plain_rmse.append(hist[-1])
             diffs.append((len(hist) - 1 - q[1], abs(hist[-1] - q[2])))
         plain_s = time.perf_counter() - t0
         plain = {"value": round(n / plain_s, 3), "unit": "instances/s", "seconds": round(plain_s, 3),
-                 "kind": "the same problems one at a time through ntc_create/ntc_sweep/ntc_loss, create included",
-                 "max_stop_sweep_diff": int(max(abs(d[0]) for d in diffs)),
-                 "max_final_rmse_diff": float(max(d[1] for d in diffs))}
-        log(f"plain one-at-a-time: {plain_s:.2f} s")
+                 "dtype": "f32",
+                 "kind": "the same problems one at a time through ntc_create/ntc_sweep/ntc_loss with FP32 "
+                         "gathers, create included",
+                 "max_stop_sweep_diff_vs_pool": int(max(abs(d[0]) for d in diffs)),
+                 "max_final_rmse_diff_vs_pool": float(max(d[1] for d in diffs))}
+        log(f"plain one-at-a-time (FP32): {plain_s:.2f} s")
+
+    check = None
+    if args.oracle_instances > 0:
+        idx = sorted(set(np.linspace(0, n - 1, min(n, args.oracle_instances)).astype(int).tolist()))
+        t0 = time.perf_counter()
+        targets, threads = _oracle_plateau([(probs[i], shapes[i][2], shapes[i][3]) for i in idx], args.cpu_threads)
+        ora_s = time.perf_counter() - t0
+        check = _rmse_check(idx, targets, [per[i][2] for i in idx],
+                            None if plain_rmse is None else [plain_rmse[i] for i in idx])
+        check.update({"oracle": f"FP64 oracle from the same default initial factors and seeds, same plateau "
+                                f"rule, {threads} threads, {ora_s:.1f} s"})
+        log(f"oracle check on {len(idx)} problems: {check}")
     out = {
         "metric": "instances/s", "value": round(n / (admit_s + run_s), 3), "unit": "instances/s",
         "n_gpus": 1, "steps": sweeps, "warmup": 0, "ms_per_step": round(run_s * 1e3 / max(sweeps, 1), 4),
@@ -597,14 +683,54 @@ def run_batch(args):
         "sweeps_per_instance": {"min": int(min(q[1] for q in per)), "median": float(np.median([q[1] for q in per])),
                                 "max": int(max(q[1] for q in per))},
         "plain": plain,
+        "speedup_vs_plain": None if plain is None else round((n / (admit_s + run_s)) / plain["value"], 2),
+        "oracle_check": check,
     }
     print(json.dumps(out), flush=True)
+
+
+def _oracle_plateau(items, cpu_threads=0, W=5, tol=1e-4, cap=500):
+    """Run the FP64 oracle on each (problem, R, seed) from the default initial
+    factors to the held-out plateau (the pool's stop rule): returns the final
+    held-out RMSE and stop sweep of each, and the threads used."""
+    import oracle as O
+    threads = O.set_threads(cpu_threads or len(os.sched_getaffinity(0)))
+    out = []
+    for p, R, sd in items:
+        o = O.Oracle(p.dims, p.coords, p.values, R, c=0.1, lam=1e-3, seed=sd, test_coords=p.test_coords,
+                     test_values=p.test_values)
+        hist = [o.loss()[2]]
+        while _stop_at(hist, W, tol, cap) is None:
+            o.sweep(1)
+            hist.append(o.loss()[2])
+        o.close()
+        out.append((float(hist[-1]), len(hist) - 1))
+    return out, threads
+
+
+def _rmse_check(idx, targets, got, plain=None, tol=1e-3):
+    """Final held-out RMSE of the sampled problems against the oracle's:
+    within tol (|diff| <= tol) and at or below the target oracle + tol."""
+    import numpy as np
+    d = np.asarray(got) - np.asarray([t[0] for t in targets])
+    out = {"instances": len(idx), "indices": idx, "tolerance": tol,
+           "within_tol": int(np.sum(np.abs(d) <= tol)), "at_or_below_target": int(np.sum(d <= tol)),
+           "max_abs_diff": float(f"{np.max(np.abs(d)):.3e}"),
+           "oracle_stop_sweeps": {"min": int(min(t[1] for t in targets)), "max": int(max(t[1] for t in targets))}}
+    if plain is not None:
+        dp = np.asarray(plain) - np.asarray([t[0] for t in targets])
+        out["plain_within_tol"] = int(np.sum(np.abs(dp) <= tol))
+        out["plain_max_abs_diff"] = float(f"{np.max(np.abs(dp)):.3e}")
+    return out
 
 
 def run_serve(args):
     """Poisson arrivals into a pool (95% batching mixture, 5% 200000x50000x500
     problems with 20M Zipf(1.1) entries, R = 16), BF16 gathers; latency is
-    arrival -> plateau stop, admission (host CSR build) included."""
+    arrival -> plateau stop, admission (host CSR build) included.  Beside it:
+    the plain method (FP32 gathers, one request at a time through
+    ntc_create/ntc_sweep/ntc_loss) on the same arrival times, and for a sample
+    of requests the FP64 oracle's final held-out RMSE as the target."""
     import collections
 
     import numpy as np
@@ -628,19 +754,22 @@ def run_serve(args):
             dims, _, R, sd = shapes[i]
             reqs.append((small[i], R, sd))
     kw = dict(c=0.1, lam=1e-3, gather_bf16=True)
+    rates = [float(x) for x in args.rates.split(",") if x]
+    unit_gaps = rng.exponential(1.0, (len(rates), n))   # arrival gaps at rate 1, scaled per rate
 
-    def serve(rate):
-        """Open loop at `rate` requests/s (rate 0: everything arrives at once).
-        A request's host work (CSR, schedule) starts on a worker thread when it
-        arrives; the pool admits it once that is done, without waiting."""
+    def serve(arrive):
+        """Open loop with the given arrival times (all zero: everything at
+        once).  A request's host work (CSR, schedule) starts on a worker thread
+        when it arrives; the pool admits it once that is done, without
+        waiting.  Returns the wall time, each request's latency and the
+        held-out RMSE at which it stopped."""
         import concurrent.futures as cf
-        gaps = rng.exponential(1.0 / rate, n) if rate > 0 else np.zeros(n)
-        arrive = np.cumsum(gaps) - (gaps[0] if rate > 0 else 0.0)
         pool = ntc.Pool(max_slots=min(n, 1024), window=5, tol=1e-4, max_sweeps=500)
         ex = cf.ThreadPoolExecutor(max_workers=args.prepare_threads)
         queue = collections.deque()
         slot_req = {}
         lat = np.zeros(n)
+        rmse = np.zeros(n)
         nxt = done = 0
         start = time.perf_counter()
         while done < n:
@@ -670,31 +799,91 @@ def run_serve(args):
             for s in pool.stopped():
                 i = slot_req.pop(s)
                 lat[i] = time.perf_counter() - start - arrive[i]
+                rmse[i] = pool.query(s)[2]
                 pool.evict(s)
                 done += 1
         wall = time.perf_counter() - start
         ex.shutdown()
         pool.close()
-        return wall, lat
+        return wall, lat, rmse
 
-    wall, lat = serve(0.0)
+    def fifo(arrive, service):
+        """Latencies of one server taking requests one at a time in arrival order."""
+        fin = np.zeros(n)
+        t = 0.0
+        for i in range(n):
+            t = max(t, arrive[i]) + service[i]
+            fin[i] = t
+        return fin[-1] - arrive[0], fin - arrive
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)), 4)
+
+    wall, lat, rm = serve(np.zeros(n))
     sat = n / wall
     log(f"saturation (all {n} at once): {wall:.2f} s -> {sat:.2f} requests/s")
-    rows = [{"rate_fraction": 0.0, "rate": None, "completions_per_s": round(sat, 3),
-             "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4)}]
-    for f in [float(x) for x in args.rates.split(",") if x]:
-        wall, lat = serve(f * sat)
-        rows.append({"rate_fraction": f, "rate": round(f * sat, 3), "completions_per_s": round(n / wall, 3),
-                     "p50_s": round(float(np.percentile(lat, 50)), 4),
-                     "p99_s": round(float(np.percentile(lat, 99)), 4)})
-        log(f"rate {f} x saturation: p50 {rows[-1]['p50_s']} s, p99 {rows[-1]['p99_s']} s")
+    runs = [(0.0, np.zeros(n), wall, lat, rm)]
+    for j, f in enumerate(rates):
+        arrive = np.cumsum(unit_gaps[j] / (f * sat))
+        arrive -= arrive[0]
+        w, l, r = serve(arrive)
+        runs.append((f, arrive, w, l, r))
+        log(f"rate {f} x saturation: p50 {pct(l, 50)} s, p99 {pct(l, 99)} s")
+
+    service = plain_rmse = None
+    if not args.no_plain:
+        service = np.zeros(n)
+        plain_rmse = np.zeros(n)
+        for i, (p, R, sd) in enumerate(reqs):
+            t0 = time.perf_counter()
+            g = ntc.Problem(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
+                            test_values=p.test_values, stream=0, c=0.1, lam=1e-3, gather_bf16=False)
+            hist = [g.loss()[2]]
+            while _stop_at(hist) is None:
+                g.sweep(1)
+                hist.append(g.loss()[2])
+            g.close()
+            service[i] = time.perf_counter() - t0
+            plain_rmse[i] = hist[-1]
+        log(f"plain one-at-a-time (FP32): {service.sum():.2f} s of service for {n} requests")
+
+    idx = []
+    targets = []
+    ora_note = None
+    if args.oracle_instances > 0:
+        idx = sorted(set(np.linspace(0, n - 1, min(n, args.oracle_instances)).astype(int).tolist()))
+        t0 = time.perf_counter()
+        targets, threads = _oracle_plateau([reqs[i] for i in idx], args.cpu_threads)
+        ora_note = (f"FP64 oracle from the same default initial factors and seeds, same plateau rule, "
+                    f"{threads} threads, {time.perf_counter() - t0:.1f} s, on requests {idx} "
+                    f"({sum(reqs[i][0].nnz > 10_000_000 for i in idx)} of them large)")
+        log(ora_note)
+
+    rows = []
+    for f, arrive, w, l, r in runs:
+        row = {"rate_fraction": f, "rate": None if f == 0 else round(f * sat, 3),
+               "completions_per_s": round(n / w, 3), "p50_s": pct(l, 50), "p99_s": pct(l, 99)}
+        if idx:
+            row["oracle_check"] = _rmse_check(idx, targets, [r[i] for i in idx],
+                                              None if plain_rmse is None else [plain_rmse[i] for i in idx])
+        if service is not None:
+            pw, pl = fifo(arrive, service)
+            row["plain"] = {"completions_per_s": round(n / pw, 3), "p50_s": pct(pl, 50), "p99_s": pct(pl, 99)}
+        rows.append(row)
     out = {"metric": "completions/s at saturation", "value": round(sat, 3), "unit": "requests/s", "n_gpus": 1,
            "steps": n, "warmup": 0, "ms_per_step": round(1e3 / sat, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16-gather/f32", "data": "synthetic",
            "config": {"workload": f"{n} requests: 95% batching mixture, 5% 200000x50000x500 20M Zipf(1.1) R=16; "
                                   "BF16 gathers, plateau stop; Poisson arrivals; host CSR on "
                                   f"{args.prepare_threads} worker threads", "requests": n, "seed": args.seed},
-           "latency": rows}
+           "latency": rows,
+           "plain": None if service is None else {
+               "kind": "FP32 gathers, one request at a time through ntc_create/ntc_sweep/ntc_loss (create "
+                       "included); latencies are those of one server taking the requests in arrival order at "
+                       "the same arrival times, from each request's measured service time",
+               "saturation_per_s": round(n / float(service.sum()), 3),
+               "max_final_rmse_diff_vs_pool": float(f"{np.max(np.abs(plain_rmse - runs[0][4])):.3e}")},
+           "oracle": ora_note}
     print(json.dumps(out), flush=True)
 
 

@@ -126,14 +126,16 @@ __device__ __forceinline__ double cw_ratio(bool live, double v, double w)
 // sum of x over the lanes of the row.  Normalising by ||H v|| only fixes the
 // length of the iterate, so the products are scaled by exact powers of two
 // instead, which round nothing: the first product fixes 2^-e with
-// 2^e <= ||H v_0|| < 2^(e+1), every later product takes the same 2^-e, and
-// the iterate is brought back near unit length once at the end.  H here is a
-// sampled Gram matrix of nonnegative rows plus lambda I, so its top
-// eigenvector u is nonnegative and ||H v_0|| >= L u.v_0 >= L / sqrt(R): each
-// later product scales the length by less than 2 sqrt(R), never shrinks the
-// component along u, and the iterate stays far inside FP64's range.  Returns
-// false if H v_0 vanishes (L = 0 by definition); else v is the final iterate
-// and vv = ||v||^2 exactly.
+// 2^e <= ||H v_0|| < 2^(e+1) and every later product takes the same 2^-e.
+// H here is a sampled Gram matrix of nonnegative rows plus lambda I, so its
+// top eigenvector u is nonnegative and ||H v_0|| >= L u.v_0 >= L / sqrt(R):
+// each later product scales the length by less than 2 sqrt(R) and never
+// shrinks the component along u.  Every 32 products the iterate is brought
+// back near unit length by another power of two (32 products grow it by at
+// most (2 sqrt(64))^32 = 2^128, so its sum of squares stays far inside
+// FP64's range for any T), and once more at the end.  Returns false if
+// H v_0 vanishes (L = 0 by definition); else v is the final iterate and
+// vv = ||v||^2 exactly.
 template <class MV, class SUM>
 __device__ __forceinline__ bool power_iterate(double &v, double &vv, int T, MV mv, SUM sum)
 {
@@ -149,8 +151,15 @@ __device__ __forceinline__ bool power_iterate(double &v, double &vv, int T, MV m
         vv = ldexp(n2, -2 * e);
         return true;
     }
-    for (int t = 1; t < T; ++t)
+    for (int t = 1; t < T; ++t) {
         v = ldexp(mv(v), -e);
+        if ((t & 31) == 0 && t + 1 < T) {  // wave-uniform: T is
+            n2 = sum(v * v);
+            if (!(n2 > 0.0))
+                return false;
+            v = ldexp(v, -(ilogb(n2) >> 1));
+        }
+    }
     n2 = sum(v * v);
     if (!(n2 > 0.0))
         return false;

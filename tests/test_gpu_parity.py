@@ -33,8 +33,9 @@ def _setup():
     ntc.lib()
 
 
-def _pair(p, R, *, init_seed=1, scale=None, **kw):
-    """(gpu problem, oracle) on identical FP32 init."""
+def _pair(p, R, *, init_seed=1, scale=None, ora_bf16=False, **kw):
+    """(gpu problem, oracle) on identical FP32 init.  The oracle is the plain
+    FP64 method unless ora_bf16 asks for its BF16-gather form."""
     if scale is None:
         scale = synth.init_scale(p.values, R, len(p.dims))
     init = synth.uniform_init(p.dims, R, init_seed, scale)
@@ -42,7 +43,7 @@ def _pair(p, R, *, init_seed=1, scale=None, **kw):
                     init=init, stream=0, **kw)
     okw = {k: v for k, v in kw.items() if k not in ("gather_bf16", "schedule")}
     o = O.Oracle(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
-                 init=init, **okw)
+                 init=init, gather_bf16=ora_bf16, **okw)
     return g, o, init
 
 
@@ -152,6 +153,15 @@ CASES = {
     # extrapolated inner steps of the MAX_INNER study
     "convergence_twin_c005_inner2": lambda: (_conv(), 10, dict(c=0.05, max_inner=2)),
     "convergence_twin_c05_inner2": lambda: (_conv(), 10, dict(c=0.5, max_inner=2)),
+    # long power iterations: the iterate is rescaled every 32 products, so T_pow = 200 stays finite in every
+    # finishing path (16-lane groups and chunks, 32-lane halves, whole waves, the generic kernel)
+    "zipf_r16_power200": lambda: (synth.c1_small(seed=10), 16, dict(c=0.1, power_iters=200)),
+    "r32_power200_split": lambda: (synth.make_problem((200, 150, 80), 100_000, 16, seed=26, zipf_s=1.1), 32,
+                                   dict(c=0.3, power_iters=200, schedule={"item_samples": 128})),
+    "r64_power200": lambda: (synth.make_problem((80, 60, 50, 40), 100_000, 12, seed=27), 64,
+                             dict(c=0.4, power_iters=200)),
+    "r24_5way_power200": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=28), 24,
+                                  dict(c=0.3, power_iters=200)),
 }
 
 
@@ -208,6 +218,69 @@ def test_bf16_gathers_final_rmse_within_1e3_of_oracle():
     o.sweep(19)
     lg, lo = g.loss(), o.loss()
     _say(f"  BF16 GPU loss {lg}, oracle {lo}")
+    assert abs(lg[2] - lo[2]) <= 1e-3
+
+
+# The precision form against the oracle's BF16-gather form (other-mode factor values rounded to bfloat16 from
+# their FP32 values, everything else FP64).  Mode by mode from shared FP32 factors both sides gather the same
+# bfloat16 numbers, so the one-update bar of the plain path applies element by element.
+BF16_CASES = {
+    # the 4-way R = 32 kernel of the 500M-entry precision workload (column pairs), Zipf(1.05) heads split
+    # over many items
+    "c2_kernel_r32_4way_split": lambda: (synth.make_problem((300, 200, 60, 20), 300_000, 32, noise_var=0.05,
+                                                            value_model="clip0", zipf_s=1.05, seed=40,
+                                                            test_frac=0.05), 32,
+                                         dict(c=0.1, schedule={"item_samples": 128})),
+    "r27_4way_odd_columns": lambda: (synth.make_problem((200, 150, 40, 16), 200_000, 12, zipf_s=1.05, seed=41,
+                                                        test_frac=0.05), 27, dict(c=0.2)),
+    "r8_zipf_tiny_groups_chunks": lambda: (synth.c1_small(seed=11), 8, dict(c=0.1)),
+    "r16_zipf_chunks_of_256": lambda: (synth.c1_small(seed=12), 16,
+                                       dict(c=0.2, schedule={"item_samples": 256, "group_max": 64})),
+    "r48_4way_quads": lambda: (synth.make_problem((120, 100, 60, 30), 150_000, 12, seed=42, zipf_s=1.1,
+                                                  test_frac=0.05), 48, dict(c=0.3)),
+    "r24_5way_generic": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=43, test_frac=0.05), 24,
+                                 dict(c=0.3)),
+}
+
+
+@pytest.mark.parametrize("case", list(BF16_CASES))
+def test_bf16_mode_updates_match_the_oracle_bf16_form(case):
+    p, R, kw = BF16_CASES[case]()
+    _say(f"case {case}: dims {p.dims} nnz {p.nnz} R {R} {kw}")
+    g, o, init = _pair(p, R, gather_bf16=True, ora_bf16=True, **kw)
+    for m in range(len(p.dims)):
+        g.update_mode(m)
+        o.update_mode(m)
+        gm = g.factors(m)
+        assert np.all(gm >= 0.0)
+        _assert_factor_close(gm.astype(np.float64), o.factors(m), f"mode {m}")
+        o.set_factors(m, gm.astype(np.float64))
+
+
+def test_bf16_c2_kernel_error_against_fp64_is_what_bf16_rounding_implies():
+    """The 4-way R = 32 precision kernel against the plain FP64 oracle: its
+    one-sweep error is the error that rounding the gathers to bfloat16
+    causes in the oracle itself (same samples, FP64 elsewhere), not more,
+    and after 20 sweeps its held-out RMSE is within 1e-3 of the FP64
+    oracle's."""
+    p, R, kw = BF16_CASES["c2_kernel_r32_4way_split"]()
+    g, o, init = _pair(p, R, gather_bf16=True, **kw)
+    ob = O.Oracle(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
+                  init=init, gather_bf16=True, c=kw["c"])
+    g.sweep(1)
+    o.sweep(1)
+    ob.sweep(1)
+    for m in range(len(p.dims)):
+        ref = o.factors(m)
+        e_gpu = np.linalg.norm(g.factors(m) - ref) / np.linalg.norm(ref)
+        e_ora = np.linalg.norm(ob.factors(m) - ref) / np.linalg.norm(ref)
+        _say(f"  mode {m}: BF16 GPU vs FP64 oracle {e_gpu:.3e}; oracle's own BF16 form vs FP64 {e_ora:.3e}")
+        assert e_ora > 1e-5                     # the rounding is visible at this size
+        assert abs(e_gpu - e_ora) <= 0.02 * e_ora + 1e-6, (m, e_gpu, e_ora)
+    g.sweep(19)
+    o.sweep(19)
+    lg, lo = g.loss(), o.loss()
+    _say(f"  after 20 sweeps: BF16 GPU test RMSE {lg[2]:.6f}, FP64 oracle {lo[2]:.6f}")
     assert abs(lg[2] - lo[2]) <= 1e-3
 
 

@@ -219,3 +219,90 @@ def test_prepared_problems_match_direct_creation():
             g.close()
     for q in preps:
         q.close()
+
+
+def _oracle_mix(seed0=1100):
+    """Batching-mixture instances for the oracle comparison: R = 8 to 32,
+    3- and 4-way, FP32 and BF16 gathers, MAX_INNER = 2, Zipf heads split over
+    many items (among them the 4-way R = 32 BF16 kernel), and one instance at
+    the mixture's upper end (2M entries)."""
+    shapes = [((60, 50, 40), 12000, 8, {}, None),
+              ((200, 90, 70), 40000, 16, {}, None),
+              ((120, 100, 30), 30000, 32, {}, None),
+              ((90, 70, 50), 25000, 12, {"max_inner": 2}, None),
+              ((400, 300, 40), 150000, 16, {"gather_bf16": True}, 1.1),
+              ((300, 200, 60, 20), 300000, 32, {"gather_bf16": True, "schedule": {"item_samples": 128}}, 1.05),
+              ((150, 80, 60), 35000, 8, {"gather_bf16": True}, None),
+              ((2000, 1500, 1200), 2_000_000, 16, {}, None)]
+    out = []
+    for i, (dims, nnz, R, kw, z) in enumerate(shapes):
+        p = synth.make_problem(dims, nnz, min(R, 8), zipf_s=z, noise_var=0.01, value_model="exact",
+                               test_frac=0.05, seed=seed0 + i, name="mix")
+        init = synth.uniform_init(p.dims, R, seed0 + i, synth.init_scale(p.values, R, len(dims)))
+        out.append((p, R, dict(seed=seed0 + i, c=0.1, **kw), init))
+    return out
+
+
+@pytest.mark.timeout(600)
+def test_pool_slots_match_the_oracle():
+    """Every slot of a pool against the FP64 oracle run on the same instance
+    from the same initial factors: after one pool sweep the factors agree to
+    the one-sweep bar (FP32 slots with the plain oracle; BF16 slots with the
+    oracle's BF16-gather form), and at the sweep where the device stop rule
+    stopped the slot its held-out RMSE is within 1e-3 of the oracle's after
+    the same number of sweeps."""
+    import oracle as O
+    O.build(force=False)
+    O.set_threads(8)
+    mix = _oracle_mix()
+    with ntc.Pool(arena_bytes=4 << 30, max_slots=16, window=5, tol=1e-4, max_sweeps=150) as pool:
+        slots = []
+        for p, R, kw, init in mix:
+            s = pool.admit(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
+                           init=init, **kw)
+            assert s is not None
+            slots.append(s)
+        _say(f"  admitted {len(slots)} problems, {pool.info()}")
+        pool.step(1)
+        oras = []
+        for (p, R, kw, init), s in zip(mix, slots):
+            bf = bool(kw.get("gather_bf16"))
+            okw = {k: v for k, v in kw.items() if k not in ("gather_bf16", "schedule")}
+            o = O.Oracle(p.dims, p.coords, p.values, R, test_coords=p.test_coords, test_values=p.test_values,
+                         init=init, gather_bf16=bf, **okw)
+            o.sweep(1)
+            for m in range(len(p.dims)):
+                got = pool.factors(s, m).astype(np.float64)
+                ref = o.factors(m)
+                err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+                scale = np.sqrt(np.mean(ref ** 2))
+                worst = np.max(np.abs(got - ref) / (np.abs(ref) + scale))
+                _say(f"  slot {s} dims {p.dims} R={R} {'BF16' if bf else 'FP32'} mode {m}: rel Frobenius "
+                     f"{err:.2e}, worst element {worst:.2e}")
+                assert np.all(got >= 0.0)
+                # BF16 slots: the rounding decisions of the gathers follow the FP32 (GPU) and FP64 (oracle)
+                # values of the factors; on these seeds none of them differs, so the one-sweep bar holds
+                # element by element as for FP32
+                assert err <= 1e-5, (s, m, err)
+                assert worst <= 1e-5, (s, m, worst)
+            if bf:   # the held-out target is the plain FP64 method's
+                o.close()
+                o = O.Oracle(p.dims, p.coords, p.values, R, test_coords=p.test_coords,
+                             test_values=p.test_values, init=init, **okw)
+                o.sweep(1)
+            oras.append(o)
+        for _ in range(60):
+            if pool.info()["running"] == 0:
+                break
+            pool.step(4)
+        assert pool.info()["running"] == 0
+        for (p, R, kw, init), s, o in zip(mix, slots, oras):
+            st, stop_at, rm = pool.query(s)
+            assert st == ntc.SLOT_STOPPED
+            o.sweep(stop_at - 1)
+            lo = o.loss()
+            lg = pool.loss(s)
+            _say(f"  slot {s} R={R} {kw.get('gather_bf16', False) and 'BF16' or 'FP32'}: stopped at sweep "
+                 f"{stop_at}, test RMSE {lg[2]:.6f}, oracle after {stop_at} sweeps {lo[2]:.6f}")
+            assert abs(lg[2] - lo[2]) <= 1e-3, (s, lg[2], lo[2])
+            o.close()

@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch: library default schedule instead of one tuned per kernel family")
     ap.add_argument("--rates", default="0.25,0.5,1,2", help="serve: arrival rates as fractions of saturation")
+    ap.add_argument("--admit-device-csr", type=int, default=0,
+                    help="serve: requests with at least this many entries are admitted with the CSR built on the "
+                         "GPU (ntc_pool_admit_device_csr) instead of prepared on a host thread (0 = never)")
     ap.add_argument("--prepare-threads", type=int, default=2,
                     help="serve: host threads building arriving requests' CSR while the pool sweeps")
     ap.add_argument("--sweeps-per-step", type=int, default=4,
@@ -705,6 +708,8 @@ def _oracle_plateau(items, cpu_threads=0, W=5, tol=1e-4, cap=500):
             hist.append(o.loss()[2])
         o.close()
         out.append((float(hist[-1]), len(hist) - 1))
+        log(f"oracle {len(out)}/{len(items)}: {p.nnz} entries, R={R}: plateau at sweep {len(hist) - 1}, "
+            f"test RMSE {hist[-1]:.6f}")
     return out, threads
 
 
@@ -717,6 +722,9 @@ def _rmse_check(idx, targets, got, plain=None, tol=1e-3):
            "within_tol": int(np.sum(np.abs(d) <= tol)), "at_or_below_target": int(np.sum(d <= tol)),
            "max_abs_diff": float(f"{np.max(np.abs(d)):.3e}"),
            "oracle_stop_sweeps": {"min": int(min(t[1] for t in targets)), "max": int(max(t[1] for t in targets))}}
+    out["outside_tol"] = [{"index": int(i), "rmse": round(float(g), 6), "oracle": round(float(t[0]), 6),
+                           "oracle_stop_sweep": int(t[1])}
+                          for i, g, t, x in zip(idx, got, targets, d) if abs(x) > tol]
     if plain is not None:
         dp = np.asarray(plain) - np.asarray([t[0] for t in targets])
         out["plain_within_tol"] = int(np.sum(np.abs(dp) <= tol))
@@ -754,6 +762,7 @@ def run_serve(args):
             dims, _, R, sd = shapes[i]
             reqs.append((small[i], R, sd))
     kw = dict(c=0.1, lam=1e-3, gather_bf16=True)
+    dev_min = args.admit_device_csr
     rates = [float(x) for x in args.rates.split(",") if x]
     unit_gaps = rng.exponential(1.0, (len(rates), n))   # arrival gaps at rate 1, scaled per rate
 
@@ -776,23 +785,33 @@ def run_serve(args):
             now = time.perf_counter() - start
             while nxt < n and arrive[nxt] <= now:
                 p, R, sd = reqs[nxt]
-                queue.append((nxt, ex.submit(ntc.Prepared, p.dims, p.coords, p.values, R, seed=sd,
-                                             test_coords=p.test_coords, test_values=p.test_values, **kw)))
+                if dev_min and p.nnz >= dev_min:   # CSR built on the GPU at admission
+                    queue.append((nxt, None))
+                else:
+                    queue.append((nxt, ex.submit(ntc.Prepared, p.dims, p.coords, p.values, R, seed=sd,
+                                                 test_coords=p.test_coords, test_values=p.test_values, **kw)))
                 nxt += 1
-            while queue and queue[0][1].done():
+            while queue and (queue[0][1] is None or queue[0][1].done()):
                 i, fut = queue[0]
-                q = fut.result()
-                s = pool.admit_prepared(q)
-                if s is None:
-                    break
-                q.close()
+                if fut is None:
+                    p, R, sd = reqs[i]
+                    s = pool.admit(p.dims, p.coords, p.values, R, seed=sd, test_coords=p.test_coords,
+                                   test_values=p.test_values, device_csr=True, **kw)
+                    if s is None:
+                        break
+                else:
+                    q = fut.result()
+                    s = pool.admit_prepared(q)
+                    if s is None:
+                        break
+                    q.close()
                 queue.popleft()
                 slot_req[s] = i
             if pool.info()["running"] > 0:
                 pool.step(args.sweeps_per_step)
             else:
                 # nothing to sweep: wait for the next arrival or the head of the queue
-                if queue:
+                if queue and queue[0][1] is not None:
                     cf.wait([queue[0][1]], timeout=0.05)
                 elif nxt < n:
                     time.sleep(max(0.0, min(arrive[nxt] - (time.perf_counter() - start), 0.05)))
@@ -875,7 +894,9 @@ def run_serve(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16-gather/f32", "data": "synthetic",
            "config": {"workload": f"{n} requests: 95% batching mixture, 5% 200000x50000x500 20M Zipf(1.1) R=16; "
                                   "BF16 gathers, plateau stop; Poisson arrivals; host CSR on "
-                                  f"{args.prepare_threads} worker threads", "requests": n, "seed": args.seed},
+                                  f"{args.prepare_threads} worker threads"
+                                  + (f", CSR on the GPU for requests of >= {dev_min} entries" if dev_min else ""),
+                       "requests": n, "seed": args.seed, "admit_device_csr_min_nnz": dev_min},
            "latency": rows,
            "plain": None if service is None else {
                "kind": "FP32 gathers, one request at a time through ntc_create/ntc_sweep/ntc_loss (create "

@@ -187,6 +187,16 @@ ntc_status ntc_get_work(ntc_handle h, int64_t *updates_per_sweep, int64_t *row_s
 ntc_status ntc_debug_sample(ntc_handle h, int64_t k, int32_t mode, int32_t l, int64_t row,
                             int32_t *pos_out, int32_t *count);
 
+/* The CSR of mode `mode` (the unfolding X_(i), M_(i) of Section II) exactly
+ * as the handle holds it on the device, whichever build made it:
+ * rowptr_out [dims[mode]+1] int64 (entries of row p are positions
+ * [rowptr[p], rowptr[p+1]) in the stable order by coordinate `mode`, ties in
+ * COO order); records_out [nnz][W] uint32 with W = 4 for nmodes <= 4 and 8
+ * otherwise: the other modes' coordinates times R in increasing mode order,
+ * the FP32 value bits, then zeros, except that for mode 0 with nmodes < W
+ * word nmodes holds the entry's own coordinate times R.  Synchronising. */
+ntc_status ntc_debug_csr(ntc_handle h, int32_t mode, int64_t *rowptr_out, uint32_t *records_out);
+
 /* The same positions computed by the library's HOST copy of the sampler for
  * a row of length n (no device, no handle).  pos_out holds >= floor(c n)
  * int32; returns the count through *count. */
@@ -300,6 +310,17 @@ ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *d
 /* Admit a problem built by ntc_prepare (on any thread): only the device
  * work happens here.  Same results and errors as ntc_pool_admit. */
 ntc_status ntc_pool_admit_prepared(ntc_pool_handle pool, ntc_prepared_handle prepared, int32_t *slot);
+
+/* Admit a problem whose CSR is built on the device, as ntc_create_device_csr
+ * builds it (bit-identical to ntc_pool_admit's problem): the COO upload, the
+ * checks, the per-mode sort and the records run on the pool's stream, and
+ * the temporaries come from the arena and return to it before the call
+ * does.  NTC_ENOMEM, with nothing changed, when no slot is free or the arena
+ * cannot hold the problem plus its temporaries now; other errors as
+ * ntc_create_device_csr.  Synchronising. */
+ntc_status ntc_pool_admit_device_csr(ntc_pool_handle pool, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                                     const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
+                                     int32_t *slot);
 
 /* Enqueue `nsweeps` pool sweeps over the running problems back to back and
  * wait for them.  The stop rule is applied on the device after every sweep;

@@ -105,6 +105,7 @@ _SIGNATURES = [
     ("ntc_get_work", ctypes.c_int, [ctypes.c_void_p, _i64p, _i64p]),
     ("ntc_debug_sample", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int64, _i32p, _i32p]),
+    ("ntc_debug_csr", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, ctypes.POINTER(ctypes.c_uint32)]),
     ("ntc_host_sample", ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _i32p, _i64p]),
     ("ntc_host_csr", ctypes.c_int, [ctypes.c_int32, _i64p, ctypes.c_int64, _i32p, ctypes.c_int32, _i64p, _i64p]),
@@ -128,6 +129,8 @@ _SIGNATURES = [
     ("ntc_pool_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_PoolParams)]),
     ("ntc_pool_admit", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, ctypes.c_int64, _i32p, _f32p,
                                       ctypes.c_int32, ctypes.POINTER(_Params), _i32p]),
+    ("ntc_pool_admit_device_csr", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, ctypes.c_int64, _i32p,
+                                                 _f32p, ctypes.c_int32, ctypes.POINTER(_Params), _i32p]),
     ("ntc_pool_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ntc_pool_query", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i32p, _i64p, _f64p]),
     ("ntc_pool_loss", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p]),
@@ -445,6 +448,14 @@ class Problem:
         _check(lib().ntc_debug_sample(self._h, k, mode, l, row, _p(out, _i32p), ctypes.byref(cnt)))
         return out[: cnt.value].copy()
 
+    def debug_csr(self, mode: int, nnz: int):
+        """(rowptr [I+1] int64, records [nnz][W] uint32) of one mode as held on the device."""
+        W = 4 if self.N <= 4 else 8
+        rp = np.zeros(self.dims[mode] + 1, dtype=np.int64)
+        rec = np.zeros((max(1, nnz), W), dtype=np.uint32)
+        _check(lib().ntc_debug_csr(self._h, mode, _p(rp, _i64p), rec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+        return rp, rec[:nnz]
+
 
 SLOT_FREE, SLOT_RUNNING, SLOT_STOPPED = 0, 1, 2
 
@@ -527,8 +538,9 @@ class Pool:
     def admit(self, dims: Sequence[int], coords: np.ndarray, values: np.ndarray, rank: int, *, c: float = 0.1,
               lam: float = 1e-3, max_inner: int = 1, power_iters: int = 20, seed: int = 0,
               gather_bf16: bool = False, test_coords=None, test_values=None, init=None,
-              schedule: Optional[dict] = None, lp_bound: int = 0) -> Optional[int]:
-        """Slot index, or None when the pool cannot hold the problem now."""
+              schedule: Optional[dict] = None, lp_bound: int = 0, device_csr: bool = False) -> Optional[int]:
+        """Slot index, or None when the pool cannot hold the problem now.
+        device_csr: build the CSR on the device (ntc_pool_admit_device_csr)."""
         d = np.asarray([int(x) for x in dims], dtype=np.int64)
         co = np.ascontiguousarray(coords, dtype=np.int32)
         va = np.ascontiguousarray(values, dtype=np.float32)
@@ -537,8 +549,9 @@ class Pool:
         prm, keep = _make_params(d.size, c, lam, max_inner, power_iters, seed, gather_bf16, test_coords,
                                  test_values, init, schedule, lp_bound)
         slot = ctypes.c_int32(-1)
-        st = lib().ntc_pool_admit(self._h, d.size, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p),
-                                  int(rank), ctypes.byref(prm), ctypes.byref(slot))
+        fn = lib().ntc_pool_admit_device_csr if device_csr else lib().ntc_pool_admit
+        st = fn(self._h, d.size, _p(d, _i64p), co.shape[0], _p(co, _i32p), _p(va, _f32p), int(rank),
+                ctypes.byref(prm), ctypes.byref(slot))
         if st == -2:      # NTC_ENOMEM: not admitted now
             return None
         _check(st)

@@ -911,6 +911,22 @@ ntc_status ntc::problem_view(ntc_handle h, ntc::ProblemView *v)
     return NTC_OK;
 }
 
+ntc_status ntc::device_csr_temp_bytes(int32_t nmodes, const int64_t *dims, int64_t nnz, size_t *bytes)
+{
+    if (!bytes || !dims || nmodes < 2 || nmodes > ntc::kMaxModes || nnz < 0)
+        return fail(NTC_EINVAL, "invalid argument");
+    auto r = [](size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; };
+    const size_t n = static_cast<size_t>(std::max<int64_t>(nnz, 1));
+    int64_t maxI = 0;
+    for (int m = 0; m < nmodes; ++m)
+        maxI = std::max(maxI, dims[m]);
+    size_t sort = 0;
+    NTC_HIP(ntc::csr_sort_bytes(nnz, &sort));
+    *bytes = r(n * nmodes * 4) + r(n * 4) + 4 * r(n * 4) + r(sizeof(unsigned long long)) +
+             r(static_cast<size_t>(maxI + 1) * 8) + r(sort);
+    return NTC_OK;
+}
+
 void ntc::note_sweeps(ntc_handle h, int64_t n)
 {
     h->k += n;
@@ -922,28 +938,47 @@ void ntc::note_sweeps(ntc_handle h, int64_t n)
 // by coordinate gives the same entry order as the host's counting sort.  The
 // records (and mode 0's row array when the record has no spare word) are
 // allocated through h and handed to commit; the row pointers come back for
-// the host-side schedule.  Temporaries use hipMalloc and are freed here.
+// the host-side schedule.  Temporaries come from h's allocator when it has
+// one (a pool's arena), else from hipMalloc, and are freed here once h's
+// stream has finished with them.
 struct DeviceTemps {
+    ntc_problem *h;
     std::vector<void *> p;
+    explicit DeviceTemps(ntc_problem *owner) : h(owner) {}
     ~DeviceTemps()
     {
-        for (void *x : p)
-            (void)hipFree(x);
+        if (!p.empty())
+            (void)hipStreamSynchronize(h->stream);
+        for (void *x : p) {
+            if (h->alloc && h->dfree)
+                h->dfree(x, h->actx);
+            else
+                (void)hipFree(x);
+        }
     }
     hipError_t get(void **dst, size_t bytes)
     {
         *dst = nullptr;
-        const hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 256));
-        if (e == hipSuccess)
-            p.push_back(*dst);
-        return e;
+        bytes = std::max<size_t>(bytes, 256);
+        if (h->alloc) {
+            *dst = h->alloc(bytes, h->stream, h->actx);
+            if (!*dst)
+                return hipErrorOutOfMemory;
+        } else {
+            const hipError_t e = hipMalloc(dst, bytes);
+            if (e != hipSuccess)
+                return e;
+        }
+        p.push_back(*dst);
+        return hipSuccess;
     }
 };
 
 ntc_status device_csr(ntc_problem *h, ntc_prepared &q, std::vector<int64_t> (&rowptr)[ntc::kMaxModes], int32_t N,
                       const int64_t *dims, int64_t nnz, const int32_t *coords, const float *values, int32_t R)
 {
-    DeviceTemps t;
+    DeviceTemps t(h);
+    const hipStream_t st = h->stream;
     int32_t *d_coords = nullptr;
     float *d_values = nullptr;
     uint32_t *keys_in = nullptr, *keys_out = nullptr, *ids_in = nullptr, *ids_out = nullptr;
@@ -966,18 +1001,19 @@ ntc_status device_csr(ntc_problem *h, ntc_prepared &q, std::vector<int64_t> (&ro
     NTC_HIP(ntc::csr_sort_bytes(nnz, &temp_bytes));
     NTC_HIP(t.get(&temp, temp_bytes));
     if (nnz > 0) {
-        NTC_HIP(hipMemcpy(d_coords, coords, static_cast<size_t>(nnz) * N * 4, hipMemcpyHostToDevice));
-        NTC_HIP(hipMemcpy(d_values, values, static_cast<size_t>(nnz) * 4, hipMemcpyHostToDevice));
+        NTC_HIP(hipMemcpyAsync(d_coords, coords, static_cast<size_t>(nnz) * N * 4, hipMemcpyHostToDevice, st));
+        NTC_HIP(hipMemcpyAsync(d_values, values, static_cast<size_t>(nnz) * 4, hipMemcpyHostToDevice, st));
     }
     // the first bad entry, reported with the host's message for it
     const unsigned long long none = ~0ull;
-    NTC_HIP(hipMemcpy(bad, &none, sizeof(none), hipMemcpyHostToDevice));
+    NTC_HIP(hipMemcpyAsync(bad, &none, sizeof(none), hipMemcpyHostToDevice, st));
     ntc::CsrDims cd{};
     for (int m = 0; m < N; ++m)
         cd.d[m] = dims[m];
-    NTC_HIP(ntc::csr_validate(d_coords, d_values, nnz, N, cd, bad, nullptr));
+    NTC_HIP(ntc::csr_validate(d_coords, d_values, nnz, N, cd, bad, st));
     unsigned long long first = none;
-    NTC_HIP(hipMemcpy(&first, bad, sizeof(first), hipMemcpyDeviceToHost));
+    NTC_HIP(hipMemcpyAsync(&first, bad, sizeof(first), hipMemcpyDeviceToHost, st));
+    NTC_HIP(hipStreamSynchronize(st));
     if (first != none)
         return check_entry(coords, values, N, dims, static_cast<int64_t>(first));
     const int rw = record_words(N);
@@ -1004,9 +1040,10 @@ ntc_status device_csr(ntc_problem *h, ntc_prepared &q, std::vector<int64_t> (&ro
             NTC_TRY(alloc_or_fail(h, reinterpret_cast<void **>(&c.row0), static_cast<size_t>(nnz) * 4, "loss rows"));
             q.dev_row0 = c.row0;
         }
-        NTC_HIP(ntc::csr_mode(c, nullptr));
+        NTC_HIP(ntc::csr_mode(c, st));
         rowptr[m].resize(static_cast<size_t>(dims[m]) + 1);
-        NTC_HIP(hipMemcpy(rowptr[m].data(), d_rowptr, (dims[m] + 1) * 8, hipMemcpyDeviceToHost));
+        NTC_HIP(hipMemcpyAsync(rowptr[m].data(), d_rowptr, (dims[m] + 1) * 8, hipMemcpyDeviceToHost, st));
+        NTC_HIP(hipStreamSynchronize(st));
         q.md[m].dev_rec = c.records;
     }
     return NTC_OK;
@@ -1325,6 +1362,20 @@ ntc_status ntc_debug_sample(ntc_handle h, int64_t k, int32_t mode, int32_t l, in
     }
     *count = cnt;
     return NTC_OK;
+}
+
+ntc_status ntc_debug_csr(ntc_handle h, int32_t mode, int64_t *rowptr_out, uint32_t *records_out)
+{
+    NTC_TRY(check_mode(h, mode));
+    if (!rowptr_out || (h->nnz > 0 && !records_out))
+        return fail(NTC_EINVAL, "null argument");
+    NTC_HIP(hipMemcpyAsync(rowptr_out, h->md[mode].rowptr, (h->dims[mode] + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToHost, h->stream));
+    if (h->nnz > 0)
+        NTC_HIP(hipMemcpyAsync(records_out, h->md[mode].records,
+                               static_cast<size_t>(h->nnz) * h->rw * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               h->stream));
+    return sync(h);
 }
 
 ntc_status ntc_host_sample(uint64_t seed, int64_t k, int32_t mode, int32_t l, int64_t row, int64_t n, double c,

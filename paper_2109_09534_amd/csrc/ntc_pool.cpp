@@ -522,6 +522,9 @@ int32_t free_slot_of(const ntc_pool *pool)
 
 // Device half of an admission: the prepared problem goes into the arena and
 // a free slot, with the stop-rule state of sweep 0.
+ntc_status register_slot(ntc_pool *pool, ntc_handle h, int32_t free_slot, int32_t *slot);
+void pool_params(ntc_pool *pool, ntc_params *q);
+
 ntc_status admit_prepared(ntc_pool *pool, ntc_prepared_handle prep, int32_t *slot)
 {
     *slot = -1;
@@ -535,13 +538,27 @@ ntc_status admit_prepared(ntc_pool *pool, ntc_prepared_handle prep, int32_t *slo
                                     std::to_string(pool->arena.largest_free()) + " in the largest free block)");
     ntc_params q;
     ntc_params_default(&q);
-    q.stream = pool->stream;
-    q.dev_alloc = arena_alloc;
-    q.dev_free = arena_free;
-    q.alloc_ctx = &pool->arena;
-    q.overlap = 0;
+    pool_params(pool, &q);
     ntc_handle h = nullptr;
     POOL_TRY(ntc_create_prepared(&h, prep, &q));
+    return register_slot(pool, h, free_slot, slot);
+}
+
+// The pool's settings for a problem's device memory and stream.
+void pool_params(ntc_pool *pool, ntc_params *q)
+{
+    q->stream = pool->stream;
+    q->dev_alloc = arena_alloc;
+    q->dev_free = arena_free;
+    q->alloc_ctx = &pool->arena;
+    q->overlap = 0;
+}
+
+// Put a created problem into free slot `free_slot`: its held-out RMSE at
+// admission opens the stop rule's history.  On failure the problem is
+// released and the slot stays free.
+ntc_status register_slot(ntc_pool *pool, ntc_handle h, int32_t free_slot, int32_t *slot)
+{
     Slot &s = pool->slots[free_slot];
     s = Slot{};
     s.h = h;
@@ -609,6 +626,34 @@ ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *d
     const ntc_status st = admit_prepared(pool, prep, slot);
     (void)ntc_prepared_release(prep);
     return st;
+}
+
+ntc_status ntc_pool_admit_device_csr(ntc_pool_handle pool, int32_t nmodes, const int64_t *dims, int64_t nnz,
+                                     const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
+                                     int32_t *slot)
+{
+    if (!pool || !slot)
+        return fail(NTC_EINVAL, "null argument");
+    *slot = -1;
+    const int32_t free_slot = free_slot_of(pool);
+    if (free_slot < 0)
+        return fail(NTC_ENOMEM, "no free slot");
+    ntc_params q;
+    if (p)
+        q = *p;
+    else
+        ntc_params_default(&q);
+    size_t bound = 0, temps = 0;
+    POOL_TRY(ntc_estimate_bytes(nmodes, dims, nnz, rank, &q, &bound));
+    POOL_TRY(ntc::device_csr_temp_bytes(nmodes, dims, nnz, &temps));
+    if (bound + temps > pool->arena.largest_free())
+        return fail(NTC_ENOMEM, "arena cannot hold the problem and its CSR temporaries now (up to " +
+                                    std::to_string(bound + temps) + " bytes needed, " +
+                                    std::to_string(pool->arena.largest_free()) + " in the largest free block)");
+    pool_params(pool, &q);
+    ntc_handle h = nullptr;
+    POOL_TRY(ntc_create_device_csr(&h, nmodes, dims, nnz, coords, values, rank, &q));
+    return register_slot(pool, h, free_slot, slot);
 }
 
 ntc_status ntc_pool_admit_prepared(ntc_pool_handle pool, ntc_prepared_handle prepared, int32_t *slot)

@@ -37,4 +37,9 @@ ntc_status problem_view(ntc_handle h, ProblemView *v);
 // The pool advanced the device sweep counter by n: keep the host copy in step.
 void note_sweeps(ntc_handle h, int64_t n);
 
+// Upper bound of the temporary device bytes ntc_create_device_csr takes (and
+// frees before it returns) for a problem of these sizes, allocations
+// rounded up to 256 bytes.
+ntc_status device_csr_temp_bytes(int32_t nmodes, const int64_t *dims, int64_t nnz, size_t *bytes);
+
 }  // namespace ntc

@@ -306,3 +306,28 @@ def test_pool_slots_match_the_oracle():
                  f"{stop_at}, test RMSE {lg[2]:.6f}, oracle after {stop_at} sweeps {lo[2]:.6f}")
             assert abs(lg[2] - lo[2]) <= 1e-3, (s, lg[2], lo[2])
             o.close()
+
+
+def test_device_csr_admission_matches_host_admission():
+    """ntc_pool_admit_device_csr builds each problem's CSR on the GPU (its
+    temporaries from the arena, returned before the call does): the slot is
+    bit-identical to the host-built admission after several sweeps, and the
+    arena holds exactly what the host-built problem holds."""
+    mix = _mix(1300)[:5]
+    res = []
+    for dev in (False, True):
+        with ntc.Pool(arena_bytes=2 << 30, max_slots=8, window=0, max_sweeps=1000) as pool:
+            slots = [pool.admit(p.dims, p.coords, p.values, R, test_coords=p.test_coords,
+                                test_values=p.test_values, device_csr=dev, **kw) for p, R, kw in mix]
+            assert all(s is not None for s in slots)
+            used = pool.info()["used"]
+            pool.step(3)
+            res.append((used, [[pool.factors(s, m) for m in range(len(p.dims))] for (p, _, _), s in zip(mix, slots)],
+                        [pool.query(s)[2] for s in slots]))
+    (uh, fh, rh), (ud, fd, rd) = res
+    _say(f"  arena bytes in use after admission: host CSR {uh}, device CSR {ud}")
+    assert uh == ud
+    for a, b in zip(fh, fd):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    assert rh == rd

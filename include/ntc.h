@@ -157,6 +157,32 @@ ntc_status ntc_update_mode(ntc_handle h, int32_t mode);
  * Returns NTC_ENONFINITE if any of them is not finite. */
 ntc_status ntc_loss(ntc_handle h, double out[4]);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The loss of
+ * ntc_loss (eq. Problem_TC, FP64, deterministic two-stage reduction) on
+ * caller-held DEVICE arrays, with no handle:
+ *   nmodes in [2, 8]; dims [nmodes] host; rank in [1, 64];
+ *   train_coords [n_train][nmodes] int32 and train_values [n_train] FP32,
+ *   test_coords [n_test][nmodes] and test_values [n_test]: device, 0-based
+ *   coordinates that MUST lie in [0, dims[m]) (they are not checked: the
+ *   call does not read device memory back);
+ *   factors: host array of nmodes device pointers, FP32 [dims[m]][rank];
+ *   out: DEVICE memory for 4 doubles, written on `stream` with
+ *   {objective on the train set, train RMSE, test RMSE, test relative error}
+ *   as ntc_loss defines them (non-finite values are written as they are).
+ * Enqueued on `stream` (hipStream_t, NULL = the null stream); nothing is
+ * allocated, set or copied by the host and nothing is synchronised.  Partial
+ * sums live in a fixed device array of 1024 x 4 doubles (32 KiB per GPU,
+ * held until the process ends); the call uses at most that, so calls that
+ * overlap on one GPU (other streams, other threads) race on it and must be
+ * ordered by the caller.  Errors: NTC_EINVAL (arguments), NTC_EUNSUPPORTED
+ * (n_train or n_test >= 2^31, or dims[m] * rank >= 2^32), NTC_EDEVICE
+ * (launch failure). */
+ntc_status ntc_loss_coo_noalloc(int32_t nmodes, const int64_t *dims, int32_t rank, int64_t n_train,
+                                const int32_t *train_coords, const float *train_values, int64_t n_test,
+                                const int32_t *test_coords, const float *test_values, const float *const *factors,
+                                double lambda, double *out, void *stream);
+
 /* Synchronise and copy mode `mode`'s FP32 factor [I_m][R] to host_out. */
 ntc_status ntc_get_factors(ntc_handle h, int32_t mode, float *host_out);
 

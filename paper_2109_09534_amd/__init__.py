@@ -97,6 +97,10 @@ _SIGNATURES = [
     ("ntc_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ntc_update_mode", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ntc_loss", ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    ("ntc_loss_coo_noalloc", ctypes.c_int, [ctypes.c_int32, _i64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_double, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     ("ntc_get_factors", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f32p]),
     ("ntc_set_factors", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f32p]),
     ("ntc_get_factors_device", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -191,6 +195,20 @@ def _check(status: int):
 
 def _p(a: np.ndarray, t):
     return a.ctypes.data_as(t)
+
+
+def loss_coo_noalloc(dims: Sequence[int], rank: int, n_train: int, train_coords: int, train_values: int,
+                     n_test: int, test_coords: int, test_values: int, factors: Sequence[int], lam: float, out: int,
+                     stream: int = 0):
+    """ntc_loss_coo_noalloc: every array argument is a DEVICE address (an
+    int, e.g. a torch tensor's data_ptr()); out receives 4 doubles on
+    `stream`.  Nothing is allocated, copied or synchronised."""
+    d = np.ascontiguousarray(dims, dtype=np.int64)
+    fp = (ctypes.c_void_p * len(factors))(*[ctypes.c_void_p(int(f)) for f in factors])
+    _check(lib().ntc_loss_coo_noalloc(len(dims), _p(d, _i64p), rank, n_train, ctypes.c_void_p(train_coords),
+                                      ctypes.c_void_p(train_values), n_test, ctypes.c_void_p(test_coords),
+                                      ctypes.c_void_p(test_values), fp, lam, ctypes.c_void_p(out),
+                                      ctypes.c_void_p(stream)))
 
 
 def host_sample(seed: int, k: int, mode: int, l: int, row: int, n: int, c: float) -> np.ndarray:

@@ -46,6 +46,18 @@ __host__ __device__ inline int entry_lanes(int R)
 }
 
 hipError_t launch_loss(const LossArgs &a, hipStream_t s);
+
+// The loss of launch_loss over two COO sets held by the caller (train and
+// held-out: test_coords/test_values/n_test of each LossArgs), with the
+// partial sums in a fixed device array of kNoallocBlocks * 4 doubles (one
+// per GPU, never freed) instead of an allocation: no hipMalloc, no memset,
+// no copy and no synchronisation, so a caller may capture it in a graph.
+// out (device, 4 doubles) receives {objective, train RMSE, test RMSE, test
+// relative error}.  Calls that overlap on one GPU race on the array.
+constexpr int kNoallocBlocks = 1024;
+constexpr int64_t kNoallocScratchDoubles = 4 * static_cast<int64_t>(kNoallocBlocks);
+hipError_t launch_loss_coo_noalloc(const LossArgs &train, const LossArgs &test, double lambda, double *out,
+                                   hipStream_t s);
 hipError_t launch_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale,
                               hipStream_t s);
 hipError_t launch_to_bf16(const float *U, uint16_t *U16, int64_t count, hipStream_t s);

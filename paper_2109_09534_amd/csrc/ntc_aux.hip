@@ -3,6 +3,8 @@
 // refresh and the device sampler probe.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ntc_aux.h"
 #include "ntc_bf16.h"
 #include "ntc_dev.h"
@@ -210,6 +212,67 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_final(const LossArgs a)
     }
 }
 
+// ---------------------------------------------------- allocation-free loss
+// Sums over two caller-held COO sets (train, held-out) and the regulariser,
+// one partial per block: part[q * gridDim.x + block] for q = train SSE,
+// held-out SSE, held-out sum x^2, sum U^2.
+template <int NM>
+__global__ __launch_bounds__(kLossThreads) void k_coo_partials(const LossArgs tr, const LossArgs te, double *part)
+{
+    __shared__ double s[kLossThreads];
+    const int R = tr.R;
+    const int nm = NM > 0 ? NM : tr.nmodes;
+    const int G = entry_lanes(R);
+    const int q = threadIdx.x & (G - 1);
+    const int64_t ngroups = static_cast<int64_t>(gridDim.x) * (blockDim.x / G);
+    const int64_t grp = static_cast<int64_t>(blockIdx.x) * (blockDim.x / G) + threadIdx.x / G;
+    double sse = 0.0, sx_train = 0.0, tse = 0.0, tsx = 0.0;
+    test_sums<4, NM>(tr, grp, ngroups, nm, R, G, q, sse, sx_train);
+    test_sums<4, NM>(te, grp, ngroups, nm, R, G, q, tse, tsx);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    double reg = 0.0;
+    for (int m = 0; m < nm; ++m) {
+        const int64_t cntm = tr.dims[m] * R;
+        for (int64_t t = tid; t < cntm; t += stride) {
+            const double u = static_cast<double>(tr.U[m][t]);
+            reg += u * u;
+        }
+    }
+    sse = block_sum(sse, s);
+    tse = block_sum(tse, s);
+    tsx = block_sum(tsx, s);
+    reg = block_sum(reg, s);
+    if (threadIdx.x == 0) {
+        const int nb = gridDim.x;
+        part[0 * nb + blockIdx.x] = sse;
+        part[1 * nb + blockIdx.x] = tse;
+        part[2 * nb + blockIdx.x] = tsx;
+        part[3 * nb + blockIdx.x] = reg;
+    }
+}
+
+// The nb block partials summed in block order, then the four results of
+// ntc_loss, written to the caller's device memory.
+__global__ __launch_bounds__(kLossThreads) void k_coo_final(const double *part, int nb, int64_t n_train,
+                                                            int64_t n_test, double lambda, double *out)
+{
+    __shared__ double s[kLossThreads];
+    double v[4];
+    for (int q = 0; q < 4; ++q) {
+        double x = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            x += part[q * nb + b];
+        v[q] = block_sum(x, s);
+    }
+    if (threadIdx.x == 0) {
+        out[0] = 0.5 * v[0] + 0.5 * lambda * v[3];
+        out[1] = n_train > 0 ? sqrt(v[0] / static_cast<double>(n_train)) : 0.0;
+        out[2] = n_test > 0 ? sqrt(v[1] / static_cast<double>(n_test)) : 0.0;
+        out[3] = (n_test > 0 && v[2] > 0.0) ? sqrt(v[1]) / sqrt(v[2]) : 0.0;
+    }
+}
+
 // ------------------------------------------------------------- init, bf16
 __global__ void k_init_factor(float *U, uint16_t *U16, int64_t count, int32_t mode, uint64_t seed, float scale)
 {
@@ -339,6 +402,67 @@ hipError_t launch_loss(const LossArgs &a, hipStream_t s)
     else
         hipLaunchKernelGGL(k_loss_partials<0>, dim3(kLossBlocks), dim3(kLossThreads), 0, s, a);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// The partial sums of launch_loss_coo_noalloc.  Host code never uses this
+// name as an address: each device's copy is reached through the pointer
+// hipGetSymbolAddress returns for it, taken once per device.
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The address of this device's copy of `scratch`, looked up on the first
+// call made with the device current.
+hipError_t scratch_ptr(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_loss_coo_noalloc(const LossArgs &train, const LossArgs &test, double lambda, double *out,
+                                   hipStream_t s)
+{
+    double *part = nullptr;
+    hipError_t e = scratch_ptr(&part);
+    if (e != hipSuccess)
+        return e;
+    // about eight group-steps of four entries per thread over both sets
+    const int64_t per = 8 * 4 * (kLossThreads / entry_lanes(train.R));
+    const int64_t total = train.n_test + test.n_test;
+    int64_t nb = (total + per - 1) / per;
+    nb = nb < 1 ? 1 : nb > kNoallocBlocks ? kNoallocBlocks : nb;
+    if (4 * nb > kNoallocScratchDoubles)
+        return hipErrorInvalidValue;
+    const dim3 grid(static_cast<uint32_t>(nb)), block(kLossThreads);
+    if (train.nmodes == 3)
+        hipLaunchKernelGGL(k_coo_partials<3>, grid, block, 0, s, train, test, part);
+    else if (train.nmodes == 4)
+        hipLaunchKernelGGL(k_coo_partials<4>, grid, block, 0, s, train, test, part);
+    else
+        hipLaunchKernelGGL(k_coo_partials<0>, grid, block, 0, s, train, test, part);
+    hipLaunchKernelGGL(k_coo_final, dim3(1), block, 0, s, static_cast<const double *>(part), static_cast<int>(nb),
+                       train.n_test, test.n_test, lambda, out);
     return hipGetLastError();
 }
 

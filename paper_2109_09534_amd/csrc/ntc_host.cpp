@@ -1272,6 +1272,49 @@ ntc_status ntc_loss(ntc_handle h, double out[4])
     return NTC_OK;
 }
 
+ntc_status ntc_loss_coo_noalloc(int32_t nmodes, const int64_t *dims, int32_t rank, int64_t n_train,
+                                const int32_t *train_coords, const float *train_values, int64_t n_test,
+                                const int32_t *test_coords, const float *test_values, const float *const *factors,
+                                double lambda, double *out, void *stream)
+{
+    if (nmodes < 2 || nmodes > ntc::kMaxModes)
+        return fail(NTC_EINVAL, "nmodes must be in [2, 8]");
+    if (rank < 1 || rank > ntc::kMaxRank)
+        return fail(NTC_EINVAL, "rank must be in [1, 64]");
+    if (!dims || !factors || !out)
+        return fail(NTC_EINVAL, "null argument");
+    if (n_train < 0 || n_test < 0)
+        return fail(NTC_EINVAL, "entry counts must be >= 0");
+    if (n_train >= (int64_t(1) << 31) || n_test >= (int64_t(1) << 31))
+        return fail(NTC_EUNSUPPORTED, "at most 2^31 - 1 entries per set");
+    if ((n_train > 0 && (!train_coords || !train_values)) || (n_test > 0 && (!test_coords || !test_values)))
+        return fail(NTC_EINVAL, "null entry arrays for a nonempty set");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda))
+        return fail(NTC_EINVAL, "lambda must be finite and >= 0");
+    ntc::LossArgs tr{}, te{};
+    for (int m = 0; m < nmodes; ++m) {
+        if (dims[m] < 1)
+            return fail(NTC_EINVAL, "dims must be >= 1");
+        // row offsets coordinate * R are 32-bit in the kernels
+        if (dims[m] * static_cast<int64_t>(rank) > (int64_t(1) << 32) - 1)
+            return fail(NTC_EUNSUPPORTED, "dims[m] * rank must be below 2^32");
+        if (!factors[m])
+            return fail(NTC_EINVAL, "null factor pointer");
+        tr.U[m] = te.U[m] = factors[m];
+        tr.dims[m] = te.dims[m] = dims[m];
+    }
+    tr.nmodes = te.nmodes = nmodes;
+    tr.R = te.R = rank;
+    tr.test_coords = train_coords;
+    tr.test_values = train_values;
+    tr.n_test = n_train;
+    te.test_coords = test_coords;
+    te.test_values = test_values;
+    te.n_test = n_test;
+    NTC_HIP(ntc::launch_loss_coo_noalloc(tr, te, lambda, out, static_cast<hipStream_t>(stream)));
+    return NTC_OK;
+}
+
 ntc_status ntc_get_factors(ntc_handle h, int32_t mode, float *host_out)
 {
     NTC_TRY(check_mode(h, mode));

@@ -25,12 +25,17 @@ _f32p = ctypes.POINTER(ctypes.c_float)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math).  A forced
+    build also compiles the sanitizer driver (syntax and types only; the
+    sanitized executable is built by its test)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared",
                                "-fno-fast-math", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    if force:
+        subprocess.check_call(["gcc", "-std=c99", "-fsyntax-only", "-Wall",
+                               os.path.join(_HERE, "sanitize_driver.c")])
     return _LIB
 
 

@@ -870,7 +870,12 @@ def run_serve(args):
     targets = []
     ora_note = None
     if args.oracle_instances > 0:
-        idx = sorted(set(np.linspace(0, n - 1, min(n, args.oracle_instances)).astype(int).tolist()))
+        # evenly spread requests plus the first request on each large tensor
+        idx = set(np.linspace(0, n - 1, min(n, args.oracle_instances)).astype(int).tolist())
+        for big in large:
+            first = [i for i, r in enumerate(reqs) if r[0] is big]
+            idx |= set(first[:1])
+        idx = sorted(idx)
         t0 = time.perf_counter()
         targets, threads = _oracle_plateau([reqs[i] for i in idx], args.cpu_threads)
         ora_note = (f"FP64 oracle from the same default initial factors and seeds, same plateau rule, "

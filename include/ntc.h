@@ -141,6 +141,24 @@ ntc_status ntc_create_prepared(ntc_handle *out, ntc_prepared_handle prepared, co
 ntc_status ntc_prepared_bytes(ntc_prepared_handle prepared, size_t *bytes);
 ntc_status ntc_prepared_release(ntc_prepared_handle prepared);
 
+/* The row schedule ntc_prepare built for `mode` (host data, no device), for
+ * checks of the invariants the row kernels rely on.  counts receives
+ * {tiny rows, items, items that are whole rows of the group kernel (the
+ * first ones), split rows, slot groups, partial slots, sampled entries}.
+ * Each non-NULL array receives its entries as four 32-bit words:
+ *   rowptr_out [dims[mode]+1] int64: the CSR row pointers;
+ *   tiny_out   rows with 1 <= B_p <= tiny_max: {row, n_p, base lo, base hi};
+ *   items_out  the first `group` items, when R <= 16 and nmodes <= 4:
+ *              {row, n_p, base lo, base hi} (whole rows); every other item:
+ *              {row, j0, j1, slot}, samples [j0, j1) of the row's minibatch,
+ *              slot -1 for a whole row, else the partial slot it writes;
+ *   split_out  {row, first slot, slot count, 0}: rows combined from slots;
+ *   groups_out {first source slot, count, destination slot, 0}: R > 16 rows
+ *              of many items, whose slots are first summed in groups.
+ * Samples of a row are B_p = floor(c n_p) (Section II-B). */
+ntc_status ntc_prepared_schedule(ntc_prepared_handle prepared, int32_t mode, int64_t counts[7], int64_t *rowptr_out,
+                                 int32_t *tiny_out, int32_t *items_out, int32_t *split_out, int32_t *groups_out);
+
 /* Enqueue `nsweeps` iterations of Alg. 2 (each: modes 0..N-1 in order, each
  * mode one S_NMC call of Alg. 1 with MAX_INNER inner steps), advancing k by
  * one per sweep.  Asynchronous: returns once the work is enqueued. */

@@ -128,6 +128,8 @@ _SIGNATURES = [
                                            ctypes.POINTER(_Params)]),
     ("ntc_prepared_bytes", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     ("ntc_prepared_release", ctypes.c_int, [ctypes.c_void_p]),
+    ("ntc_prepared_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, _i64p, _i32p, _i32p, _i32p,
+                                             _i32p]),
     ("ntc_pool_admit_prepared", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _i32p]),
     ("ntc_pool_params_default", None, [ctypes.POINTER(_PoolParams)]),
     ("ntc_pool_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_PoolParams)]),
@@ -500,6 +502,21 @@ class Prepared:
                                  int(rank), ctypes.byref(prm)))
         self._h = h
         self.dims, self.rank = [int(x) for x in d], int(rank)
+
+    def row_schedule(self, mode: int) -> dict:
+        """The host row schedule of one mode (ntc_prepared_schedule): rowptr and
+        the tiny/items/split/groups tables as [n, 4] int32 arrays."""
+        cnt = np.zeros(7, dtype=np.int64)
+        _check(lib().ntc_prepared_schedule(self._h, mode, _p(cnt, _i64p), None, None, None, None, None))
+        rp = np.zeros(self.dims[mode] + 1, dtype=np.int64)
+        arr = {k: np.zeros((max(1, int(n)), 4), dtype=np.int32)
+               for k, n in zip(("tiny", "items", "split", "groups"), (cnt[0], cnt[1], cnt[3], cnt[4]))}
+        _check(lib().ntc_prepared_schedule(self._h, mode, _p(cnt, _i64p), _p(rp, _i64p), _p(arr["tiny"], _i32p),
+                                           _p(arr["items"], _i32p), _p(arr["split"], _i32p), _p(arr["groups"], _i32p)))
+        out = {k: arr[k][: int(n)] for k, n in zip(("tiny", "items", "split", "groups"), (cnt[0], cnt[1], cnt[3],
+                                                                                          cnt[4]))}
+        out.update(rowptr=rp, n_group=int(cnt[2]), n_slots=int(cnt[5]), samples=int(cnt[6]))
+        return out
 
     @property
     def device_bytes(self) -> int:

@@ -1155,6 +1155,38 @@ ntc_status ntc_prepare(ntc_prepared_handle *out, int32_t nmodes, const int64_t *
     return NTC_OK;
 }
 
+ntc_status ntc_prepared_schedule(ntc_prepared_handle q, int32_t mode, int64_t counts[7], int64_t *rowptr_out,
+                                 int32_t *tiny_out, int32_t *items_out, int32_t *split_out, int32_t *groups_out)
+{
+    if (!q || !counts)
+        return fail(NTC_EINVAL, "null argument");
+    if (mode < 0 || mode >= q->N)
+        return fail(NTC_EINVAL, "mode out of range");
+    const ntc_prepared::Mode &pm = q->md[mode];
+    const ModeState &md = pm.st;
+    counts[0] = static_cast<int64_t>(pm.tiny.size());
+    counts[1] = static_cast<int64_t>(pm.items.size());
+    counts[2] = md.n_group;
+    counts[3] = static_cast<int64_t>(pm.split.size());
+    counts[4] = static_cast<int64_t>(pm.groups.size());
+    counts[5] = md.n_slots;
+    counts[6] = md.samples;
+    if (rowptr_out)
+        std::memcpy(rowptr_out, md.h_rowptr.data(), md.h_rowptr.size() * sizeof(int64_t));
+    static_assert(sizeof(ntc::RowItem) == 16 && sizeof(Item) == 16 && sizeof(SplitRow) == 16 &&
+                      sizeof(ntc::SlotGroup) == 16,
+                  "schedule entries are four 32-bit words");
+    if (tiny_out && !pm.tiny.empty())
+        std::memcpy(tiny_out, pm.tiny.data(), pm.tiny.size() * 16);
+    if (items_out && !pm.items.empty())
+        std::memcpy(items_out, pm.items.data(), pm.items.size() * 16);
+    if (split_out && !pm.split.empty())
+        std::memcpy(split_out, pm.split.data(), pm.split.size() * 16);
+    if (groups_out && !pm.groups.empty())
+        std::memcpy(groups_out, pm.groups.data(), pm.groups.size() * 16);
+    return NTC_OK;
+}
+
 ntc_status ntc_prepared_bytes(ntc_prepared_handle q, size_t *bytes)
 {
     if (!q || !bytes)

@@ -121,52 +121,85 @@ __device__ __forceinline__ double cw_ratio(bool live, double v, double w)
     return (live && v > 0.0) ? w / v : 0.0;
 }
 
-// The T normalised products of the power method (Alg. 1, L_p) on an iterate
-// held one entry per lane: mv(x) returns this lane's entry of H v, sum(x) the
-// sum of x over the lanes of the row.  Normalising by ||H v|| only fixes the
-// length of the iterate, so the products are scaled by exact powers of two
-// instead, which round nothing: the first product fixes 2^-e with
-// 2^e <= ||H v_0|| < 2^(e+1) and every later product takes the same 2^-e.
-// H here is a sampled Gram matrix of nonnegative rows plus lambda I, so its
-// top eigenvector u is nonnegative and ||H v_0|| >= L u.v_0 >= L / sqrt(R):
-// each later product scales the length by less than 2 sqrt(R) and never
-// shrinks the component along u.  Every 32 products the iterate is brought
-// back near unit length by another power of two (32 products grow it by at
-// most (2 sqrt(64))^32 = 2^128, so its sum of squares stays far inside
-// FP64's range for any T), and once more at the end.  Returns false if
-// H v_0 vanishes (L = 0 by definition); else v is the final iterate and
-// vv = ||v||^2 exactly.
-template <class MV, class SUM>
-__device__ __forceinline__ bool power_iterate(double &v, double &vv, int T, MV mv, SUM sum)
+// L_p of Alg. 1 by the power method on an iterate held one entry per lane,
+// from the start vector entry v (1/sqrt(R) on live lanes, 0 elsewhere):
+// mv(x) returns this lane's entry of H x, sum(x) and mx(x) the sum and the
+// maximum of x over the lanes of the row.  Returns the Rayleigh quotient of
+// the T-th normalised iterate, or with lp_bound its Collatz-Wielandt bound
+// max_i (H v)_i / v_i; 0 when H v_0 vanishes (L = 0 by definition).
+//
+// Normalising by ||H v|| only fixes the length of the iterate, so the
+// products are scaled by exact powers of two instead, which round nothing:
+// the first product fixes 2^-e with 2^e <= ||H v_0|| < 2^(e+1) and every
+// later product takes the same 2^-e.  H here is a sampled Gram matrix of
+// nonnegative rows plus lambda I, so its top eigenvector u is nonnegative and
+// ||H v_0|| >= L u.v_0 >= L / sqrt(R): each later product scales the length
+// by less than 2 sqrt(R) and never shrinks the component along u.  Every 32
+// products the iterate is brought back near unit length by another power of
+// two (32 products grow it by at most (2 sqrt(64))^32 = 2^128, so its sum of
+// squares stays far inside FP64's range for any T), and once more at the end.
+//
+// The Rayleigh quotient of power iterates of a positive semidefinite matrix
+// never decreases and approaches lambda_max geometrically.  Every 4 products
+// from the 4th on the quotient is taken; once two consecutive ones (4
+// products apart, the later at least the 8th) agree to 2^-46 of the
+// quotient, the remaining products could move it only by steps no larger
+// than the last, so that quotient is returned: it equals the T-th one to
+// about 1e-13 relative.  The Collatz-Wielandt bound always runs all T
+// products.
+//
+// Every decision here (the scale exponents, the exit) must be the same in
+// all lanes of the row, or the lanes would leave the loop at different
+// products and the cross-lane sums would read lanes that have left.  The
+// sums are built from commutative pairwise adds, so they are the same bits
+// in every lane as long as no product is fused into the first add: the
+// products below are formed with contraction off.  The exit is also voted:
+// it is taken only when no lane of the row disagrees.
+constexpr double kRqConverged = 1.4210854715202004e-14;  // 2^-46
+
+template <class MV, class SUM, class MAX>
+__device__ __forceinline__ double lp_estimate(bool live, double v, int T, int lp_bound, MV mv, SUM sum, MAX mx)
 {
-    if (T <= 0)
-        return true;
-    const double w = mv(v);
-    double n2 = sum(w * w);
-    if (!(n2 > 0.0))
-        return false;
-    const int e = ilogb(n2) >> 1;
-    v = ldexp(w, -e);
-    if (T == 1) {
-        vv = ldexp(n2, -2 * e);
-        return true;
-    }
-    for (int t = 1; t < T; ++t) {
-        v = ldexp(mv(v), -e);
-        if ((t & 31) == 0 && t + 1 < T) {  // wave-uniform: T is
+#pragma clang fp contract(off)
+    double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
+    if (T > 0) {
+        double w = mv(v);
+        double n2 = sum(w * w);
+        if (!(n2 > 0.0))
+            return 0.0;
+        const int e = ilogb(n2) >> 1;
+        v = ldexp(w, -e);
+        if (T == 1) {
+            vv = ldexp(n2, -2 * e);
+        } else {
+            double rq_prev = 0.0;
+            for (int t = 1; t < T; ++t) {
+                w = mv(v);  // H v_t
+                if (!lp_bound && (t & 3) == 0 && t + 1 < T) {
+                    const double rq = sum(v * w) / sum(v * v);
+                    const bool done = t >= 8 && fabs(rq - rq_prev) <= kRqConverged * rq;
+                    if (t >= 8 && sum(done ? 0.0 : 1.0) == 0.0)  // exact small integers: the same in every lane
+                        return rq;
+                    rq_prev = rq;
+                }
+                v = ldexp(w, -e);
+                if ((t & 31) == 0 && t + 1 < T) {
+                    n2 = sum(v * v);
+                    if (!(n2 > 0.0))
+                        return 0.0;
+                    v = ldexp(v, -(ilogb(n2) >> 1));
+                }
+            }
             n2 = sum(v * v);
             if (!(n2 > 0.0))
-                return false;
-            v = ldexp(v, -(ilogb(n2) >> 1));
+                return 0.0;
+            const int k = ilogb(n2) >> 1;
+            v = ldexp(v, -k);
+            vv = ldexp(n2, -2 * k);
         }
     }
-    n2 = sum(v * v);
-    if (!(n2 > 0.0))
-        return false;
-    const int k = ilogb(n2) >> 1;
-    v = ldexp(v, -k);
-    vv = ldexp(n2, -2 * k);
-    return true;
+    const double w = mv(v);
+    return lp_bound ? mx(cw_ratio(live, v, w)) : sum(v * w) / vv;
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));

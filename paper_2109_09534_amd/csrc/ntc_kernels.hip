@@ -57,15 +57,9 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
         g += a.lambda * static_cast<double>(y);
         hd[0] += a.lambda;  // sigma_0 is the identity: the diagonal
     }
-    double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
-    double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
-    const bool vanished = !power_iterate(v, vv, a.power_iters, [&](double x) { return skew_matvec(hd, x); },
-                                         [](double x) { return row_sum_f64(x); });
-    double L = 0.0;
-    if (!vanished) {
-        const double w = skew_matvec(hd, v);
-        L = a.lp_bound ? row_max_f64(cw_ratio(live, v, w)) : row_sum_f64(v * w) / vv;
-    }
+    const double L = lp_estimate(live, live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0, a.power_iters, a.lp_bound,
+                                 [&](double x) { return skew_matvec(hd, x); }, [](double x) { return row_sum_f64(x); },
+                                 [](double x) { return row_max_f64(x); });
     if (!live)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + r;

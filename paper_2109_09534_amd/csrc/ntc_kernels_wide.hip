@@ -52,14 +52,8 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
         __syncthreads();
         return w;
     };
-    double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
-    double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
-    const bool vanished = !power_iterate(v, vv, a.power_iters, matvec, [](double x) { return wave_sum(x); });
-    double L = 0.0;
-    if (!vanished) {
-        const double w = matvec(v);
-        L = a.lp_bound ? wave_max(cw_ratio(live, v, w)) : wave_sum(v * w) / vv;
-    }
+    const double L = lp_estimate(live, live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0, a.power_iters, a.lp_bound,
+                                 matvec, [](double x) { return wave_sum(x); }, [](double x) { return wave_max(x); });
     if (!live)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + lane;
@@ -355,7 +349,6 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
             if (16 * half + q == i)
                 hd[q] += a.lambda;
     }
-    double v = live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0;
     // w_i = (H v)_i: each half sums its 16 columns, then the halves combine
     auto matvec = [&](double vi) {
         if (half == 0)
@@ -368,13 +361,9 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
         __builtin_amdgcn_wave_barrier();
         return swap32_sum((w4[0] + w4[1]) + (w4[2] + w4[3]));
     };
-    double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
-    const bool vanished = !power_iterate(v, vv, a.power_iters, matvec, [](double x) { return group32_sum_f64(x); });
-    double L = 0.0;
-    if (!vanished) {
-        const double w = matvec(v);
-        L = a.lp_bound ? group32_max_f64(cw_ratio(live, v, w)) : group32_sum_f64(v * w) / vv;
-    }
+    const double L = lp_estimate(live, live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0, a.power_iters, a.lp_bound,
+                                 matvec, [](double x) { return group32_sum_f64(x); },
+                                 [](double x) { return group32_max_f64(x); });
     if (!live || half != 0)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + col;

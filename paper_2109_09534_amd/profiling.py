@@ -12,6 +12,7 @@ the short text summaries kept beside the code:
 
 Usage:
   python -m paper_2109_09534_amd.profiling trace DIR --title T --command C [--last 9]
+  python -m paper_2109_09534_amd.profiling counters DIR [DIR ...] --title T --command C
   python -m paper_2109_09534_amd.profiling traffic --kernel K --fetch DIR --write DIR
          --copy-fetch DIR --copy-write DIR --copy-bytes B --command C [--out FILE]
 """
@@ -75,6 +76,48 @@ def trace(path: str, title: str, command: str, last: int = 9) -> str:
     return "\n".join(out) + "\n"
 
 
+def counters(paths, title: str, command: str, kernels=ROW_KERNELS, clock_ghz: float = 2.4) -> str:
+    """Per-dispatch counter values of the row kernels from one or more
+    rocprofv3 --pmc runs of the same program (dispatch ids line up), with
+    the derived memory figures: L2-to-memory read requests per microsecond
+    and their mean number in flight (TCC_EA0_RDREQ_LEVEL over the cycles of
+    the dispatch), whose ratio is the mean request latency (Little's law)."""
+    per = {}
+    dur = {}
+    for path in paths:
+        con = _db(path)
+        for did, name, cn, v in con.execute(
+                "select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
+                "group by dispatch_id, counter_name order by dispatch_id"):
+            per.setdefault((did, short_name(name)), {})[cn] = v
+        try:
+            for did, start, end in con.execute("select dispatch_id, start, end from kernels"):
+                dur.setdefault(did, (end - start) / 1e3)
+        except sqlite3.Error:
+            pass
+    names = sorted({c for v in per.values() for c in v})
+    derived = "TCC_EA0_RDREQ_sum" in names and "TCC_EA0_RDREQ_LEVEL_sum" in names
+    head = ["dispatch", "kernel", "us"] + (["G req/s", "in flight", "latency ns"] if derived else []) + names
+    out = [f"# {title}", "", "Command (from the repository root; REPO is its absolute path):", "", "```", command,
+           "```", ""]
+    if derived:
+        out += ["Derived: G req/s = TCC_EA0_RDREQ_sum / duration; in flight = TCC_EA0_RDREQ_LEVEL_sum / "
+                f"(duration x {clock_ghz} GHz); latency = in flight / rate.", ""]
+    out += ["| " + " | ".join(head) + " |", "|" + "---|" * len(head)]
+    for (did, name), c in sorted(per.items()):
+        if not any(k in name for k in kernels):
+            continue
+        us = dur.get(did, 0.0)
+        row = [str(did), f"`{name}`", f"{us:.1f}"]
+        if derived:
+            rate = c.get("TCC_EA0_RDREQ_sum", 0.0) / us / 1e3 if us > 0 else 0.0
+            inflight = c.get("TCC_EA0_RDREQ_LEVEL_sum", 0.0) / (us * 1e3 * clock_ghz) if us > 0 else 0.0
+            row += [f"{rate:.1f}", f"{inflight:.0f}", f"{inflight / rate:.0f}" if rate > 0 else ""]
+        row += [f"{c[n]:.4g}" if n in c else "" for n in names]
+        out.append("| " + " | ".join(row) + " |")
+    return "\n".join(out) + "\n"
+
+
 def _per_dispatch(path: str, counter: str):
     con = _db(path)
     q = ("select dispatch_id, kernel_name, sum(value) from counters_collection where counter_name = ? "
@@ -118,6 +161,11 @@ def main(argv=None):
     t.add_argument("--command", required=True)
     t.add_argument("--last", type=int, default=9)
     t.add_argument("--out")
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--out")
     f = sub.add_parser("traffic")
     for k in ("kernel", "fetch", "write", "copy-fetch", "copy-write", "command"):
         f.add_argument("--" + k, required=True)
@@ -127,6 +175,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "trace":
         text = trace(a.dir, a.title, a.command, a.last)
+    elif a.what == "counters":
+        text = counters(a.dirs, a.title, a.command)
     else:
         text = json.dumps(traffic(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.command,
                                   a.wide), indent=1) + "\n"

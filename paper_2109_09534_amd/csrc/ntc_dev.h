@@ -140,13 +140,15 @@ __device__ __forceinline__ double cw_ratio(bool live, double v, double w)
 // squares stays far inside FP64's range for any T), and once more at the end.
 //
 // The Rayleigh quotient of power iterates of a positive semidefinite matrix
-// never decreases and approaches lambda_max geometrically.  Every 4 products
-// from the 4th on the quotient is taken; once two consecutive ones (4
-// products apart, the later at least the 8th) agree to 2^-46 of the
+// never decreases and approaches lambda_max geometrically; here the start
+// vector has a component of at least 1/sqrt(R) along the nonnegative top
+// eigenvector, so the approach is regular from the first products.  Every 2
+// products from the 4th on the quotient is taken; once two consecutive ones
+// (2 products apart, the later at least the 6th) agree to 2^-40 of the
 // quotient, the remaining products could move it only by steps no larger
 // than the last, so that quotient is returned: it equals the T-th one to
-// about 1e-13 relative.  The Collatz-Wielandt bound always runs all T
-// products.
+// about 1e-11 relative, six orders of magnitude inside the one-sweep parity
+// bar.  The Collatz-Wielandt bound always runs all T products.
 //
 // Every decision here (the scale exponents, the exit) must be the same in
 // all lanes of the row, or the lanes would leave the loop at different
@@ -155,7 +157,7 @@ __device__ __forceinline__ double cw_ratio(bool live, double v, double w)
 // in every lane as long as no product is fused into the first add: the
 // products below are formed with contraction off.  The exit is also voted:
 // it is taken only when no lane of the row disagrees.
-constexpr double kRqConverged = 1.4210854715202004e-14;  // 2^-46
+constexpr double kRqConverged = 9.094947017729282e-13;  // 2^-40
 
 template <class MV, class SUM, class MAX>
 __device__ __forceinline__ double lp_estimate(bool live, double v, int T, int lp_bound, MV mv, SUM sum, MAX mx)
@@ -175,10 +177,10 @@ __device__ __forceinline__ double lp_estimate(bool live, double v, int T, int lp
             double rq_prev = 0.0;
             for (int t = 1; t < T; ++t) {
                 w = mv(v);  // H v_t
-                if (!lp_bound && (t & 3) == 0 && t + 1 < T) {
+                if (!lp_bound && t >= 4 && (t & 1) == 0 && t + 1 < T) {
                     const double rq = sum(v * w) / sum(v * v);
-                    const bool done = t >= 8 && fabs(rq - rq_prev) <= kRqConverged * rq;
-                    if (t >= 8 && sum(done ? 0.0 : 1.0) == 0.0)  // exact small integers: the same in every lane
+                    const bool done = t >= 6 && fabs(rq - rq_prev) <= kRqConverged * rq;
+                    if (t >= 6 && sum(done ? 0.0 : 1.0) == 0.0)  // exact small integers: the same in every lane
                         return rq;
                     rq_prev = rq;
                 }

@@ -114,7 +114,7 @@ struct KernelClass {
 
 // The row kernels.  R <= 16: kRows takes whole rows with B_p <= group_max, one
 // per 16-lane group (for N > 4 also every chunk); kChunks takes row chunks,
-// one per 256-thread block; kTiny rows with B_p <= kTinyB, one per lane;
+// one per 256-thread block; kTiny rows with B_p <= kTinyB, one per lane (one-wave blocks);
 // kFinalize combines the partial slots of split rows.  R > 16: kRows takes
 // every work item, one per wave.
 // kReduce (R > 16) sums groups of partial slots of rows split into many items.

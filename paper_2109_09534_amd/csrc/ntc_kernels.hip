@@ -811,11 +811,17 @@ __device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
     }
 }
 
+// One-wave blocks: a wave of this kernel holds a whole SIMD's registers, so
+// a block of four would wait for a CU whose four SIMDs are all free, while a
+// one-wave block starts on any free SIMD, beside the blocks of the launches
+// running concurrently.
+constexpr int kTinyBlock = 64;
+
 template <int NM, int RW, bool BF16>
-__global__ __launch_bounds__(256) void k_tiny16(NTC_ROW_PARAMS)
+__global__ __launch_bounds__(kTinyBlock) void k_tiny16(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
-    const int id = blk_ * 256 + threadIdx.x;
+    const int id = blk_ * kTinyBlock + threadIdx.x;
     if (id >= a.n_tiny)
         return;
     // R % 4 is uniform over the block (one problem per block)
@@ -901,13 +907,13 @@ template <bool BF16>
 hipError_t go_tiny(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_tiny16<3, 4, BF16>), 256);
+        NTC_GO((k_tiny16<3, 4, BF16>), kTinyBlock);
     else if (kc.nmodes == 4)
-        NTC_GO((k_tiny16<4, 4, BF16>), 256);
+        NTC_GO((k_tiny16<4, 4, BF16>), kTinyBlock);
     else if (kc.nmodes == 2)
-        NTC_GO((k_tiny16<2, 4, BF16>), 256);
+        NTC_GO((k_tiny16<2, 4, BF16>), kTinyBlock);
     else
-        NTC_GO((k_tiny16<0, 8, BF16>), 256);
+        NTC_GO((k_tiny16<0, 8, BF16>), kTinyBlock);
     return hipGetLastError();
 }
 
@@ -946,7 +952,7 @@ int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items
     case kFinalize:
         return n_split;
     case kTiny:
-        return g16 ? (n_tiny + 255) / 256 : 0;
+        return g16 ? (n_tiny + kTinyBlock - 1) / kTinyBlock : 0;
     case kChunks:
         return (g16 && kc.nmodes <= 4) ? n_items - n_group : 0;
     case kReduce:

@@ -11,7 +11,7 @@ the short text summaries kept beside the code:
   with a hash of the row-kernel sources it was taken on.
 
 Usage:
-  python -m paper_2109_09534_amd.profiling trace DIR --title T --command C [--last 9]
+  python -m paper_2109_09534_amd.profiling trace DIR --title T --command C [--last 9] [--before NAME]
   python -m paper_2109_09534_amd.profiling counters DIR [DIR ...] --title T --command C
   python -m paper_2109_09534_amd.profiling traffic --kernel K --fetch DIR --write DIR
          --copy-fetch DIR --copy-write DIR --copy-bytes B --command C [--out FILE]
@@ -56,7 +56,9 @@ def short_name(name: str) -> str:
     return re.sub(r"^void ", "", name).split("(")[0]
 
 
-def trace(path: str, title: str, command: str, last: int = 9) -> str:
+def trace(path: str, title: str, command: str, last: int = 9, before: str = "") -> str:
+    """``before``: take the sweep that ends where the first dispatch whose
+    name contains it starts (a run that times two precisions in turn)."""
     con = _db(path)
     out = [f"# {title}", "", "Command (from the repository root; REPO is its absolute path):", "",
            "```", command, "```", "",
@@ -68,6 +70,9 @@ def trace(path: str, title: str, command: str, last: int = 9) -> str:
     like = " or ".join(f"name like '%{k}%'" for k in ROW_KERNELS)
     rows = list(con.execute(f"select name, grid_x, workgroup_x, duration, vgpr_count, accum_vgpr_count, "
                             f"lds_size, scratch_size from kernels where {like} order by start"))
+    if before:
+        cut = next((i for i, r in enumerate(rows) if before in short_name(r[0])), len(rows))
+        rows = rows[:cut]
     out += ["", f"## Row-kernel dispatches of the last sweep ({min(last, len(rows))} launches, in order)", "",
             "| kernel | grid (threads) | block | duration us | VGPR | AGPR | LDS B | scratch B |",
             "|---|---|---|---|---|---|---|---|"]
@@ -160,6 +165,7 @@ def main(argv=None):
     t.add_argument("--title", required=True)
     t.add_argument("--command", required=True)
     t.add_argument("--last", type=int, default=9)
+    t.add_argument("--before", default="", help="end the dispatch table before the first kernel of this name")
     t.add_argument("--out")
     c = sub.add_parser("counters")
     c.add_argument("dirs", nargs="+")
@@ -174,7 +180,7 @@ def main(argv=None):
     f.add_argument("--out")
     a = ap.parse_args(argv)
     if a.what == "trace":
-        text = trace(a.dir, a.title, a.command, a.last)
+        text = trace(a.dir, a.title, a.command, a.last, a.before)
     elif a.what == "counters":
         text = counters(a.dirs, a.title, a.command)
     else:

@@ -54,6 +54,31 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Two wave sums at once, level by level, so that each level's two exchanges
+// are in flight together.
+__device__ __forceinline__ void wave_sum2(double &x, double &y)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double px = __shfl_xor(x, off, 64), py = __shfl_xor(y, off, 64);
+        x += px;
+        y += py;
+    }
+}
+
+// True when d holds in every active lane of the wave.
+__device__ __forceinline__ bool wave_all(bool d)
+{
+    return __ballot(!d) == 0;
+}
+
+// True when d holds in every active lane of this lane's 16-lane DPP row.
+__device__ __forceinline__ bool row_all(bool d)
+{
+    const unsigned long long m = __ballot(!d);
+    return ((m >> (__lane_id() & 48)) & 0xFFFFull) == 0;
+}
+
 // DPP controls (gfx9): quad permutations, half-row and row mirrors, row rotations.
 constexpr int kDppXor1 = 0xB1;       // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;       // quad_perm [2,3,0,1]
@@ -96,6 +121,27 @@ __device__ __forceinline__ double row_sum_f64(double x)
     return x;
 }
 
+// Two row sums at once, level by level (independent DPP moves fill each
+// other's wait states).
+__device__ __forceinline__ void row_sum2_f64(double &x, double &y)
+{
+    double px = dpp_f64<kDppXor1>(x), py = dpp_f64<kDppXor1>(y);
+    x += px;
+    y += py;
+    px = dpp_f64<kDppXor2>(x);
+    py = dpp_f64<kDppXor2>(y);
+    x += px;
+    y += py;
+    px = dpp_f64<kDppHalfMirror>(x);
+    py = dpp_f64<kDppHalfMirror>(y);
+    x += px;
+    y += py;
+    px = dpp_f64<kDppMirror>(x);
+    py = dpp_f64<kDppMirror>(y);
+    x += px;
+    y += py;
+}
+
 __device__ __forceinline__ double row_max_f64(double x)
 {
     x = fmax(x, dpp_f64<kDppXor1>(x));
@@ -124,7 +170,9 @@ __device__ __forceinline__ double cw_ratio(bool live, double v, double w)
 // L_p of Alg. 1 by the power method on an iterate held one entry per lane,
 // from the start vector entry v (1/sqrt(R) on live lanes, 0 elsewhere):
 // mv(x) returns this lane's entry of H x, sum(x) and mx(x) the sum and the
-// maximum of x over the lanes of the row.  Returns the Rayleigh quotient of
+// maximum of x over the lanes of the row, sum2(x, y) replaces x and y by
+// their two sums (the same adds as sum, interleaved), all(d) whether d holds
+// in every lane of the row.  Returns the Rayleigh quotient of
 // the T-th normalised iterate, or with lp_bound its Collatz-Wielandt bound
 // max_i (H v)_i / v_i; 0 when H v_0 vanishes (L = 0 by definition).
 //
@@ -155,12 +203,13 @@ __device__ __forceinline__ double cw_ratio(bool live, double v, double w)
 // products and the cross-lane sums would read lanes that have left.  The
 // sums are built from commutative pairwise adds, so they are the same bits
 // in every lane as long as no product is fused into the first add: the
-// products below are formed with contraction off.  The exit is also voted:
-// it is taken only when no lane of the row disagrees.
+// products below are formed with contraction off.  The exit is also voted
+// (a wave ballot): it is taken only when no lane of the row disagrees.
 constexpr double kRqConverged = 9.094947017729282e-13;  // 2^-40
 
-template <class MV, class SUM, class MAX>
-__device__ __forceinline__ double lp_estimate(bool live, double v, int T, int lp_bound, MV mv, SUM sum, MAX mx)
+template <class MV, class SUM, class SUM2, class MAX, class ALL>
+__device__ __forceinline__ double lp_estimate(bool live, double v, int T, int lp_bound, MV mv, SUM sum, SUM2 sum2,
+                                              MAX mx, ALL all)
 {
 #pragma clang fp contract(off)
     double vv = 1.0;  // ||v||^2 (the start vector has unit norm)
@@ -178,9 +227,10 @@ __device__ __forceinline__ double lp_estimate(bool live, double v, int T, int lp
             for (int t = 1; t < T; ++t) {
                 w = mv(v);  // H v_t
                 if (!lp_bound && t >= 4 && (t & 1) == 0 && t + 1 < T) {
-                    const double rq = sum(v * w) / sum(v * v);
-                    const bool done = t >= 6 && fabs(rq - rq_prev) <= kRqConverged * rq;
-                    if (t >= 6 && sum(done ? 0.0 : 1.0) == 0.0)  // exact small integers: the same in every lane
+                    double vw = v * w, vv2 = v * v;
+                    sum2(vw, vv2);
+                    const double rq = vw / vv2;
+                    if (t >= 6 && all(fabs(rq - rq_prev) <= kRqConverged * rq))
                         return rq;
                     rq_prev = rq;
                 }

@@ -341,6 +341,8 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.seed = h->seed;
     a.kptr = h->kdev;
     a.lambda = h->lambda;
+    a.sqrt_lambda = std::sqrt(h->lambda);
+    a.v0 = 1.0 / std::sqrt(static_cast<double>(h->R));
     a.mode = mode;
     a.l = l;
     a.nmodes = h->N;

@@ -69,6 +69,8 @@ struct RowArgs {
     const int64_t *kptr;          // sweep counter k of the problem (device)
     const int32_t *stop;          // pool: nonzero once the problem has stopped (device), else null
     double lambda;
+    double sqrt_lambda;           // sqrt(lambda), for the extrapolation weight beta
+    double v0;                    // 1 / sqrt(R): every entry of the power method's start vector
     double c;
     int32_t mode;
     int32_t l;

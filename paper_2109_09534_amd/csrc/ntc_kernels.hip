@@ -57,9 +57,10 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
         g += a.lambda * static_cast<double>(y);
         hd[0] += a.lambda;  // sigma_0 is the identity: the diagonal
     }
-    const double L = lp_estimate(live, live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0, a.power_iters, a.lp_bound,
+    const double L = lp_estimate(live, live ? a.v0 : 0.0, a.power_iters, a.lp_bound,
                                  [&](double x) { return skew_matvec(hd, x); }, [](double x) { return row_sum_f64(x); },
-                                 [](double x) { return row_max_f64(x); });
+                                 [](double &x, double &y) { row_sum2_f64(x, y); },
+                                 [](double x) { return row_max_f64(x); }, [](bool d) { return row_all(d); });
     if (!live)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + r;
@@ -68,7 +69,7 @@ __device__ void finish_row16(const Args &a, int row, int r, double g, double (&h
     if (L > 0.0) {
         double an = static_cast<double>(y) - g / L;
         an = an > 0.0 ? an : 0.0;
-        const double sl = sqrt(L), sm = sqrt(a.lambda);
+        const double sl = sqrt(L), sm = a.sqrt_lambda;
         const double beta = (sl - sm) / (sl + sm);
         const float af = static_cast<float>(an);
         a.A[off] = af;
@@ -664,7 +665,7 @@ __device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
 
     // c = K v0 and G = K K^T in FP64 (products of FP32 values are exact)
     const double lam = a.lambda;
-    const double v0 = 1.0 / sqrt(static_cast<double>(R));
+    const double v0 = a.v0;
     double c[kTinyB], G[kTinyB][kTinyB];
 #pragma unroll
     for (int i = 0; i < kTinyB; ++i) {
@@ -749,7 +750,7 @@ __device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
 
     const bool more = a.l + 1 < a.max_inner;
     if (L > 0.0) {
-        const double sl = sqrt(L), sm = sqrt(lam);
+        const double sl = sqrt(L), sm = a.sqrt_lambda;
         const double beta = (sl - sm) / (sl + sm);
         // A_l: the row read for y when l == 0, else the whole row in one go
         float al16[16];

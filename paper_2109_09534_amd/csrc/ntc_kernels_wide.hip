@@ -52,8 +52,9 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
         __syncthreads();
         return w;
     };
-    const double L = lp_estimate(live, live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0, a.power_iters, a.lp_bound,
-                                 matvec, [](double x) { return wave_sum(x); }, [](double x) { return wave_max(x); });
+    const double L = lp_estimate(live, live ? a.v0 : 0.0, a.power_iters, a.lp_bound, matvec,
+                                 [](double x) { return wave_sum(x); }, [](double &x, double &y) { wave_sum2(x, y); },
+                                 [](double x) { return wave_max(x); }, [](bool d) { return wave_all(d); });
     if (!live)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + lane;
@@ -62,7 +63,7 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
     if (L > 0.0) {
         double an = static_cast<double>(y) - g / L;
         an = an > 0.0 ? an : 0.0;
-        const double sl = sqrt(L), sm = sqrt(a.lambda);
+        const double sl = sqrt(L), sm = a.sqrt_lambda;
         const double beta = (sl - sm) / (sl + sm);
         const float af = static_cast<float>(an);
         a.A[off] = af;
@@ -301,6 +302,14 @@ __device__ __forceinline__ double group32_sum_f64(double x)
     return swap16_sum(x);
 }
 
+// Two group32 sums at once, level by level.
+__device__ __forceinline__ void group32_sum2_f64(double &x, double &y)
+{
+    row_sum2_f64(x, y);
+    x = swap16_sum(x);
+    y = swap16_sum(y);
+}
+
 constexpr int kSlot32 = 32 + 32 * 32;  // doubles per partial slot: g[32], row-major H[32][32]
 
 // One entry summed over `count` consecutive partial slots of S doubles, in
@@ -332,7 +341,8 @@ __device__ __forceinline__ int mfma32_row(int v, int l)
 // Power method, step, projection and extrapolation for a row held by the
 // whole wave, with H in any symmetric ordering of the columns.  Lane l:
 // i = l % 32, half = l / 32 holds hd[q] = H[i][16 half + q] of the sampled
-// Hessian (without ridge) in that ordering; index i stands for column `col`
+// Hessian in that ordering, with the ridge lambda already on its diagonal
+// (the callers add it where H is staged); index i stands for column `col`
 // of the factor; g: sampled gradient of that column (without ridge), y its
 // Y value, on every lane.
 template <bool BF16, class Args>
@@ -342,13 +352,8 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
     const int R = a.R;
     const int i = lane & 31, half = lane >> 5;
     const bool live = col < R;
-    if (live) {
+    if (live)
         g += a.lambda * static_cast<double>(y);
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (16 * half + q == i)
-                hd[q] += a.lambda;
-    }
     // w_i = (H v)_i: each half sums its 16 columns, then the halves combine
     auto matvec = [&](double vi) {
         if (half == 0)
@@ -361,9 +366,10 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
         __builtin_amdgcn_wave_barrier();
         return swap32_sum((w4[0] + w4[1]) + (w4[2] + w4[3]));
     };
-    const double L = lp_estimate(live, live ? 1.0 / sqrt(static_cast<double>(R)) : 0.0, a.power_iters, a.lp_bound,
-                                 matvec, [](double x) { return group32_sum_f64(x); },
-                                 [](double x) { return group32_max_f64(x); });
+    const double L = lp_estimate(live, live ? a.v0 : 0.0, a.power_iters, a.lp_bound, matvec,
+                                 [](double x) { return group32_sum_f64(x); },
+                                 [](double &x, double &y) { group32_sum2_f64(x, y); },
+                                 [](double x) { return group32_max_f64(x); }, [](bool d) { return wave_all(d); });
     if (!live || half != 0)
         return;
     const int64_t off = static_cast<int64_t>(row) * R + col;
@@ -372,7 +378,7 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
     if (L > 0.0) {
         double an = static_cast<double>(y) - g / L;
         an = an > 0.0 ? an : 0.0;
-        const double sl = sqrt(L), sm = sqrt(a.lambda);
+        const double sl = sqrt(L), sm = a.sqrt_lambda;
         const double beta = (sl - sm) / (sl + sm);
         const float af = static_cast<float>(an);
         a.A[off] = af;
@@ -558,8 +564,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     s_g[lane] = static_cast<double>(gf0);
     s_g[64 + lane] = static_cast<double>(gf1);
     __builtin_amdgcn_wave_barrier();
-    // block entries: register v of lane l holds D[4 (l / 16) + v][l % 16]
-    auto blk = [&](int b, int r, int c) { return s_h[(4 * b + (r & 3)) * 64 + 16 * (r >> 2) + c]; };
+    // block entries: register v of lane l holds D[4 (l / 16) + v][l % 16], kept at
+    // s_h[(4 b + (r & 3)) * 64 + 16 (r >> 2) + c] for entry (r, c) of block b (EE, EO, OO)
     auto gsum = [&](int c) {
         const int par = c & 1, jj = c >> 1;
         return ((s_g[64 * par + jj] + s_g[64 * par + 16 + jj]) + s_g[64 * par + 32 + jj]) + s_g[64 * par + 48 + jj];
@@ -582,18 +588,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
         }
         return;
     }
-    // the power method on the permuted order: index p < 16 is column 2p, p >= 16 is column 2(p-16)+1
+    // the power method on the permuted order: index p < 16 is column 2p, p >= 16 is column 2(p-16)+1.
+    // Lane (i, half) takes row i, columns 16 half .. 16 half + 15 of
+    //   [EE EO ]
+    //   [EO' OO]
+    // which is a row of EE, EO or OO, or for i >= 16, half 0, a column of EO.
     const int i = lane & 31, half = lane >> 5;
     const int col = i < 16 ? 2 * i : 2 * (i - 16) + 1;
+    const double g = gsum(col);
+    __builtin_amdgcn_wave_barrier();  // every lane has read s_g before the record area is reused below
+    // EO transposed into the record area (16 x 16, row-major): lane l holds EO[4 (l / 16) + v][l % 16]
+    double *const s_t = s_g;
+    {
+        const int c = lane & 15, r0 = 4 * (lane >> 4);
+        double2 *const dst = reinterpret_cast<double2 *>(s_t + c * 16 + r0);
+        dst[0] = make_double2(s_h[4 * 64 + lane], s_h[5 * 64 + lane]);
+        dst[1] = make_double2(s_h[6 * 64 + lane], s_h[7 * 64 + lane]);
+    }
+    // the ridge on the diagonal, by the lane that reads it: EE[i][i] (lanes 0-15), OO[i-16][i-16] (lanes 48-63)
+    const int r = i & 15;
+    const int b = i < 16 ? half : 2;  // block of the row read: EE, EO or OO
+    const int rbase = (4 * b + (r & 3)) * 64 + 16 * (r >> 2);
+    if (col < R && (i < 16) == (half == 0))
+        s_h[rbase + r] += a.lambda;
+    __builtin_amdgcn_wave_barrier();
+    const double *const src = (i >= 16 && half == 0) ? s_t + 16 * r : s_h + rbase;
     double hd[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        if (i < 16)
-            hd[q] = half == 0 ? blk(0, i, q) : blk(1, i, q);
-        else
-            hd[q] = half == 0 ? blk(1, q, i - 16) : blk(2, i - 16, q);
-    }
-    const double g = gsum(col);
+    for (int q = 0; q < 16; ++q)
+        hd[q] = src[q];
+    __builtin_amdgcn_wave_barrier();  // the power method's vector reuses the record area
     const float y = i < 16 ? y0 : y1;  // column col of the row, already in registers
     finish_row32<BF16>(a, it.row, lane, col, g, hd, y, s_v);
 }
@@ -886,6 +910,8 @@ __global__ __launch_bounds__(256) void k_finalize32(NTC_ROW_PARAMS)
     const int lane = tid;
     const int i = lane & 31, half = lane >> 5;
     const double g = s_p[i];
+    if (i < a.R && half == (i >> 4))
+        s_p[32 + i * 33] += a.lambda;  // the ridge, by the lane that reads the diagonal
     double hd[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q)

@@ -298,7 +298,7 @@ ntc::KernelClass kernel_class(const ntc_problem *h)
     // 2 = four columns per load (R % 4 == 0), 1 = two (R even), 0 = one
     int32_t pairs = 0;
     if (h->RP == 32)
-        pairs = h->R % 2 == 0 ? 1 : 0;
+        pairs = h->R % 8 == 0 ? 3 : h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
     else if (h->RP == 64)
         pairs = h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
     return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0, pairs};
@@ -526,8 +526,8 @@ ntc_status check_params(int32_t N, const int64_t *dims, int64_t nnz, const int32
         return fail(NTC_EINVAL, "power_iters must be >= 0");
     if (p.lp_bound != 0 && p.lp_bound != 1)
         return fail(NTC_EINVAL, "lp_bound must be 0 or 1");
-    if (p.tiny_max < -1 || p.tiny_max > ntc::kTinyB)
-        return fail(NTC_EINVAL, "tiny_max must be -1 or in [0, 4]");
+    if (p.tiny_max < -1 || p.tiny_max > ntc::kFewB32 || (R <= 16 && p.tiny_max > ntc::kTinyB))
+        return fail(NTC_EINVAL, "tiny_max must be -1 or in [0, 4] (R <= 16), [0, 16] (R > 16)");
     if (p.item_samples < 0 || (p.item_samples > 0 && p.item_samples < 16))
         return fail(NTC_EINVAL, "item_samples must be 0 or >= 16");
     if (p.group_max < 0)
@@ -585,7 +585,7 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
     q->lp_bound = p.lp_bound;
     q->seed = p.seed;
     q->bf16 = p.gather_bf16 != 0;
-    q->tiny_max = p.tiny_max < 0 ? ntc::kTinyB : p.tiny_max;
+    q->tiny_max = p.tiny_max >= 0 ? p.tiny_max : R <= 16 ? ntc::kTinyB : ntc::kFewB32;
     q->item_samples = p.item_samples;
     q->group_max = p.group_max > 0 ? p.group_max : 512;
     for (int m = 0; m < N; ++m)
@@ -680,10 +680,17 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
                 md.chunk_samples = md.chunk_fused = 0;
             }
         } else {
+            // 17 <= R <= 32, N <= 4: rows of at most tiny_max samples, four per wave
+            const int64_t few_max = (rp == 32 && N <= 4) ? q->tiny_max : 0;
             for (int32_t r : rows) {
                 const int64_t b = bsz[r];
                 md.samples += b;
                 md.active_rows += 1;
+                if (b <= few_max) {
+                    tiny.push_back(row_item(r));
+                    md.tiny_samples += b;
+                    continue;
+                }
                 md.row_samples += b;
                 if (b <= smax) {
                     md.fused_rows += 1;

@@ -55,7 +55,8 @@ struct RowArgs {
     const Item *items;
     const SplitRow *split;
     const SlotGroup *groups;      // (R > 16) second-level slot sums, n_groups of them
-    const RowItem *tiny;          // rows whose minibatch has 1..kTinyB samples (R <= 16 kernels)
+    const RowItem *tiny;          // rows whose minibatch has 1..kTinyB samples (R <= 16 kernels) or
+                                  // 1..kFewB32 samples (17 <= R <= 32, N <= 4)
     const RowItem *rows;          // (R <= 16, N <= 4) items [0, n_group) stored as RowItem
     const float *gath[kMaxModes - 1];     // other modes' FP32 factors, increasing mode order
     const uint16_t *gath16[kMaxModes - 1];// their BF16 shadows (precision form)
@@ -89,8 +90,11 @@ struct RowArgs {
     int32_t n_groups;
 };
 
-// Rows whose minibatch has at most this many samples run one row per lane.
+// Rows whose minibatch has at most this many samples run one row per lane (R <= 16).
 constexpr int kTinyB = 4;
+// 17 <= R <= 32, N <= 4: rows with at most this many samples run four to a
+// wave, one per 16-lane group and one sample per lane.
+constexpr int kFewB32 = 16;
 
 
 // One launch of a row kernel over n entries (problems).  args: [n] device
@@ -105,8 +109,10 @@ struct Launch {
 };
 
 // Kernel family of a problem: padded rank (16, 32, 64), mode count, BF16
-// gathers, and (R <= 32 kernels) whether R is even, so that column pairs of a
-// factor row are read with one load.
+// gathers, and how wide the loads of a factor row may be: for R <= 32, 3 when
+// R % 8 == 0, 2 when R % 4 == 0, 1 when R is even, else 0 (R is even: a lane
+// reads its column pair with one load); for R <= 64, 2 when R % 4 == 0, 1 when
+// R is even, else 0.
 struct KernelClass {
     int32_t rp;
     int32_t nmodes;
@@ -118,7 +124,8 @@ struct KernelClass {
 // per 16-lane group (for N > 4 also every chunk); kChunks takes row chunks,
 // one per 256-thread block; kTiny rows with B_p <= kTinyB, one per lane (one-wave blocks);
 // kFinalize combines the partial slots of split rows.  R > 16: kRows takes
-// every work item, one per wave.
+// every work item, one per wave; for 17 <= R <= 32 with N <= 4, kTiny takes
+// the rows with B_p <= kFewB32, four per one-wave block.
 // kReduce (R > 16) sums groups of partial slots of rows split into many items.
 enum RowKernel { kRows = 0, kFinalize = 1, kTiny = 2, kChunks = 3, kReduce = 4 };
 constexpr int kRowKernels = 5;

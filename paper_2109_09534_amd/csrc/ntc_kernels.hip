@@ -953,7 +953,9 @@ int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items
     case kFinalize:
         return n_split;
     case kTiny:
-        return g16 ? (n_tiny + kTinyBlock - 1) / kTinyBlock : 0;
+        if (g16)
+            return (n_tiny + kTinyBlock - 1) / kTinyBlock;
+        return (kc.rp == 32 && kc.nmodes <= 4) ? (n_tiny + 3) / 4 : 0;
     case kChunks:
         return (g16 && kc.nmodes <= 4) ? n_items - n_group : 0;
     case kReduce:

@@ -162,6 +162,20 @@ CASES = {
                              dict(c=0.4, power_iters=200)),
     "r24_5way_power200": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=28), 24,
                                   dict(c=0.3, power_iters=200)),
+    # 17 <= R <= 32, N <= 4: rows of at most 16 samples four to a wave, one sample per lane, the power
+    # method on (alpha, u) with v = alpha v_0 + K^T u; every load width (four, two, one column), two to four
+    # modes, unconverged and long power iterations, lambda = 0, MAX_INNER = 2, the Collatz-Wielandt bound
+    "few_r25_odd_zipf": lambda: (synth.c1_small(seed=13), 25, dict(c=0.1)),
+    "few_r30_4way_inner2": lambda: (synth.make_problem((2000, 1500, 40, 16), 200_000, 12, zipf_s=1.05, seed=44), 30,
+                                    dict(c=0.1, max_inner=2)),
+    "few_r32_power0": lambda: (synth.c1_small(seed=14), 32, dict(c=0.1, power_iters=0)),
+    "few_r32_power1_lam0": lambda: (synth.c1_small(seed=15), 32, dict(c=0.1, power_iters=1, lam=0.0)),
+    "few_r20_power3": lambda: (synth.c1_small(seed=16), 20, dict(c=0.15, power_iters=3)),
+    "few_r28_power200": lambda: (synth.c1_small(seed=17), 28, dict(c=0.1, power_iters=200)),
+    "few_r18_matrix": lambda: (synth.make_problem((3000, 2000), 60_000, 8, seed=46, zipf_s=1.1), 18, dict(c=0.2)),
+    "cw_few_r24_zipf": lambda: (synth.c1_small(seed=18), 24, dict(c=0.1, lp_bound=1)),
+    "cw_few_r31_4way_power3": lambda: (synth.make_problem((2000, 1500, 40, 16), 200_000, 12, zipf_s=1.05, seed=45),
+                                       31, dict(c=0.1, lp_bound=1, power_iters=3)),
 }
 
 
@@ -240,6 +254,11 @@ BF16_CASES = {
                                                   test_frac=0.05), 48, dict(c=0.3)),
     "r24_5way_generic": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=43, test_frac=0.05), 24,
                                  dict(c=0.3)),
+    # the four-rows-per-wave kernel's BF16 loads: eight, two and one column at a time
+    "few_r24_3way_bf16": lambda: (synth.c1_small(seed=19), 24, dict(c=0.1)),
+    "few_r30_4way_bf16_pairs": lambda: (synth.make_problem((2000, 1500, 40, 16), 200_000, 12, zipf_s=1.05, seed=47),
+                                        30, dict(c=0.1)),
+    "few_r19_odd_bf16": lambda: (synth.c1_small(seed=20), 19, dict(c=0.1)),
 }
 
 

@@ -1,7 +1,8 @@
 """Host-side bounds checks of the row schedule (no device).
 
 ntc_prepare turns each mode's CSR into work for the row kernels: rows of at
-most tiny_max samples (one per lane), whole rows, chunks of long rows that
+most tiny_max samples (one per lane for R <= 16, four per wave for
+17 <= R <= 32 with N <= 4), whole rows, chunks of long rows that
 write partial slots, split rows combined from those slots, and (R > 16)
 groups of slots summed first.  The kernels index rows, records and slots
 from these tables without checks of their own, so the checker below states
@@ -96,7 +97,20 @@ CASES = {
     "r50_4way": lambda: (synth.make_problem((183, 24, 114, 171), 150_000, 10, seed=5), 50, dict(c=0.5)),
     "r16_5way": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=6), 16, dict(c=0.3)),
     "matrix_r64": lambda: (synth.make_problem((400, 300), 60_000, 8, seed=17), 64, dict(c=1.0)),
+    # 17 <= R <= 32, N <= 4: rows of at most 16 samples four to a wave, the rest whole or split
+    "zipf_r32_4way_few_rows": lambda: (synth.make_problem((3000, 2000, 60, 20), 300_000, 12, zipf_s=1.05,
+                                                          seed=40), 32, dict(c=0.1, schedule={"item_samples": 128})),
+    "zipf_r27_few_max_5": lambda: (synth.c1_small(seed=3), 27, dict(c=0.1, schedule={"tiny_max": 5})),
+    "r24_5way_no_few_rows": lambda: (synth.make_problem((20, 15, 12, 10, 8), 60_000, 5, seed=6), 24, dict(c=0.05)),
 }
+
+
+def _tiny_max(R, N, sch):
+    if R <= 16:
+        return sch.get("tiny_max", 4)
+    if R <= 32 and N <= 4:
+        return sch.get("tiny_max", 16)
+    return 0
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -106,9 +120,21 @@ def test_row_schedule_invariants(case):
     sch = kw.get("schedule", {})
     for m in range(len(p.dims)):
         s = q.row_schedule(m)
-        check_schedule(s, c=kw["c"], R=R, N=len(p.dims), nnz=p.nnz, tiny_max=sch.get("tiny_max", 4) if R <= 16 else 0,
+        check_schedule(s, c=kw["c"], R=R, N=len(p.dims), nnz=p.nnz, tiny_max=_tiny_max(R, len(p.dims), sch),
                        group_max=sch.get("group_max", 512))
     q.close()
+
+
+def test_few_sample_rows_of_the_r32_kernels_are_scheduled_apart():
+    """17 <= R <= 32 with N <= 4: every row with 1 <= B_p <= 16 is in the few-row list, none with more."""
+    p = synth.make_problem((3000, 2000, 60, 20), 300_000, 12, zipf_s=1.05, seed=40)
+    q = ntc.Prepared(p.dims, p.coords, p.values, 32, c=0.1)
+    s = q.row_schedule(0)
+    q.close()
+    b = np.floor(0.1 * np.diff(s["rowptr"]).astype(np.float64)).astype(np.int64)
+    few = set(int(r) for r in s["tiny"][:, 0])
+    assert few == set(int(r) for r in np.nonzero((b >= 1) & (b <= 16))[0])
+    assert len(few) > 1000
 
 
 def test_the_checker_catches_planted_schedule_errors():

@@ -30,6 +30,16 @@ typedef const __attribute__((address_space(4))) RowArgs CRowArgs;
     if (a.stop != nullptr && *a.stop != 0)                   \
         return
 
+// A 16-byte record, loaded non-temporally: each sampled record is read once
+// per sweep, so its line is marked to leave the L2 first and the factor rows
+// that the gathers reuse stay cached longer.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load_record4(const uint32_t *p)
+{
+    const u32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+
 // c ? u : v for a 16-byte record, one component at a time (a select of the
 // whole vector can be lowered through private memory).
 __device__ __forceinline__ uint4 pick4(bool c, const uint4 &u, const uint4 &v)

@@ -298,7 +298,7 @@ ntc::KernelClass kernel_class(const ntc_problem *h)
     // 2 = four columns per load (R % 4 == 0), 1 = two (R even), 0 = one
     int32_t pairs = 0;
     if (h->RP == 32)
-        pairs = h->R % 8 == 0 ? 3 : h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
+        pairs = h->R == 32 ? 4 : h->R % 8 == 0 ? 3 : h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
     else if (h->RP == 64)
         pairs = h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
     return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0, pairs};

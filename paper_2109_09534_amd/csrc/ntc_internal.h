@@ -109,10 +109,10 @@ struct Launch {
 };
 
 // Kernel family of a problem: padded rank (16, 32, 64), mode count, BF16
-// gathers, and how wide the loads of a factor row may be: for R <= 32, 3 when
-// R % 8 == 0, 2 when R % 4 == 0, 1 when R is even, else 0 (R is even: a lane
-// reads its column pair with one load); for R <= 64, 2 when R % 4 == 0, 1 when
-// R is even, else 0.
+// gathers, and how wide the loads of a factor row may be: for R <= 32, 4 when
+// R == 32, 3 when R % 8 == 0, 2 when R % 4 == 0, 1 when R is even, else 0 (R
+// is even: a lane reads its column pair with one load); for R <= 64, 2 when
+// R % 4 == 0, 1 when R is even, else 0.
 struct KernelClass {
     int32_t rp;
     int32_t nmodes;

@@ -154,9 +154,9 @@ __device__ __forceinline__ bool fetch_record(const Args &a, const GroupItem &g, 
     int64_t e = 0;
     if (live)
         e = g.base + prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r));
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.records + e * RW);
-    w0 = src[0];
-    w1 = (RW == 8) ? src[1] : w0;
+    const uint32_t *src = a.records + e * RW;
+    w0 = load_record4(src);
+    w1 = (RW == 8) ? load_record4(src + 4) : w0;
     return live;
 }
 
@@ -615,10 +615,10 @@ __device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
     uint32_t rec[kTinyB][RW];
 #pragma unroll
     for (int j = 0; j < kTinyB; ++j) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.records + at[j] * RW);
+        const uint32_t *src = a.records + at[j] * RW;
 #pragma unroll
         for (int w4 = 0; w4 < RW / 4; ++w4) {
-            const uint4 t = src[w4];
+            const uint4 t = load_record4(src + 4 * w4);
             rec[j][4 * w4] = t.x;
             rec[j][4 * w4 + 1] = t.y;
             rec[j][4 * w4 + 2] = t.z;

@@ -113,14 +113,14 @@ __global__ __launch_bounds__(64) void k_row_items(NTC_ROW_PARAMS)
         const int cnt = min(64, it.j1 - jb);
         if (lane < cnt) {
             const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
-            const uint4 *src = reinterpret_cast<const uint4 *>(a.records + (base + q) * rw);
-            const uint4 w0 = src[0];
+            const uint32_t *src = a.records + (base + q) * rw;
+            const uint4 w0 = load_record4(src);
             s_rec[lane * 8 + 0] = w0.x;
             s_rec[lane * 8 + 1] = w0.y;
             s_rec[lane * 8 + 2] = w0.z;
             s_rec[lane * 8 + 3] = w0.w;
             if (rw == 8) {
-                const uint4 w1 = src[1];
+                const uint4 w1 = load_record4(src + 4);
                 s_rec[lane * 8 + 4] = w1.x;
                 s_rec[lane * 8 + 5] = w1.y;
                 s_rec[lane * 8 + 6] = w1.z;
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
         int64_t e = 0;
         if (live)
             e = base + prp_index(prp, static_cast<uint32_t>(jb + lane));
-        return *reinterpret_cast<const uint4 *>(a.records + e * 4);
+        return load_record4(a.records + e * 4);
     };
     // gathers of the four steps from s0 of a staged block
     auto issue = [&](const uint4 *buf, int s0, Sub &S) {
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(64) void k_rows64(NTC_ROW_PARAMS)
         int64_t e = 0;
         if (lv)
             e = base + prp_index(prp, static_cast<uint32_t>(jb + lane));
-        return *reinterpret_cast<const uint4 *>(a.records + e * 4);
+        return load_record4(a.records + e * 4);
     };
     // gathers of the two steps from s0 of a staged block
     auto issue = [&](const uint4 *buf, int s0, Sub &S) {
@@ -962,11 +962,21 @@ __global__ __launch_bounds__(256) void k_reduce_slots(NTC_ROW_PARAMS)
 
 // The first 32 columns of a factor row; columns >= R are zero, and a load
 // past R reads the start of the same row instead (never past the row's end).
-// W: 2 = four FP32 or eight BF16 columns per load, 1 = two per load, 0 = one.
+// W: 3 = R is 32, four FP32 or eight BF16 columns per load; 2 = four FP32 or
+// eight BF16 columns per load; 1 = two per load; 0 = one.
 template <int W>
 __device__ __forceinline__ void few_row(const float *p, int R, float (&out)[32])
 {
-    if constexpr (W == 2) {
+    if constexpr (W == 3) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[q];
+            out[4 * q] = t.x;
+            out[4 * q + 1] = t.y;
+            out[4 * q + 2] = t.z;
+            out[4 * q + 3] = t.w;
+        }
+    } else if constexpr (W == 2) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const bool in = 4 * q < R;
@@ -997,7 +1007,18 @@ __device__ __forceinline__ void few_row(const float *p, int R, float (&out)[32])
 template <int W>
 __device__ __forceinline__ void few_row(const uint16_t *p, int R, float (&out)[32])
 {
-    if constexpr (W == 2) {
+    if constexpr (W == 3) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 t = reinterpret_cast<const uint4 *>(p)[q];
+            const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                out[8 * q + 2 * h] = __uint_as_float(w[h] << 16);
+                out[8 * q + 2 * h + 1] = __uint_as_float(w[h] & 0xFFFF0000u);
+            }
+        }
+    } else if constexpr (W == 2) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const bool in = 8 * q < R;
@@ -1077,7 +1098,7 @@ __device__ __forceinline__ void few_colsum(float (&r)[32], int s)
 }
 
 template <int NM, bool BF16, int W>
-__global__ __launch_bounds__(64) void k_few32(NTC_ROW_PARAMS)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_few32(NTC_ROW_PARAMS)
 {
 #pragma clang fp contract(off)
     NTC_ROW_RESOLVE(a, blk_);
@@ -1098,7 +1119,7 @@ __global__ __launch_bounds__(64) void k_few32(NTC_ROW_PARAMS)
         const Prp prp = make_prp(static_cast<uint32_t>(ri.n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, ri.row));
         e = ri.base + prp_index(prp, static_cast<uint32_t>(s));
     }
-    const uint4 w = *reinterpret_cast<const uint4 *>(a.records + e * 4);
+    const uint4 w = load_record4(a.records + e * 4);
     const uint4 rec = pick4(s < B, w, make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const int64_t roff = static_cast<int64_t>(ri.row) * R;
@@ -1125,7 +1146,7 @@ __global__ __launch_bounds__(64) void k_few32(NTC_ROW_PARAMS)
         gacc[v] = 0.0f;
 #pragma unroll
     for (int c = 0; c < 32; ++c)
-        if (c < R)  // uniform
+        if (W == 3 || c < R)  // uniform
             gacc = __builtin_amdgcn_mfma_f32_16x16x1f32(k[c], k[c], gacc, 0, 0, 0);
     // register v of lane l holds block v / 4, row 4 (l / 16) + v % 4, column l % 16: four
     // consecutive rows of one column per block, stored column-major
@@ -1356,13 +1377,15 @@ hipError_t go_few32(const KernelClass &kc, const Launch &L, hipStream_t s)
 }
 
 // load width of the few-sample kernel: FP32 four columns when R % 4 == 0, BF16
-// eight when R % 8 == 0; two when R is even; else one
+// eight when R % 8 == 0; two when R is even; else one; R = 32 without masks
 template <bool BF16>
 hipError_t go_few(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.rp != 32 || kc.nmodes > 4)
         return hipErrorInvalidValue;
-    const int w = BF16 ? (kc.pairs == 3 ? 2 : kc.pairs >= 1 ? 1 : 0) : (kc.pairs >= 2 ? 2 : kc.pairs);
+    const int w = kc.pairs == 4 ? 3 : BF16 ? (kc.pairs == 3 ? 2 : kc.pairs >= 1 ? 1 : 0) : (kc.pairs >= 2 ? 2 : kc.pairs);
+    if (w == 3)
+        return go_few32<BF16, 3>(kc, L, s);
     if (w == 2)
         return go_few32<BF16, 2>(kc, L, s);
     if (w == 1)

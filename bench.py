@@ -35,11 +35,15 @@ def kernel_name(kind: str, nmodes: int, R: int, bf16: bool) -> str:
     b = "true" if bf16 else "false"
     if R <= 16:
         return {"row_items": f"k_rows16<{nmodes}, 4, {b}>", "row_chunks": f"k_chunk16<{nmodes}, 4, {b}>",
-                "row_tiny": f"k_tiny16<{nmodes}, 4, {b}>", "row_finalize": f"k_finalize16<{b}>"}[kind]
+                "row_tiny": f"k_quad16<{nmodes}, {b}, {'true' if R % 4 == 0 else 'false'}>",
+                "row_finalize": f"k_finalize16<{b}>",
+                "row_few": f"k_few16<{nmodes}, {b}, {'true' if R % 4 == 0 else 'false'}>"}[kind]
     if R <= 32:
         pairs = "true" if R % 2 == 0 else "false"
+        w = 3 if R == 32 else (2 if R % 8 == 0 else 1 if R % 2 == 0 else 0) if bf16 else \
+            (2 if R % 4 == 0 else 1 if R % 2 == 0 else 0)
         return {"row_items": f"k_rows32<{nmodes}, {b}, {pairs}>", "row_finalize": f"k_finalize32<{b}>",
-                "row_reduce": "k_reduce_slots<32>"}[kind]
+                "row_reduce": "k_reduce_slots<32>", "row_tiny": f"k_few32<{nmodes}, {b}, {w}>"}[kind]
     vec = 4 if R % 4 == 0 else 2 if R % 2 == 0 else 1
     return {"row_items": f"k_rows64<{nmodes}, {b}, {vec}>", "row_finalize": f"k_row_finalize<64, {b}>",
             "row_reduce": "k_reduce_slots<64>"}[kind]

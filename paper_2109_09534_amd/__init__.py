@@ -412,7 +412,7 @@ class Problem:
         buf = (LaunchRecord * cap)()
         cnt = ctypes.c_int32(0)
         _check(lib().ntc_profile_sweeps(self._h, nsweeps, int(bool(concurrent)), buf, cap, ctypes.byref(cnt)))
-        return [dict(kernel=("row_items", "row_finalize", "row_tiny", "row_chunks", "row_reduce")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
+        return [dict(kernel=("row_items", "row_finalize", "row_tiny", "row_chunks", "row_reduce", "row_few")[r.kernel], mode=r.mode, inner=r.inner, blocks=r.blocks,
                      samples=r.samples, rows=r.rows, ms=r.ms) for r in buf[: min(cnt.value, cap)]]
 
     def update_mode(self, mode: int):

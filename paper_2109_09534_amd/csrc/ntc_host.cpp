@@ -179,6 +179,8 @@ struct ModeState {
     int32_t n_items = 0;
     int32_t n_partial = 0;
     int32_t n_group = 0;
+    int32_t n_few = 0;                           // the last n_few whole rows of the group kernel's list
+    int64_t few_samples = 0;
     int32_t n_split = 0;
     int32_t n_slots = 0;
     int64_t samples = 0;
@@ -294,10 +296,13 @@ ntc_status alloc_or_fail(ntc_problem *h, void **dst, size_t bytes, const char *w
 
 ntc::KernelClass kernel_class(const ntc_problem *h)
 {
-    // pairs: R <= 32, a lane reads its two columns as one pair (R even); R <= 64,
-    // 2 = four columns per load (R % 4 == 0), 1 = two (R even), 0 = one
+    // pairs: how wide the loads of a factor row may be (R <= 16: 2 when R % 4 == 0;
+    // R <= 32: 4 when R == 32, 3 when R % 8 == 0, 2 when R % 4 == 0, 1 when R is
+    // even; R <= 64: 2 when R % 4 == 0, 1 when R is even; else 0)
     int32_t pairs = 0;
-    if (h->RP == 32)
+    if (h->RP == 16)
+        pairs = h->R % 4 == 0 ? 2 : 0;
+    else if (h->RP == 32)
         pairs = h->R == 32 ? 4 : h->R % 8 == 0 ? 3 : h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
     else if (h->RP == 64)
         pairs = h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
@@ -354,6 +359,7 @@ ntc::RowArgs row_args(ntc_problem *h, int mode, int l)
     a.n_items = m.n_items;
     a.n_partial = m.n_partial;
     a.n_group = m.n_group;
+    a.n_few = m.n_few;
     a.n_split = m.n_split;
     return a;
 }
@@ -382,17 +388,20 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
         // overlap = 2 keeps the one-row-per-lane rows on the main stream, ahead of the chunks.
         const bool rows_aside = kc.rp == 16 && kc.nmodes <= 4;
         const bool tiny_aside = h->overlap != 2;
-        const int32_t n_aside = (tiny_aside ? md.n_tiny : 0) + (rows_aside ? md.n_group : 0);
-        const int32_t n_main = (rows_aside ? md.n_items - md.n_group : md.n_items) + md.n_split +
+        const int32_t n_aside = (tiny_aside ? md.n_tiny : 0) + (rows_aside ? md.n_group - md.n_few : 0);
+        const int32_t n_main = (rows_aside ? md.n_items - md.n_group + md.n_few : md.n_items) + md.n_split +
                                (tiny_aside ? 0 : md.n_tiny);
         const bool fork = (!probe || probe->concurrent) && h->side && n_aside > 0 && n_main > 0;
         if (fork) {
             NTC_HIP(hipEventRecord(h->ev_fork, h->stream));
             NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         }
-        // launch order: one-row-per-lane, chunks, rows, finalize of split rows
-        for (ntc::RowKernel kern : {ntc::kTiny, ntc::kChunks, ntc::kRows, ntc::kReduce, ntc::kFinalize}) {
-            L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny, md.n_groups);
+        // launch order: one-row-per-lane, chunks, few-sample rows, rows, finalize of split rows.
+        // The few-sample rows (R <= 16) stay on the main stream after the chunks: the side
+        // stream already carries the one-row-per-lane rows and the group rows.
+        for (ntc::RowKernel kern : {ntc::kTiny, ntc::kChunks, ntc::kFew, ntc::kRows, ntc::kReduce, ntc::kFinalize}) {
+            L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny, md.n_groups,
+                                              md.n_few);
             if (L.blocks <= 0)
                 continue;
             const bool aside = (kern == ntc::kTiny && tiny_aside) || (kern == ntc::kRows && rows_aside);
@@ -414,9 +423,10 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
                 r.inner = l;
                 r.blocks = L.blocks;
                 r.samples = kern == ntc::kRows ? md.row_samples : kern == ntc::kTiny ? md.tiny_samples
-                            : kern == ntc::kChunks ? md.chunk_samples : 0;
+                            : kern == ntc::kChunks ? md.chunk_samples : kern == ntc::kFew ? md.few_samples : 0;
                 r.rows = kern == ntc::kRows ? md.row_fused : kern == ntc::kFinalize ? md.n_split
-                         : kern == ntc::kTiny ? md.n_tiny : kern == ntc::kChunks ? md.chunk_fused : 0;
+                         : kern == ntc::kTiny ? md.n_tiny : kern == ntc::kChunks ? md.chunk_fused
+                         : kern == ntc::kFew ? md.n_few : 0;
                 probe->rec.push_back(r);
             }
         }
@@ -643,7 +653,8 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
         };
         int32_t slot = 0;
         if (rp == 16) {
-            // one row per lane / one row per 16-lane group / 16 groups per row chunk
+            // one row per lane / one sample per lane / one row per 16-lane group / 16 groups per row chunk
+            const int64_t few_max = q->N <= 4 ? std::min<int64_t>(ntc::kFewB16, q->group_max) : 0;
             std::vector<Item> chunks;
             for (int32_t r : rows) {
                 const int64_t b = bsz[r];
@@ -654,8 +665,13 @@ ntc_status prepare_impl(ntc_prepared *q, int32_t N, const int64_t *dims, int64_t
                     md.tiny_samples += b;
                 } else if (b <= q->group_max) {
                     md.fused_rows += 1;
-                    md.row_fused += 1;
-                    md.row_samples += b;
+                    if (b <= few_max) {  // the tail of the list (rows come in decreasing B_p)
+                        md.n_few += 1;
+                        md.few_samples += b;
+                    } else {
+                        md.row_fused += 1;
+                        md.row_samples += b;
+                    }
                     // N <= 4: the group kernel reads these as RowItem
                     items.push_back(q->N <= 4 ? as_item(row_item(r)) : Item{r, 0, static_cast<int32_t>(b), -1});
                 } else if (b <= smax) {
@@ -905,7 +921,7 @@ ntc_status ntc::problem_view(ntc_handle h, ntc::ProblemView *v)
         const ModeState &md = h->md[m];
         for (int kind = 0; kind < ntc::kRowKernels; ++kind)
             v->blocks[m][kind] = ntc::row_kernel_blocks(static_cast<ntc::RowKernel>(kind), v->kc, md.n_items,
-                                                        md.n_group, md.n_split, md.n_tiny, md.n_groups);
+                                                        md.n_group, md.n_split, md.n_tiny, md.n_groups, md.n_few);
         v->U[m] = h->U[m];
     }
     v->n_test = h->n_test;

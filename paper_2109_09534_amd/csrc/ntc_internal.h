@@ -85,6 +85,8 @@ struct RowArgs {
     int32_t n_partial;            // (wave-per-item kernels) items [0, n_partial) write partial slots
     int32_t n_group;              // (R <= 16) items [0, n_group) are whole rows for the group kernel,
                                   // items [n_group, n_items) row chunks for the block kernel
+    int32_t n_few;                // (R <= 16, N <= 4) the last n_few whole rows, [n_group - n_few,
+                                  // n_group), have at most 16 samples: the few-sample kernel takes them
     int32_t n_split;
     int32_t n_tiny;
     int32_t n_groups;
@@ -95,6 +97,9 @@ constexpr int kTinyB = 4;
 // 17 <= R <= 32, N <= 4: rows with at most this many samples run four to a
 // wave, one per 16-lane group and one sample per lane.
 constexpr int kFewB32 = 16;
+// R <= 16, N <= 4: whole rows with tiny_max < B_p <= this many samples (and at
+// most group_max) run the same way instead of in the group kernel.
+constexpr int kFewB16 = 16;
 
 
 // One launch of a row kernel over n entries (problems).  args: [n] device
@@ -109,7 +114,8 @@ struct Launch {
 };
 
 // Kernel family of a problem: padded rank (16, 32, 64), mode count, BF16
-// gathers, and how wide the loads of a factor row may be: for R <= 32, 4 when
+// gathers, and how wide the loads of a factor row may be: for R <= 16, 2 when
+// R % 4 == 0, else 0; for R <= 32, 4 when
 // R == 32, 3 when R % 8 == 0, 2 when R % 4 == 0, 1 when R is even, else 0 (R
 // is even: a lane reads its column pair with one load); for R <= 64, 2 when
 // R % 4 == 0, 1 when R is even, else 0.
@@ -125,14 +131,16 @@ struct KernelClass {
 // one per 256-thread block; kTiny rows with B_p <= kTinyB, one per lane (one-wave blocks);
 // kFinalize combines the partial slots of split rows.  R > 16: kRows takes
 // every work item, one per wave; for 17 <= R <= 32 with N <= 4, kTiny takes
-// the rows with B_p <= kFewB32, four per one-wave block.
+// the rows with B_p <= kFewB32, four per one-wave block.  kFew (R <= 16,
+// N <= 4) takes the whole rows with kTinyB < B_p <= kFewB16, four per
+// one-wave block, one sample per lane.
 // kReduce (R > 16) sums groups of partial slots of rows split into many items.
-enum RowKernel { kRows = 0, kFinalize = 1, kTiny = 2, kChunks = 3, kReduce = 4 };
-constexpr int kRowKernels = 5;
+enum RowKernel { kRows = 0, kFinalize = 1, kTiny = 2, kChunks = 3, kReduce = 4, kFew = 5 };
+constexpr int kRowKernels = 6;
 
 // Grid blocks one problem needs for `kind`.
 int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items, int32_t n_group, int32_t n_split,
-                          int32_t n_tiny, int32_t n_groups);
+                          int32_t n_tiny, int32_t n_groups, int32_t n_few);
 hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s);
 // the R > 16 kernels (called by launch_row_kernel)
 hipError_t launch_row_kernel_wide(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s);

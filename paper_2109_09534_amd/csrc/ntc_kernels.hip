@@ -4,6 +4,7 @@
 
 #include "ntc_bf16.h"
 #include "ntc_dev.h"
+#include "ntc_few.h"
 #include "ntc_internal.h"
 #include "ntc_rng.h"
 
@@ -110,7 +111,7 @@ template <class Args>
 __device__ __forceinline__ GroupItem load_row_item(const Args &a, int id)
 {
     GroupItem g;
-    g.has = id < a.n_group;
+    g.has = id < a.n_group - a.n_few;
     RowItem ri{0, 1, 0};
     if (g.has)
         ri = a.rows[id];
@@ -832,6 +833,54 @@ __global__ __launch_bounds__(kTinyBlock) void k_tiny16(NTC_ROW_PARAMS)
         tiny_row<NM, RW, BF16, false>(a, id);
 }
 
+// Rows with 1 <= B_p <= tiny_max samples (N <= 4): sixteen per one-wave
+// block, four lanes per row and one sample per lane (ntc_few.h).  V4: R % 4 == 0
+// (the kernel class); the load width within it follows R.
+template <int NM, bool BF16, bool V4>
+__global__ __launch_bounds__(64) void k_quad16(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    if constexpr (V4) {
+        if (a.R == 16)
+            quad_rows<NM, BF16, 3>(a, a.tiny, a.n_tiny, blk_);
+        else if (!BF16 || (a.R & 7) == 0)
+            quad_rows<NM, BF16, 2>(a, a.tiny, a.n_tiny, blk_);
+        else
+            quad_rows<NM, BF16, 1>(a, a.tiny, a.n_tiny, blk_);
+    } else {
+        if ((a.R & 1) == 0)
+            quad_rows<NM, BF16, 1>(a, a.tiny, a.n_tiny, blk_);
+        else
+            quad_rows<NM, BF16, 0>(a, a.tiny, a.n_tiny, blk_);
+    }
+}
+
+// Whole rows with 5 <= B_p <= 16 samples (N <= 4): four per one-wave block,
+// one sample per lane, the power method in the span of v_0 and the sampled
+// rows (ntc_few.h).  V4: R % 4 == 0 (the kernel class); the load width
+// within it follows R, which is uniform over the block (one problem per
+// block).
+template <int NM, bool BF16, bool V4>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_few16(NTC_ROW_PARAMS)
+{
+    NTC_ROW_RESOLVE(a, blk_);
+    __shared__ FewShared sh;
+    const RowItem *list = a.rows + (a.n_group - a.n_few);
+    if constexpr (V4) {
+        if (a.R == 16)
+            few_rows<16, NM, BF16, 3>(a, list, a.n_few, blk_, sh);
+        else if (!BF16 || (a.R & 7) == 0)
+            few_rows<16, NM, BF16, 2>(a, list, a.n_few, blk_, sh);
+        else
+            few_rows<16, NM, BF16, 1>(a, list, a.n_few, blk_, sh);
+    } else {
+        if ((a.R & 1) == 0)
+            few_rows<16, NM, BF16, 1>(a, list, a.n_few, blk_, sh);
+        else
+            few_rows<16, NM, BF16, 0>(a, list, a.n_few, blk_, sh);
+    }
+}
+
 // Rows split over several items: one 256-thread block per row; its 16
 // groups sum the row's slots with a fixed stride, a fixed-order tree in LDS
 // combines them, and the first group finishes the row.
@@ -904,18 +953,45 @@ hipError_t go_rows16(const KernelClass &kc, const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
+template <bool BF16, bool V4>
+hipError_t go_quad16(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.nmodes == 3)
+        NTC_GO((k_quad16<3, BF16, V4>), 64);
+    else if (kc.nmodes == 4)
+        NTC_GO((k_quad16<4, BF16, V4>), 64);
+    else
+        NTC_GO((k_quad16<2, BF16, V4>), 64);
+    return hipGetLastError();
+}
+
 template <bool BF16>
 hipError_t go_tiny(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
-    if (kc.nmodes == 3)
-        NTC_GO((k_tiny16<3, 4, BF16>), kTinyBlock);
-    else if (kc.nmodes == 4)
-        NTC_GO((k_tiny16<4, 4, BF16>), kTinyBlock);
-    else if (kc.nmodes == 2)
-        NTC_GO((k_tiny16<2, 4, BF16>), kTinyBlock);
-    else
-        NTC_GO((k_tiny16<0, 8, BF16>), kTinyBlock);
+    if (kc.nmodes <= 4)
+        return kc.pairs ? go_quad16<BF16, true>(kc, L, s) : go_quad16<BF16, false>(kc, L, s);
+    NTC_GO((k_tiny16<0, 8, BF16>), kTinyBlock);
     return hipGetLastError();
+}
+
+template <bool BF16, bool V4>
+hipError_t go_few16v(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    if (kc.nmodes == 3)
+        NTC_GO((k_few16<3, BF16, V4>), 64);
+    else if (kc.nmodes == 4)
+        NTC_GO((k_few16<4, BF16, V4>), 64);
+    else if (kc.nmodes == 2)
+        NTC_GO((k_few16<2, BF16, V4>), 64);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <bool BF16>
+hipError_t go_few16(const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    return kc.pairs ? go_few16v<BF16, true>(kc, L, s) : go_few16v<BF16, false>(kc, L, s);
 }
 
 template <bool BF16>
@@ -944,17 +1020,19 @@ __global__ void k_advance(int64_t *k, int32_t n)
 }  // namespace
 
 int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items, int32_t n_group, int32_t n_split,
-                          int32_t n_tiny, int32_t n_groups)
+                          int32_t n_tiny, int32_t n_groups, int32_t n_few)
 {
     const bool g16 = kc.rp == 16;
     switch (kind) {
     case kRows:
-        return g16 ? (kc.nmodes > 4 ? (n_items + 3) / 4 : (n_group + 3) / 4) : n_items;
+        return g16 ? (kc.nmodes > 4 ? (n_items + 3) / 4 : (n_group - n_few + 3) / 4) : n_items;
+    case kFew:
+        return (g16 && kc.nmodes <= 4) ? (n_few + 3) / 4 : 0;
     case kFinalize:
         return n_split;
     case kTiny:
         if (g16)
-            return (n_tiny + kTinyBlock - 1) / kTinyBlock;
+            return kc.nmodes <= 4 ? (n_tiny + 15) / 16 : (n_tiny + kTinyBlock - 1) / kTinyBlock;
         return (kc.rp == 32 && kc.nmodes <= 4) ? (n_tiny + 3) / 4 : 0;
     case kChunks:
         return (g16 && kc.nmodes <= 4) ? n_items - n_group : 0;
@@ -984,6 +1062,8 @@ hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch
         return b ? go_chunks<true>(kc, L, s) : go_chunks<false>(kc, L, s);
     case kReduce:
         return hipSuccess;
+    case kFew:
+        return b ? go_few16<true>(kc, L, s) : go_few16<false>(kc, L, s);
     }
     return hipErrorInvalidValue;
 }

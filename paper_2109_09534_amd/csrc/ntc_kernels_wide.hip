@@ -17,6 +17,7 @@
 
 #include "ntc_bf16.h"
 #include "ntc_dev.h"
+#include "ntc_few.h"
 #include "ntc_internal.h"
 #include "ntc_rng.h"
 
@@ -941,375 +942,14 @@ __global__ __launch_bounds__(256) void k_reduce_slots(NTC_ROW_PARAMS)
 
 // ------------------------------------------------- rows with few samples (17 <= R <= 32)
 //
-// Rows whose minibatch has at most kFewB32 samples (most rows of a
-// long-tailed mode) run four to a one-wave block: 16-lane group b owns a row,
-// lane s of the group its sample s.  A lane gathers its sample's whole factor
-// rows, so k, k.y and the row sum of k stay in the lane.  The Gram matrix
-// G = K K^T of each row (B x B, B <= 16) comes from one
-// v_mfma_f32_16x16x1f32 per column: its four output blocks are the four
-// groups' rank-one updates by that column.  The column sums of the residual
-// terms (the sampled gradient) are a four-level DPP reduce-scatter that leaves
-// lane s with columns 2s and 2s + 1.
-//
-// The power method on H = K^T K + lambda I runs in the span of v_0 and the
-// sampled rows, v = alpha v_0 + K^T u: with c = K v_0, z = G u and
-// K v = alpha c + z,
-//   H v = (lambda alpha) v_0 + K^T (K v + lambda u),
-//   ||v||^2 = alpha^2 + u.(2 alpha c + z),   v.Hv = ||K v||^2 + lambda ||v||^2,
-// so every product is one 16-entry product by G, and the iterates, the
-// power-of-two scalings, the exit test and the Rayleigh quotient are those
-// of the R-dimensional method in exact arithmetic.
-
-// The first 32 columns of a factor row; columns >= R are zero, and a load
-// past R reads the start of the same row instead (never past the row's end).
-// W: 3 = R is 32, four FP32 or eight BF16 columns per load; 2 = four FP32 or
-// eight BF16 columns per load; 1 = two per load; 0 = one.
-template <int W>
-__device__ __forceinline__ void few_row(const float *p, int R, float (&out)[32])
-{
-    if constexpr (W == 3) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float4 t = reinterpret_cast<const float4 *>(p)[q];
-            out[4 * q] = t.x;
-            out[4 * q + 1] = t.y;
-            out[4 * q + 2] = t.z;
-            out[4 * q + 3] = t.w;
-        }
-    } else if constexpr (W == 2) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const bool in = 4 * q < R;
-            const float4 t = reinterpret_cast<const float4 *>(p)[in ? q : 0];
-            out[4 * q] = in ? t.x : 0.0f;
-            out[4 * q + 1] = in ? t.y : 0.0f;
-            out[4 * q + 2] = in ? t.z : 0.0f;
-            out[4 * q + 3] = in ? t.w : 0.0f;
-        }
-    } else if constexpr (W == 1) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const bool in = 2 * q < R;
-            const float2 t = reinterpret_cast<const float2 *>(p)[in ? q : 0];
-            out[2 * q] = in ? t.x : 0.0f;
-            out[2 * q + 1] = in ? t.y : 0.0f;
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < 32; ++c) {
-            const bool in = c < R;
-            const float t = p[in ? c : 0];
-            out[c] = in ? t : 0.0f;
-        }
-    }
-}
-
-template <int W>
-__device__ __forceinline__ void few_row(const uint16_t *p, int R, float (&out)[32])
-{
-    if constexpr (W == 3) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint4 t = reinterpret_cast<const uint4 *>(p)[q];
-            const uint32_t w[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                out[8 * q + 2 * h] = __uint_as_float(w[h] << 16);
-                out[8 * q + 2 * h + 1] = __uint_as_float(w[h] & 0xFFFF0000u);
-            }
-        }
-    } else if constexpr (W == 2) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const bool in = 8 * q < R;
-            const uint4 t = reinterpret_cast<const uint4 *>(p)[in ? q : 0];
-            const uint32_t w[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                out[8 * q + 2 * h] = in ? __uint_as_float(w[h] << 16) : 0.0f;
-                out[8 * q + 2 * h + 1] = in ? __uint_as_float(w[h] & 0xFFFF0000u) : 0.0f;
-            }
-        }
-    } else if constexpr (W == 1) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const bool in = 2 * q < R;
-            const uint32_t t = reinterpret_cast<const uint32_t *>(p)[in ? q : 0];
-            out[2 * q] = in ? __uint_as_float(t << 16) : 0.0f;
-            out[2 * q + 1] = in ? __uint_as_float(t & 0xFFFF0000u) : 0.0f;
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < 32; ++c) {
-            const bool in = c < R;
-            const uint16_t t = p[in ? c : 0];
-            out[c] = in ? bf16_to_f32(t) : 0.0f;
-        }
-    }
-}
-
-// k = the elementwise product of the sample's other-mode factor rows
-template <int NM, bool BF16, int W, class Args>
-__device__ __forceinline__ void few_k(const Args &a, const uint4 &rec, float (&k)[32])
-{
-    const uint32_t rw[3] = {rec.x, rec.y, rec.z};
-    if (BF16)
-        few_row<W>(a.gath16[0] + rw[0], a.R, k);
-    else
-        few_row<W>(a.gath[0] + rw[0], a.R, k);
-#pragma unroll
-    for (int mm = 1; mm < NM - 1; ++mm) {
-        float f[32];
-        if (BF16)
-            few_row<W>(a.gath16[mm] + rw[mm], a.R, f);
-        else
-            few_row<W>(a.gath[mm] + rw[mm], a.R, f);
-#pragma unroll
-        for (int c = 0; c < 32; ++c)
-            k[c] *= f[c];
-    }
-}
-
-// One level of the reduce-scatter over a 16-lane row: lane l keeps the upper
-// half of its N values when `hi`, else the lower half, and adds the partner's
-// copy of the half it keeps (the partner, l ^ mask with the bit of `hi`
-// flipped, keeps the other half).
-template <int CTRL, int N>
-__device__ __forceinline__ void few_rs(float (&r)[32], bool hi)
-{
-#pragma unroll
-    for (int i = 0; i < N / 2; ++i) {
-        const float keep = hi ? r[i + N / 2] : r[i];
-        const float send = hi ? r[i] : r[i + N / 2];
-        r[i] = keep + dpp_f32<CTRL>(send);
-    }
-}
-
-// Column sums over the 16 lanes of the group; lane s gets columns 2s and 2s + 1
-// in r[0] and r[1] (partners l ^ 15, l ^ 7, l ^ 3, l ^ 1 keep the column
-// halves selected by bits 3, 2, 1, 0 of s).
-__device__ __forceinline__ void few_colsum(float (&r)[32], int s)
-{
-    constexpr int kDppXor3 = 0x1B;  // quad_perm [3,2,1,0]
-    few_rs<kDppMirror, 32>(r, (s >> 3) & 1);
-    few_rs<kDppHalfMirror, 16>(r, (s >> 2) & 1);
-    few_rs<kDppXor3, 8>(r, (s >> 1) & 1);
-    few_rs<kDppXor1, 4>(r, s & 1);
-}
-
+// Rows whose minibatch has at most tiny_max (16 by default) samples, four to
+// a one-wave block, one sample per lane (ntc_few.h).
 template <int NM, bool BF16, int W>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_few32(NTC_ROW_PARAMS)
 {
-#pragma clang fp contract(off)
     NTC_ROW_RESOLVE(a, blk_);
-    __shared__ float4 s_gram[4 * 64];  // the four groups' G, column-major 16 x 16 each
-    __shared__ double2 s_u[4 * 8];     // each group's u, for the products by G
-    const int lane = threadIdx.x;
-    const int grp = lane >> 4, s = lane & 15;
-    const int id = blk_ * 4 + grp;
-    const bool has = id < a.n_tiny;
-    RowItem ri{0, 0, 0};
-    if (has)
-        ri = a.tiny[id];
-    const int R = a.R;
-    const int B = has ? static_cast<int>(minibatch_size(a.c, ri.n)) : 0;  // 1 .. kFewB32
-    // sample s: its record, or entry 0 of the records read and replaced by the zero record
-    int64_t e = 0;
-    if (s < B) {
-        const Prp prp = make_prp(static_cast<uint32_t>(ri.n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, ri.row));
-        e = ri.base + prp_index(prp, static_cast<uint32_t>(s));
-    }
-    const uint4 w = load_record4(a.records + e * 4);
-    const uint4 rec = pick4(s < B, w, make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]));
-    const float *ysrc = (a.l == 0) ? a.A : a.Y;
-    const int64_t roff = static_cast<int64_t>(ri.row) * R;
-    float y[32];
-    few_row<W>(ysrc + roff, R, y);  // (BF16 W = 2 implies R % 4 == 0, W = 1 that R is even)
-    float k[32];
-    few_k<NM, BF16, W>(a, rec, k);
-
-    // the residual of the sample, c_s = (K v_0)_s in FP64, and the Gram matrix
-    const uint32_t xw[4] = {rec.x, rec.y, rec.z, rec.w};
-    const float x = __uint_as_float(xw[NM - 1]);  // 0 for a missing sample
-    float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    double c4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int c = 0; c < 32; ++c) {
-        p4[c & 3] = fmaf(k[c], y[c], p4[c & 3]);
-        c4[c & 3] += static_cast<double>(k[c]);
-    }
-    const float res = ((p4[0] + p4[1]) + (p4[2] + p4[3])) - x;
-    const double cs = ((c4[0] + c4[1]) + (c4[2] + c4[3])) * a.v0;
-    f32x16 gacc;
-#pragma unroll
-    for (int v = 0; v < 16; ++v)
-        gacc[v] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 32; ++c)
-        if (W == 3 || c < R)  // uniform
-            gacc = __builtin_amdgcn_mfma_f32_16x16x1f32(k[c], k[c], gacc, 0, 0, 0);
-    // register v of lane l holds block v / 4, row 4 (l / 16) + v % 4, column l % 16: four
-    // consecutive rows of one column per block, stored column-major
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-        s_gram[b * 64 + (lane & 15) * 4 + (lane >> 4)] =
-            make_float4(gacc[4 * b], gacc[4 * b + 1], gacc[4 * b + 2], gacc[4 * b + 3]);
-    // the sampled gradient's column sums (FP32), lane s: columns 2s and 2s + 1
-    float gk[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c)
-        gk[c] = res * k[c];
-    few_colsum(gk, s);
-    __builtin_amdgcn_wave_barrier();
-    // row s of this group's G (column s: G is symmetric)
-    double hd[16];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float4 t = s_gram[grp * 64 + s * 4 + q];
-        hd[4 * q] = static_cast<double>(t.x);
-        hd[4 * q + 1] = static_cast<double>(t.y);
-        hd[4 * q + 2] = static_cast<double>(t.z);
-        hd[4 * q + 3] = static_cast<double>(t.w);
-    }
-
-    // the power method on (alpha, u)
-    const double lam = a.lambda;
-    const int T = a.power_iters;
-    auto gmv = [&](double uu) {  // (G u)_s
-        reinterpret_cast<double *>(s_u)[16 * grp + s] = uu;
-        __builtin_amdgcn_wave_barrier();
-        const double2 *uv = s_u + 8 * grp;
-        double z4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const double2 t = uv[q];
-            z4[(2 * q) & 3] = fma(hd[2 * q], t.x, z4[(2 * q) & 3]);
-            z4[(2 * q + 1) & 3] = fma(hd[2 * q + 1], t.y, z4[(2 * q + 1) & 3]);
-        }
-        __builtin_amdgcn_wave_barrier();
-        return (z4[0] + z4[1]) + (z4[2] + z4[3]);
-    };
-    auto norm2 = [&](double al, double u, double z) {  // ||v||^2
-        return al * al + row_sum_f64(u * (2.0 * al * cs + z));
-    };
-    double al = 1.0, u = 0.0, z = 0.0, vv = 1.0;
-    double L = -1.0;  // set when the method ends early
-    if (T > 0) {
-        al = lam;  // v_1 = H v_0 = lambda v_0 + K^T c
-        u = cs;
-        z = gmv(u);
-        double n2 = norm2(al, u, z);
-        if (!(n2 > 0.0)) {
-            L = 0.0;
-        } else {
-            const int e2 = ilogb(n2) >> 1;
-            al = ldexp(al, -e2);
-            u = ldexp(u, -e2);
-            z = ldexp(z, -e2);
-            if (T == 1) {
-                vv = ldexp(n2, -2 * e2);
-            } else {
-                double rq_prev = 0.0;
-                for (int t = 1; t < T; ++t) {
-                    const double kv = al * cs + z;  // (K v_t)_s
-                    if (!a.lp_bound && t >= 4 && (t & 1) == 0 && t + 1 < T) {
-                        double s1 = kv * kv, s2 = u * (2.0 * al * cs + z);
-                        row_sum2_f64(s1, s2);
-                        const double nv = al * al + s2;
-                        const double rq = (s1 + lam * nv) / nv;
-                        if (t >= 6 && row_all(fabs(rq - rq_prev) <= kRqConverged * rq)) {
-                            L = rq;
-                            break;
-                        }
-                        rq_prev = rq;
-                    }
-                    al = ldexp(lam * al, -e2);
-                    u = ldexp(kv + lam * u, -e2);
-                    z = gmv(u);
-                    if ((t & 31) == 0 && t + 1 < T) {
-                        n2 = norm2(al, u, z);
-                        if (!(n2 > 0.0)) {
-                            L = 0.0;
-                            break;
-                        }
-                        const int e3 = ilogb(n2) >> 1;
-                        al = ldexp(al, -e3);
-                        u = ldexp(u, -e3);
-                        z = ldexp(z, -e3);
-                    }
-                }
-                if (L < 0.0) {
-                    n2 = norm2(al, u, z);
-                    if (!(n2 > 0.0)) {
-                        L = 0.0;
-                    } else {
-                        const int e4 = ilogb(n2) >> 1;
-                        al = ldexp(al, -e4);
-                        u = ldexp(u, -e4);
-                        z = ldexp(z, -e4);
-                        vv = ldexp(n2, -2 * e4);
-                    }
-                }
-            }
-        }
-    }
-    const double kv = al * cs + z;  // K v of the final iterate
-    if (L < 0.0 && !a.lp_bound)
-        L = (row_sum_f64(kv * kv) + lam * vv) / vv;
-    // lane s: columns 2s and 2s + 1
-    const int c0 = 2 * s;
-    if (a.lp_bound) {
-        // Collatz-Wielandt bound of the final iterate: v_i = alpha v0 + (K^T u)_i,
-        // (H v)_i = (K^T K v)_i + lambda v_i, from the sample rows gathered again
-        float kk[32];
-        few_k<NM, BF16, W>(a, rec, kk);
-        float xu[32], xk[32];
-        const float uf = static_cast<float>(u), kvf = static_cast<float>(kv);
-#pragma unroll
-        for (int c = 0; c < 32; ++c) {
-            xu[c] = kk[c] * uf;
-            xk[c] = kk[c] * kvf;
-        }
-        few_colsum(xu, s);
-        few_colsum(xk, s);
-        double m = 0.0;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const double vi = al * a.v0 + static_cast<double>(xu[j]);
-            const double hv = static_cast<double>(xk[j]) + lam * vi;
-            if (c0 + j < R && vi > 0.0)
-                m = fmax(m, hv / vi);
-        }
-        if (L < 0.0)
-            L = row_max_f64(m);
-    }
-    if (!has)
-        return;
-    const bool more = a.l + 1 < a.max_inner;
-    const double sl = sqrt(L > 0.0 ? L : 0.0), sm = a.sqrt_lambda;
-    const double beta = (sl - sm) / (sl + sm);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int col = c0 + j;
-        if (col >= R)
-            continue;
-        const int64_t off = roff + col;
-        const float yc = ysrc[off];
-        const float a_prev = (a.l == 0) ? yc : a.A[off];
-        if (L > 0.0) {
-            const double g = static_cast<double>(gk[j]) + lam * static_cast<double>(yc);
-            double an = static_cast<double>(yc) - g / L;
-            an = an > 0.0 ? an : 0.0;
-            const float af = static_cast<float>(an);
-            a.A[off] = af;
-            if (BF16)
-                a.A16[off] = f32_to_bf16(af);
-            if (more)
-                a.Y[off] = static_cast<float>(an + beta * (an - static_cast<double>(a_prev)));
-        } else if (more && a.l == 0) {
-            a.Y[off] = yc;  // row skipped: Y_1 = Y_0
-        }
-    }
+    __shared__ FewShared sh;
+    few_rows<32, NM, BF16, W>(a, a.tiny, a.n_tiny, blk_, sh);
 }
 
 #define NTC_GO(KERNEL, BLOCK) \
@@ -1433,6 +1073,7 @@ hipError_t launch_row_kernel_wide(RowKernel kind, const KernelClass &kc, const L
     case kTiny:
         return b ? go_few<true>(kc, L, s) : go_few<false>(kc, L, s);
     case kChunks:
+    case kFew:
         return hipSuccess;
     }
     return hipErrorInvalidValue;

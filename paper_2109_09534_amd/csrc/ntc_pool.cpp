@@ -277,7 +277,7 @@ ntc_status rebuild(ntc_pool *pool)
     };
     std::vector<Pending> pend;
     TableImage img;
-    const ntc::RowKernel order[5] = {ntc::kTiny, ntc::kChunks, ntc::kRows, ntc::kReduce, ntc::kFinalize};
+    const ntc::RowKernel order[6] = {ntc::kTiny, ntc::kFew, ntc::kChunks, ntc::kRows, ntc::kReduce, ntc::kFinalize};
     for (int m = 0; m < maxN; ++m) {
         for (int l = 0; l < maxL; ++l) {
             for (const auto &kc : classes) {

@@ -31,7 +31,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROW_KERNEL_SOURCES = ["ntc_kernels.hip", "ntc_dev.h", "ntc_rng.h", "ntc_bf16.h", "ntc_internal.h"]
 WIDE_KERNEL_SOURCES = ["ntc_kernels_wide.hip"]
 ROW_KERNELS = ("k_rows16", "k_chunk16", "k_tiny16", "k_finalize16", "k_row_items", "k_row_finalize",
-               "k_rows16_nm", "k_rows32", "k_finalize32", "k_reduce_slots")
+               "k_rows16_nm", "k_rows32", "k_finalize32", "k_reduce_slots", "k_few16", "k_few32", "k_quad16")
 
 
 def source_hash(wide: bool = False) -> str:

@@ -176,6 +176,16 @@ CASES = {
     "cw_few_r24_zipf": lambda: (synth.c1_small(seed=18), 24, dict(c=0.1, lp_bound=1)),
     "cw_few_r31_4way_power3": lambda: (synth.make_problem((2000, 1500, 40, 16), 200_000, 12, zipf_s=1.05, seed=45),
                                        31, dict(c=0.1, lp_bound=1, power_iters=3)),
+    # R <= 16, N <= 4: whole rows with 5 <= B_p <= 16 in the same four-rows-per-wave kernel (16 columns)
+    "few16_r12_quads": lambda: (synth.c1_small(seed=21), 12, dict(c=0.1)),
+    "few16_r10_pairs": lambda: (synth.c1_small(seed=22), 10, dict(c=0.1, max_inner=2)),
+    "few16_r7_odd": lambda: (synth.c1_small(seed=23), 7, dict(c=0.1)),
+    "few16_r14_4way": lambda: (synth.make_problem((2000, 1500, 40, 16), 200_000, 12, zipf_s=1.05, seed=48), 14,
+                               dict(c=0.1)),
+    "few16_r16_matrix_zipf": lambda: (synth.make_problem((3000, 2000), 60_000, 8, seed=49, zipf_s=1.1), 16,
+                                      dict(c=0.2)),
+    "few16_group_max_8": lambda: (synth.c1_small(seed=24), 16, dict(c=0.1, schedule={"group_max": 8})),
+    "cw_few16_r16_power3": lambda: (synth.c1_small(seed=25), 16, dict(c=0.1, lp_bound=1, power_iters=3)),
 }
 
 
@@ -259,6 +269,8 @@ BF16_CASES = {
     "few_r30_4way_bf16_pairs": lambda: (synth.make_problem((2000, 1500, 40, 16), 200_000, 12, zipf_s=1.05, seed=47),
                                         30, dict(c=0.1)),
     "few_r19_odd_bf16": lambda: (synth.c1_small(seed=20), 19, dict(c=0.1)),
+    "few16_r12_bf16_pairs": lambda: (synth.c1_small(seed=26), 12, dict(c=0.1)),
+    "few16_r9_odd_bf16": lambda: (synth.c1_small(seed=27), 9, dict(c=0.1)),
 }
 
 

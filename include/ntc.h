@@ -62,8 +62,10 @@ typedef struct ntc_params {
     uint64_t seed;        /* Philox key of the minibatch sampler and the default init */
     int32_t gather_bf16;  /* 1: gather other-mode factor rows from a BF16 shadow copy
                              (FP32 master factors, FP32 accumulation) */
-    int32_t tiny_max;     /* schedule: rows with 1 <= B_p <= tiny_max run one row per lane
-                             (R <= 16 only); -1 = default (4), 0 = off, at most 4 */
+    int32_t tiny_max;     /* schedule: rows with 1 <= B_p <= tiny_max run several rows per
+                             wave, one sample per lane: R <= 16 (four lanes per row; -1 =
+                             default 4, at most 4) and 17 <= R <= 32 with nmodes <= 4 (16
+                             lanes per row; -1 = default 16, at most 16); 0 = off */
     int64_t n_test;             /* optional held-out entries for ntc_loss (0 = none) */
     const int32_t *test_coords; /* [n_test][nmodes], host, copied */
     const float *test_values;   /* [n_test], host, copied */

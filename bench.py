@@ -707,9 +707,14 @@ def _oracle_plateau(items, cpu_threads=0, W=5, tol=1e-4, cap=500):
         o = O.Oracle(p.dims, p.coords, p.values, R, c=0.1, lam=1e-3, seed=sd, test_coords=p.test_coords,
                      test_values=p.test_values)
         hist = [o.loss()[2]]
+        t_log = time.time()
         while _stop_at(hist, W, tol, cap) is None:
             o.sweep(1)
             hist.append(o.loss()[2])
+            if time.time() - t_log > 30.0:  # a long oracle run reports its progress
+                t_log = time.time()
+                log(f"oracle {len(out) + 1}/{len(items)}: {p.nnz} entries, sweep {len(hist) - 1}, "
+                    f"test RMSE {hist[-1]:.6f}")
         o.close()
         out.append((float(hist[-1]), len(hist) - 1))
         log(f"oracle {len(out)}/{len(items)}: {p.nnz} entries, R={R}: plateau at sweep {len(hist) - 1}, "

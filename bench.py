@@ -30,22 +30,26 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def kernel_name(kind: str, nmodes: int, R: int, bf16: bool) -> str:
+CACHED_RECORD_BYTES = 256 << 20  # records (all modes) above this are loaded non-temporally
+
+
+def kernel_name(kind: str, nmodes: int, R: int, bf16: bool, nnz: int) -> str:
     """The kernel rocprofv3 reports for one of profile_sweep's launch kinds (N <= 4)."""
     b = "true" if bf16 else "false"
+    nt = "true" if nnz * 16 * nmodes > CACHED_RECORD_BYTES else "false"
     if R <= 16:
-        return {"row_items": f"k_rows16<{nmodes}, 4, {b}>", "row_chunks": f"k_chunk16<{nmodes}, 4, {b}>",
-                "row_tiny": f"k_quad16<{nmodes}, {b}, {'true' if R % 4 == 0 else 'false'}>",
-                "row_finalize": f"k_finalize16<{b}>",
-                "row_few": f"k_few16<{nmodes}, {b}, {'true' if R % 4 == 0 else 'false'}>"}[kind]
+        v4 = "true" if R % 4 == 0 else "false"
+        return {"row_items": f"k_rows16<{nmodes}, 4, {b}, {nt}>", "row_chunks": f"k_chunk16<{nmodes}, 4, {b}, {nt}>",
+                "row_tiny": f"k_quad16<{nmodes}, {b}, {v4}, {nt}>", "row_finalize": f"k_finalize16<{b}>",
+                "row_few": f"k_few16<{nmodes}, {b}, {v4}, {nt}>"}[kind]
     if R <= 32:
         pairs = "true" if R % 2 == 0 else "false"
         w = 3 if R == 32 else (2 if R % 8 == 0 else 1 if R % 2 == 0 else 0) if bf16 else \
             (2 if R % 4 == 0 else 1 if R % 2 == 0 else 0)
-        return {"row_items": f"k_rows32<{nmodes}, {b}, {pairs}>", "row_finalize": f"k_finalize32<{b}>",
-                "row_reduce": "k_reduce_slots<32>", "row_tiny": f"k_few32<{nmodes}, {b}, {w}>"}[kind]
+        return {"row_items": f"k_rows32<{nmodes}, {b}, {pairs}, {nt}>", "row_finalize": f"k_finalize32<{b}>",
+                "row_reduce": "k_reduce_slots<32>", "row_tiny": f"k_few32<{nmodes}, {b}, {w}, {nt}>"}[kind]
     vec = 4 if R % 4 == 0 else 2 if R % 2 == 0 else 1
-    return {"row_items": f"k_rows64<{nmodes}, {b}, {vec}>", "row_finalize": f"k_row_finalize<64, {b}>",
+    return {"row_items": f"k_rows64<{nmodes}, {b}, {vec}, {nt}>", "row_finalize": f"k_row_finalize<64, {b}>",
             "row_reduce": "k_reduce_slots<64>"}[kind]
 
 
@@ -218,12 +222,12 @@ def main():
     avg_ms = kd["ms"] / kd["launches"]
     bytes_per_launch = kd["bytes"] / kd["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kfile = kernel_name(dom, p.nmodes, R, args.bf16).split("<")[0]
+    kfile = kernel_name(dom, p.nmodes, R, args.bf16, p.nnz).split("<")[0]
     traffic_rec = load_traffic(f"{kfile}_{args.workload}{'_bf16' if args.bf16 else ''}_traffic.json")
     traffic = traffic_rec["hbm_bytes_per_launch"] if traffic_rec else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kernel_name(dom, p.nmodes, R, args.bf16), "avg_launch_ms": round(avg_ms, 4),
+                "kernel": kernel_name(dom, p.nmodes, R, args.bf16, p.nnz), "avg_launch_ms": round(avg_ms, 4),
                 "launches_per_sweep": kd["launches"] // max(args.steps, 1),
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
                 "sweep_share": round(kd["ms"] / sum(v["ms"] for v in per_kernel.values()), 3)}

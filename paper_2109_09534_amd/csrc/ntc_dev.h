@@ -30,13 +30,22 @@ typedef const __attribute__((address_space(4))) RowArgs CRowArgs;
     if (a.stop != nullptr && *a.stop != 0)                   \
         return
 
-// A 16-byte record, loaded non-temporally: each sampled record is read once
-// per sweep, so its line is marked to leave the L2 first and the factor rows
-// that the gathers reuse stay cached longer.
+// A 16-byte record.  NT (the problem's records are larger than the GPU's
+// last-level cache): each sampled record is read once per sweep, so it is
+// loaded non-temporally; its line is marked to leave the caches first and the
+// factor rows that the gathers reuse stay cached longer.  A smaller record
+// set stays cached from one sweep to the next and loads normally.  (A
+// runtime choice between the two loads is merged by the compiler into one
+// load without the hint, so the choice is a template parameter.)
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+template <bool NT>
 __device__ __forceinline__ uint4 load_record4(const uint32_t *p)
 {
-    const u32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    u32x4_t t;
+    if constexpr (NT)
+        t = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    else
+        t = *reinterpret_cast<const u32x4_t *>(p);
     return make_uint4(t.x, t.y, t.z, t.w);
 }
 

@@ -155,7 +155,7 @@ struct FewShared {
 };
 
 // Rows list[0 .. count) of one problem; this wave takes rows 4 blk .. 4 blk + 3.
-template <int C, int NM, bool BF16, int W, class Args>
+template <int C, int NM, bool BF16, int W, bool NT, class Args>
 __device__ __forceinline__ void few_rows(const Args &a, const RowItem *list, int count, int blk, FewShared &sh)
 {
 #pragma clang fp contract(off)
@@ -175,7 +175,7 @@ __device__ __forceinline__ void few_rows(const Args &a, const RowItem *list, int
         const Prp prp = make_prp(static_cast<uint32_t>(ri.n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, ri.row));
         e = ri.base + prp_index(prp, static_cast<uint32_t>(s));
     }
-    const uint4 w = load_record4(a.records + e * 4);
+    const uint4 w = load_record4<NT>(a.records + e * 4);
     const uint4 rec = pick4(s < B, w, make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const int64_t roff = static_cast<int64_t>(ri.row) * R;
@@ -430,7 +430,7 @@ __device__ __forceinline__ void quad_colsum(float (&r)[16], int s)
 
 // Rows list[0 .. count) of one problem with at most 4 samples each; this wave
 // takes rows 16 blk .. 16 blk + 15.
-template <int NM, bool BF16, int W, class Args>
+template <int NM, bool BF16, int W, bool NT, class Args>
 __device__ __forceinline__ void quad_rows(const Args &a, const RowItem *list, int count, int blk)
 {
 #pragma clang fp contract(off)
@@ -449,7 +449,7 @@ __device__ __forceinline__ void quad_rows(const Args &a, const RowItem *list, in
         const Prp prp = make_prp(static_cast<uint32_t>(ri.n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, ri.row));
         e = ri.base + prp_index(prp, static_cast<uint32_t>(s));
     }
-    const uint4 w = load_record4(a.records + e * 4);
+    const uint4 w = load_record4<NT>(a.records + e * 4);
     const uint4 rec = pick4(s < B, w, make_uint4(a.zrec[0], a.zrec[1], a.zrec[2], a.zrec[3]));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const int64_t roff = static_cast<int64_t>(ri.row) * R;

@@ -306,7 +306,8 @@ ntc::KernelClass kernel_class(const ntc_problem *h)
         pairs = h->R == 32 ? 4 : h->R % 8 == 0 ? 3 : h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
     else if (h->RP == 64)
         pairs = h->R % 4 == 0 ? 2 : h->R % 2 == 0 ? 1 : 0;
-    return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0, pairs};
+    const int32_t nt = h->nnz * h->rw * 4 * h->N > ntc::kCachedRecordBytes ? 1 : 0;
+    return ntc::KernelClass{h->RP, h->N, h->bf16 ? 1 : 0, pairs, nt};
 }
 
 ntc::RowArgs row_args(ntc_problem *h, int mode, int l)

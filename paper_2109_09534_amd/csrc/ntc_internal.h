@@ -92,6 +92,11 @@ struct RowArgs {
     int32_t n_groups;
 };
 
+// Records of a problem (all modes) up to this many bytes stay in the GPU's
+// last-level cache (256 MB on MI355X) from one sweep to the next; larger
+// record sets are loaded non-temporally.
+constexpr int64_t kCachedRecordBytes = int64_t(256) << 20;
+
 // Rows whose minibatch has at most this many samples run one row per lane (R <= 16).
 constexpr int kTinyB = 4;
 // 17 <= R <= 32, N <= 4: rows with at most this many samples run four to a
@@ -124,6 +129,7 @@ struct KernelClass {
     int32_t nmodes;
     int32_t bf16;
     int32_t pairs;
+    int32_t nt;  // 1: records loaded non-temporally (the problem's records exceed kCachedRecordBytes)
 };
 
 // The row kernels.  R <= 16: kRows takes whole rows with B_p <= group_max, one

@@ -147,7 +147,7 @@ __device__ __forceinline__ GroupItem load_group_item(const Args &a, int id)
 // stage_record puts the zero record in its place.  With no load under a
 // branch the compiler can count the loads in flight, so a later wait for
 // older loads leaves this one outstanding.
-template <int RW, class Args>
+template <int RW, bool NT, class Args>
 __device__ __forceinline__ bool fetch_record(const Args &a, const GroupItem &g, int jb, int r, uint4 &w0,
                                              uint4 &w1)
 {
@@ -156,8 +156,8 @@ __device__ __forceinline__ bool fetch_record(const Args &a, const GroupItem &g, 
     if (live)
         e = g.base + prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r));
     const uint32_t *src = a.records + e * RW;
-    w0 = load_record4(src);
-    w1 = (RW == 8) ? load_record4(src + 4) : w0;
+    w0 = load_record4<NT>(src);
+    w1 = (RW == 8) ? load_record4<NT>(src + 4) : w0;
     return live;
 }
 
@@ -201,7 +201,7 @@ __device__ __forceinline__ void gather_batch(const Args &a, const uint32_t *srec
 // batch loop is software-pipelined: while batch b is reduced, the factor
 // gathers of batch b+1 and the record fetches of batch b+2 are in flight
 // (records double-buffered in LDS, gathered values held raw until used).
-template <int NM, int RW, bool BF16>
+template <int NM, int RW, bool BF16, bool NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_rows16(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
         // both batches' records in flight together; batch 1 is staged after
         // batch 0's gathers are issued (all zero records when nb == 1)
         uint4 v0, v1;
-        const bool l0 = fetch_record<RW>(a, g, 0, r, w0, w1);
-        const bool l1 = fetch_record<RW>(a, g, 16, r, v0, v1);
+        const bool l0 = fetch_record<RW, NT>(a, g, 0, r, w0, w1);
+        const bool l1 = fetch_record<RW, NT>(a, g, 16, r, v0, v1);
         stage_record<RW>(a, s_rec[0], lane, l0, w0, w1);
         gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(s_rec[0]) + grp * 16 * RW, rr, f);
         stage_record<RW>(a, s_rec[1], lane, l1, v0, v1);
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
         // issue order: records of batch b+2, then gathers of batch b+1, so
         // that staging the records later waits only for the record loads
         // (fetched in every iteration: past the end they are zero records)
-        const bool lv2 = fetch_record<RW>(a, g, jb + 32, r, w0, w1);
+        const bool lv2 = fetch_record<RW, NT>(a, g, jb + 32, r, w0, w1);
         if (bi + 1 < nb)
             gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(s_rec[(bi + 1) & 1]) + grp * 16 * RW,
                                        rr, f);
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
 // H[4*(l/16) + v][l%16].  The four waves' FP64 sums and the 16 groups'
 // gradients are combined in LDS in a fixed order; a chunk that is the whole
 // row finishes it in place, otherwise it writes a partial slot.
-template <int NM, int RW, bool BF16>
+template <int NM, int RW, bool BF16, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_chunk16(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
@@ -351,8 +351,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
     uint4 *rb1 = s_rec[wave][1];
     if (nit > 0) {
         uint4 v0, v1;
-        const bool l0 = fetch_record<RW>(a, g, 16 * G, r, w0, w1);
-        const bool l1 = fetch_record<RW>(a, g, 16 * (G + 16), r, v0, v1);
+        const bool l0 = fetch_record<RW, NT>(a, g, 16 * G, r, w0, w1);
+        const bool l1 = fetch_record<RW, NT>(a, g, 16 * (G + 16), r, v0, v1);
         stage_record<RW>(a, rb0, lane, l0, w0, w1);
         gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(rb0) + grp * 16 * RW, rr, f);
         stage_record<RW>(a, rb1, lane, l1, v0, v1);
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
                 k *= f[mm][t];
             kc[t] = rlive ? k : 0.0f;  // a missing sample gathered the zero rows
         }
-        const bool lv2 = fetch_record<RW>(a, g, 16 * (G + 16 * (i + 2)), r, w0, w1);
+        const bool lv2 = fetch_record<RW, NT>(a, g, 16 * (G + 16 * (i + 2)), r, w0, w1);
         if (i + 1 < nit)
             gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>((i & 1) ? rb0 : rb1) + grp * 16 * RW,
                                        rr, f);
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
 // Items of the group kernels for 5 <= N <= 8 (32-byte records): the same
 // computation without the software pipeline; the Khatri-Rao product is
 // accumulated over a runtime mode loop.
-template <bool BF16>
+template <bool BF16, bool NT>
 __global__ __launch_bounds__(64) void k_rows16_nm(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(64) void k_rows16_nm(NTC_ROW_PARAMS)
         const int cnt = min(16, max(0, g.len - jb));
         const int tmax = min(16, maxlen - jb);
         uint4 w0, w1;
-        const bool lv = fetch_record<8>(a, g, jb, r, w0, w1);
+        const bool lv = fetch_record<8, NT>(a, g, jb, r, w0, w1);
         stage_record<8>(a, s_rec, lane, lv, w0, w1);
         const uint32_t *srec = reinterpret_cast<const uint32_t *>(s_rec) + grp * 16 * 8;
         float kp[16];
@@ -586,7 +586,7 @@ __device__ __forceinline__ void load_row16(const uint16_t *p, int R, float (&out
     }
 }
 
-template <int NM, int RW, bool BF16, bool V4>
+template <int NM, int RW, bool BF16, bool V4, bool NT>
 __device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
 {
     const int nm = (NM > 0) ? NM : a.nmodes;
@@ -619,7 +619,7 @@ __device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
         const uint32_t *src = a.records + at[j] * RW;
 #pragma unroll
         for (int w4 = 0; w4 < RW / 4; ++w4) {
-            const uint4 t = load_record4(src + 4 * w4);
+            const uint4 t = load_record4<NT>(src + 4 * w4);
             rec[j][4 * w4] = t.x;
             rec[j][4 * w4 + 1] = t.y;
             rec[j][4 * w4 + 2] = t.z;
@@ -819,7 +819,7 @@ __device__ __forceinline__ void tiny_row(CRowArgs &a, int id)
 // running concurrently.
 constexpr int kTinyBlock = 64;
 
-template <int NM, int RW, bool BF16>
+template <int NM, int RW, bool BF16, bool NT>
 __global__ __launch_bounds__(kTinyBlock) void k_tiny16(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
@@ -828,30 +828,30 @@ __global__ __launch_bounds__(kTinyBlock) void k_tiny16(NTC_ROW_PARAMS)
         return;
     // R % 4 is uniform over the block (one problem per block)
     if ((a.R & 3) == 0)
-        tiny_row<NM, RW, BF16, true>(a, id);
+        tiny_row<NM, RW, BF16, true, NT>(a, id);
     else
-        tiny_row<NM, RW, BF16, false>(a, id);
+        tiny_row<NM, RW, BF16, false, NT>(a, id);
 }
 
 // Rows with 1 <= B_p <= tiny_max samples (N <= 4): sixteen per one-wave
 // block, four lanes per row and one sample per lane (ntc_few.h).  V4: R % 4 == 0
 // (the kernel class); the load width within it follows R.
-template <int NM, bool BF16, bool V4>
+template <int NM, bool BF16, bool V4, bool NT>
 __global__ __launch_bounds__(64) void k_quad16(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
     if constexpr (V4) {
         if (a.R == 16)
-            quad_rows<NM, BF16, 3>(a, a.tiny, a.n_tiny, blk_);
+            quad_rows<NM, BF16, 3, NT>(a, a.tiny, a.n_tiny, blk_);
         else if (!BF16 || (a.R & 7) == 0)
-            quad_rows<NM, BF16, 2>(a, a.tiny, a.n_tiny, blk_);
+            quad_rows<NM, BF16, 2, NT>(a, a.tiny, a.n_tiny, blk_);
         else
-            quad_rows<NM, BF16, 1>(a, a.tiny, a.n_tiny, blk_);
+            quad_rows<NM, BF16, 1, NT>(a, a.tiny, a.n_tiny, blk_);
     } else {
         if ((a.R & 1) == 0)
-            quad_rows<NM, BF16, 1>(a, a.tiny, a.n_tiny, blk_);
+            quad_rows<NM, BF16, 1, NT>(a, a.tiny, a.n_tiny, blk_);
         else
-            quad_rows<NM, BF16, 0>(a, a.tiny, a.n_tiny, blk_);
+            quad_rows<NM, BF16, 0, NT>(a, a.tiny, a.n_tiny, blk_);
     }
 }
 
@@ -860,7 +860,7 @@ __global__ __launch_bounds__(64) void k_quad16(NTC_ROW_PARAMS)
 // rows (ntc_few.h).  V4: R % 4 == 0 (the kernel class); the load width
 // within it follows R, which is uniform over the block (one problem per
 // block).
-template <int NM, bool BF16, bool V4>
+template <int NM, bool BF16, bool V4, bool NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_few16(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
@@ -868,16 +868,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const RowItem *list = a.rows + (a.n_group - a.n_few);
     if constexpr (V4) {
         if (a.R == 16)
-            few_rows<16, NM, BF16, 3>(a, list, a.n_few, blk_, sh);
+            few_rows<16, NM, BF16, 3, NT>(a, list, a.n_few, blk_, sh);
         else if (!BF16 || (a.R & 7) == 0)
-            few_rows<16, NM, BF16, 2>(a, list, a.n_few, blk_, sh);
+            few_rows<16, NM, BF16, 2, NT>(a, list, a.n_few, blk_, sh);
         else
-            few_rows<16, NM, BF16, 1>(a, list, a.n_few, blk_, sh);
+            few_rows<16, NM, BF16, 1, NT>(a, list, a.n_few, blk_, sh);
     } else {
         if ((a.R & 1) == 0)
-            few_rows<16, NM, BF16, 1>(a, list, a.n_few, blk_, sh);
+            few_rows<16, NM, BF16, 1, NT>(a, list, a.n_few, blk_, sh);
         else
-            few_rows<16, NM, BF16, 0>(a, list, a.n_few, blk_, sh);
+            few_rows<16, NM, BF16, 0, NT>(a, list, a.n_few, blk_, sh);
     }
 }
 
@@ -939,70 +939,70 @@ __global__ __launch_bounds__(256) void k_finalize16(NTC_ROW_PARAMS)
 #define NTC_GO(KERNEL, BLOCK) \
     hipLaunchKernelGGL(KERNEL, dim3(L.blocks), dim3(BLOCK), 0, s, L.args, L.start, L.owner, L.n)
 
-template <bool BF16>
+template <bool BF16, bool NT>
 hipError_t go_rows16(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_rows16<3, 4, BF16>), 64);
+        NTC_GO((k_rows16<3, 4, BF16, NT>), 64);
     else if (kc.nmodes == 4)
-        NTC_GO((k_rows16<4, 4, BF16>), 64);
+        NTC_GO((k_rows16<4, 4, BF16, NT>), 64);
     else if (kc.nmodes == 2)
-        NTC_GO((k_rows16<2, 4, BF16>), 64);
+        NTC_GO((k_rows16<2, 4, BF16, NT>), 64);
     else
-        NTC_GO((k_rows16_nm<BF16>), 64);
+        NTC_GO((k_rows16_nm<BF16, NT>), 64);
     return hipGetLastError();
 }
 
-template <bool BF16, bool V4>
+template <bool BF16, bool V4, bool NT>
 hipError_t go_quad16(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_quad16<3, BF16, V4>), 64);
+        NTC_GO((k_quad16<3, BF16, V4, NT>), 64);
     else if (kc.nmodes == 4)
-        NTC_GO((k_quad16<4, BF16, V4>), 64);
+        NTC_GO((k_quad16<4, BF16, V4, NT>), 64);
     else
-        NTC_GO((k_quad16<2, BF16, V4>), 64);
+        NTC_GO((k_quad16<2, BF16, V4, NT>), 64);
     return hipGetLastError();
 }
 
-template <bool BF16>
+template <bool BF16, bool NT>
 hipError_t go_tiny(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes <= 4)
-        return kc.pairs ? go_quad16<BF16, true>(kc, L, s) : go_quad16<BF16, false>(kc, L, s);
-    NTC_GO((k_tiny16<0, 8, BF16>), kTinyBlock);
+        return kc.pairs ? go_quad16<BF16, true, NT>(kc, L, s) : go_quad16<BF16, false, NT>(kc, L, s);
+    NTC_GO((k_tiny16<0, 8, BF16, NT>), kTinyBlock);
     return hipGetLastError();
 }
 
-template <bool BF16, bool V4>
+template <bool BF16, bool V4, bool NT>
 hipError_t go_few16v(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_few16<3, BF16, V4>), 64);
+        NTC_GO((k_few16<3, BF16, V4, NT>), 64);
     else if (kc.nmodes == 4)
-        NTC_GO((k_few16<4, BF16, V4>), 64);
+        NTC_GO((k_few16<4, BF16, V4, NT>), 64);
     else if (kc.nmodes == 2)
-        NTC_GO((k_few16<2, BF16, V4>), 64);
+        NTC_GO((k_few16<2, BF16, V4, NT>), 64);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-template <bool BF16>
+template <bool BF16, bool NT>
 hipError_t go_few16(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
-    return kc.pairs ? go_few16v<BF16, true>(kc, L, s) : go_few16v<BF16, false>(kc, L, s);
+    return kc.pairs ? go_few16v<BF16, true, NT>(kc, L, s) : go_few16v<BF16, false, NT>(kc, L, s);
 }
 
-template <bool BF16>
+template <bool BF16, bool NT>
 hipError_t go_chunks(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_chunk16<3, 4, BF16>), 256);
+        NTC_GO((k_chunk16<3, 4, BF16, NT>), 256);
     else if (kc.nmodes == 4)
-        NTC_GO((k_chunk16<4, 4, BF16>), 256);
+        NTC_GO((k_chunk16<4, 4, BF16, NT>), 256);
     else if (kc.nmodes == 2)
-        NTC_GO((k_chunk16<2, 4, BF16>), 256);
+        NTC_GO((k_chunk16<2, 4, BF16, NT>), 256);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1042,30 +1042,40 @@ int32_t row_kernel_blocks(RowKernel kind, const KernelClass &kc, int32_t n_items
     return 0;
 }
 
+namespace {
+
+template <bool NT>
+hipError_t launch_row16(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    const bool b = kc.bf16 != 0;
+    switch (kind) {
+    case kRows:
+        return b ? go_rows16<true, NT>(kc, L, s) : go_rows16<false, NT>(kc, L, s);
+    case kFinalize:
+        hipLaunchKernelGGL(b ? k_finalize16<true> : k_finalize16<false>, dim3(L.blocks), dim3(256), 0, s, L.args,
+                           L.start, L.owner, L.n);
+        return hipGetLastError();
+    case kTiny:
+        return b ? go_tiny<true, NT>(kc, L, s) : go_tiny<false, NT>(kc, L, s);
+    case kChunks:
+        return b ? go_chunks<true, NT>(kc, L, s) : go_chunks<false, NT>(kc, L, s);
+    case kReduce:
+        return hipSuccess;
+    case kFew:
+        return b ? go_few16<true, NT>(kc, L, s) : go_few16<false, NT>(kc, L, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
 hipError_t launch_row_kernel(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (L.blocks <= 0 || L.n <= 0)
         return hipSuccess;
     if (kc.rp != 16)
         return launch_row_kernel_wide(kind, kc, L, s);
-    const bool b = kc.bf16 != 0;
-    switch (kind) {
-    case kRows:
-        return b ? go_rows16<true>(kc, L, s) : go_rows16<false>(kc, L, s);
-    case kFinalize:
-        hipLaunchKernelGGL(b ? k_finalize16<true> : k_finalize16<false>, dim3(L.blocks), dim3(256), 0, s, L.args,
-                           L.start, L.owner, L.n);
-        return hipGetLastError();
-    case kTiny:
-        return b ? go_tiny<true>(kc, L, s) : go_tiny<false>(kc, L, s);
-    case kChunks:
-        return b ? go_chunks<true>(kc, L, s) : go_chunks<false>(kc, L, s);
-    case kReduce:
-        return hipSuccess;
-    case kFew:
-        return b ? go_few16<true>(kc, L, s) : go_few16<false>(kc, L, s);
-    }
-    return hipErrorInvalidValue;
+    return kc.nt ? launch_row16<true>(kind, kc, L, s) : launch_row16<false>(kind, kc, L, s);
 }
 
 hipError_t launch_advance(int64_t *k, int32_t n, hipStream_t s)

@@ -77,7 +77,7 @@ __device__ void finish_row(const Args &a, int row, int lane, double g, double (&
     }
 }
 
-template <int RP, int NM, bool BF16>
+template <int RP, int NM, bool BF16, bool NT>
 __global__ __launch_bounds__(64) void k_row_items(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
@@ -115,13 +115,13 @@ __global__ __launch_bounds__(64) void k_row_items(NTC_ROW_PARAMS)
         if (lane < cnt) {
             const uint32_t q = prp_index(prp, static_cast<uint32_t>(jb + lane));
             const uint32_t *src = a.records + (base + q) * rw;
-            const uint4 w0 = load_record4(src);
+            const uint4 w0 = load_record4<NT>(src);
             s_rec[lane * 8 + 0] = w0.x;
             s_rec[lane * 8 + 1] = w0.y;
             s_rec[lane * 8 + 2] = w0.z;
             s_rec[lane * 8 + 3] = w0.w;
             if (rw == 8) {
-                const uint4 w1 = load_record4(src + 4);
+                const uint4 w1 = load_record4<NT>(src + 4);
                 s_rec[lane * 8 + 4] = w1.x;
                 s_rec[lane * 8 + 5] = w1.y;
                 s_rec[lane * 8 + 6] = w1.z;
@@ -392,7 +392,7 @@ __device__ void finish_row32(const Args &a, int row, int lane, int col, double g
     }
 }
 
-template <int NM, bool BF16, bool PAIRS>
+template <int NM, bool BF16, bool PAIRS, bool NT>
 // Five waves per SIMD: at most 96 registers, no spills, with the 8 KB of
 // LDS below that is 20 waves per CU.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_rows32(NTC_ROW_PARAMS)
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
         int64_t e = 0;
         if (live)
             e = base + prp_index(prp, static_cast<uint32_t>(jb + lane));
-        return load_record4(a.records + e * 4);
+        return load_record4<NT>(a.records + e * 4);
     };
     // gathers of the four steps from s0 of a staged block
     auto issue = [&](const uint4 *buf, int s0, Sub &S) {
@@ -644,7 +644,7 @@ __device__ __forceinline__ int blk64(int q1, int q2)
     return q1 * 4 - (q1 * (q1 - 1)) / 2 + (q2 - q1);
 }
 
-template <int NM, bool BF16, int VEC>
+template <int NM, bool BF16, int VEC, bool NT>
 __global__ __launch_bounds__(64) void k_rows64(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(64) void k_rows64(NTC_ROW_PARAMS)
         int64_t e = 0;
         if (lv)
             e = base + prp_index(prp, static_cast<uint32_t>(jb + lane));
-        return load_record4(a.records + e * 4);
+        return load_record4<NT>(a.records + e * 4);
     };
     // gathers of the two steps from s0 of a staged block
     auto issue = [&](const uint4 *buf, int s0, Sub &S) {
@@ -944,93 +944,93 @@ __global__ __launch_bounds__(256) void k_reduce_slots(NTC_ROW_PARAMS)
 //
 // Rows whose minibatch has at most tiny_max (16 by default) samples, four to
 // a one-wave block, one sample per lane (ntc_few.h).
-template <int NM, bool BF16, int W>
+template <int NM, bool BF16, int W, bool NT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_few32(NTC_ROW_PARAMS)
 {
     NTC_ROW_RESOLVE(a, blk_);
     __shared__ FewShared sh;
-    few_rows<32, NM, BF16, W>(a, a.tiny, a.n_tiny, blk_, sh);
+    few_rows<32, NM, BF16, W, NT>(a, a.tiny, a.n_tiny, blk_, sh);
 }
 
 #define NTC_GO(KERNEL, BLOCK) \
     hipLaunchKernelGGL(KERNEL, dim3(L.blocks), dim3(BLOCK), 0, s, L.args, L.start, L.owner, L.n)
 
-template <bool BF16, bool PAIRS>
+template <bool BF16, bool PAIRS, bool NT>
 hipError_t go_rows32(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_rows32<3, BF16, PAIRS>), 64);
+        NTC_GO((k_rows32<3, BF16, PAIRS, NT>), 64);
     else if (kc.nmodes == 4)
-        NTC_GO((k_rows32<4, BF16, PAIRS>), 64);
+        NTC_GO((k_rows32<4, BF16, PAIRS, NT>), 64);
     else
-        NTC_GO((k_rows32<2, BF16, PAIRS>), 64);
+        NTC_GO((k_rows32<2, BF16, PAIRS, NT>), 64);
     return hipGetLastError();
 }
 
-template <bool BF16, int VEC>
+template <bool BF16, int VEC, bool NT>
 hipError_t go_rows64(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_rows64<3, BF16, VEC>), 64);
+        NTC_GO((k_rows64<3, BF16, VEC, NT>), 64);
     else if (kc.nmodes == 4)
-        NTC_GO((k_rows64<4, BF16, VEC>), 64);
+        NTC_GO((k_rows64<4, BF16, VEC, NT>), 64);
     else
-        NTC_GO((k_rows64<2, BF16, VEC>), 64);
+        NTC_GO((k_rows64<2, BF16, VEC, NT>), 64);
     return hipGetLastError();
 }
 
-template <bool BF16>
+template <bool BF16, bool NT>
 hipError_t go_rows(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.rp == 32) {
         if (kc.nmodes > 4)
-            NTC_GO((k_row_items<32, 0, BF16>), 64);
+            NTC_GO((k_row_items<32, 0, BF16, NT>), 64);
         else if (kc.pairs)
-            return go_rows32<BF16, true>(kc, L, s);
+            return go_rows32<BF16, true, NT>(kc, L, s);
         else
-            return go_rows32<BF16, false>(kc, L, s);
+            return go_rows32<BF16, false, NT>(kc, L, s);
     } else if (kc.rp == 64) {
         if (kc.nmodes > 4)
-            NTC_GO((k_row_items<64, 0, BF16>), 64);
+            NTC_GO((k_row_items<64, 0, BF16, NT>), 64);
         else if (kc.pairs == 2)
-            return go_rows64<BF16, 4>(kc, L, s);
+            return go_rows64<BF16, 4, NT>(kc, L, s);
         else if (kc.pairs == 1)
-            return go_rows64<BF16, 2>(kc, L, s);
+            return go_rows64<BF16, 2, NT>(kc, L, s);
         else
-            return go_rows64<BF16, 1>(kc, L, s);
+            return go_rows64<BF16, 1, NT>(kc, L, s);
     } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <bool BF16, int W>
+template <bool BF16, int W, bool NT>
 hipError_t go_few32(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.nmodes == 3)
-        NTC_GO((k_few32<3, BF16, W>), 64);
+        NTC_GO((k_few32<3, BF16, W, NT>), 64);
     else if (kc.nmodes == 4)
-        NTC_GO((k_few32<4, BF16, W>), 64);
+        NTC_GO((k_few32<4, BF16, W, NT>), 64);
     else
-        NTC_GO((k_few32<2, BF16, W>), 64);
+        NTC_GO((k_few32<2, BF16, W, NT>), 64);
     return hipGetLastError();
 }
 
 // load width of the few-sample kernel: FP32 four columns when R % 4 == 0, BF16
 // eight when R % 8 == 0; two when R is even; else one; R = 32 without masks
-template <bool BF16>
+template <bool BF16, bool NT>
 hipError_t go_few(const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     if (kc.rp != 32 || kc.nmodes > 4)
         return hipErrorInvalidValue;
     const int w = kc.pairs == 4 ? 3 : BF16 ? (kc.pairs == 3 ? 2 : kc.pairs >= 1 ? 1 : 0) : (kc.pairs >= 2 ? 2 : kc.pairs);
     if (w == 3)
-        return go_few32<BF16, 3>(kc, L, s);
+        return go_few32<BF16, 3, NT>(kc, L, s);
     if (w == 2)
-        return go_few32<BF16, 2>(kc, L, s);
+        return go_few32<BF16, 2, NT>(kc, L, s);
     if (w == 1)
-        return go_few32<BF16, 1>(kc, L, s);
-    return go_few32<BF16, 0>(kc, L, s);
+        return go_few32<BF16, 1, NT>(kc, L, s);
+    return go_few32<BF16, 0, NT>(kc, L, s);
 }
 
 template <bool BF16>
@@ -1060,23 +1060,33 @@ hipError_t go_reduce(const KernelClass &kc, const Launch &L, hipStream_t s)
 
 }  // namespace
 
-hipError_t launch_row_kernel_wide(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s)
+namespace {
+
+template <bool NT>
+hipError_t launch_wide(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s)
 {
     const bool b = kc.bf16 != 0;
     switch (kind) {
     case kRows:
-        return b ? go_rows<true>(kc, L, s) : go_rows<false>(kc, L, s);
+        return b ? go_rows<true, NT>(kc, L, s) : go_rows<false, NT>(kc, L, s);
     case kFinalize:
         return b ? go_finalize<true>(kc, L, s) : go_finalize<false>(kc, L, s);
     case kReduce:
         return go_reduce(kc, L, s);
     case kTiny:
-        return b ? go_few<true>(kc, L, s) : go_few<false>(kc, L, s);
+        return b ? go_few<true, NT>(kc, L, s) : go_few<false, NT>(kc, L, s);
     case kChunks:
     case kFew:
         return hipSuccess;
     }
     return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_row_kernel_wide(RowKernel kind, const KernelClass &kc, const Launch &L, hipStream_t s)
+{
+    return kc.nt ? launch_wide<true>(kind, kc, L, s) : launch_wide<false>(kind, kc, L, s);
 }
 
 }  // namespace ntc

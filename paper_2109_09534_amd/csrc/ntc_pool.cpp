@@ -241,7 +241,7 @@ struct TableImage {
 
 bool same_class(const ntc::KernelClass &a, const ntc::KernelClass &b)
 {
-    return a.rp == b.rp && a.nmodes == b.nmodes && a.bf16 == b.bf16 && a.pairs == b.pairs;
+    return a.rp == b.rp && a.nmodes == b.nmodes && a.bf16 == b.bf16 && a.pairs == b.pairs && a.nt == b.nt;
 }
 
 // Launch tables of the running slots: per (mode, inner step), per kernel

@@ -132,7 +132,7 @@ def _per_dispatch(path: str, counter: str):
 
 def traffic(kernel: str, fetch: str, write: str, copy_fetch: str, copy_write: str, copy_bytes: int,
             command: str, wide: bool = False) -> dict:
-    """HBM bytes per launch of `kernel` (name prefix, e.g. 'k_chunk16<3, 4, false>')."""
+    """HBM bytes per launch of `kernel` (name prefix, e.g. 'k_chunk16<3, 4, false, true>')."""
     kib = 1024.0
     scale = {}
     for counter, path, expect in (("FETCH_SIZE", copy_fetch, copy_bytes), ("WRITE_SIZE", copy_write, copy_bytes)):

@@ -56,3 +56,33 @@ def test_full_size_mode_updates_match_oracle_on_sampled_rows():
         idle = np.nonzero(b == 0)[0][:1000]
         assert np.array_equal(g.factors(m)[idle], init[m][idle])
         g.set_factors(m, init[m])      # the next mode starts from the shared factors again
+
+
+@pytest.mark.timeout(600)
+def test_records_past_the_cache_load_non_temporally_and_match_the_oracle():
+    """17 <= R <= 32, 4-way, with more than 256 MB of records (4.6M entries x 16 B x 4 modes): the row
+    kernels take the non-temporal record loads; every mode update, from the same FP32 factors, matches
+    the oracle's whole update element by element."""
+    O.build(force=False)
+    O.set_threads(16)
+    p = synth.make_problem((20000, 10000, 200, 50), 4_600_000, 16, zipf_s=1.05, noise_var=0.05, seed=50)
+    assert p.nnz * 16 * 4 > (256 << 20)
+    R = 32
+    init = synth.uniform_init(p.dims, R, 1, synth.init_scale(p.values, R, 4))
+    _say(f"records past the cache: dims {p.dims} nnz {p.nnz} R {R}")
+    g = ntc.Problem(p.dims, p.coords, p.values, R, c=0.1, init=init, stream=0)
+    o = O.Oracle(p.dims, p.coords, p.values, R, c=0.1, init=init)
+    for m in range(4):
+        g.update_mode(m)
+        o.update_mode(m)
+        got = g.factors(m).astype(np.float64)
+        ref = o.factors(m)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        scale = np.sqrt(np.mean(ref ** 2))
+        worst = np.max(np.abs(got - ref) / (np.abs(ref) + scale))
+        _say(f"  mode {m}: rel Frobenius {err:.3e}, worst element {worst:.3e}")
+        assert np.all(got >= 0)
+        assert err <= 1e-5 and worst <= 1e-5
+        o.set_factors(m, g.factors(m).astype(np.float64))
+    g.close()
+    o.close()

@@ -60,12 +60,12 @@ def test_full_size_mode_updates_match_oracle_on_sampled_rows():
 
 @pytest.mark.timeout(600)
 def test_records_past_the_cache_load_non_temporally_and_match_the_oracle():
-    """17 <= R <= 32, 4-way, with more than 256 MB of records (4.6M entries x 16 B x 4 modes): the row
+    """17 <= R <= 32, 4-way, with more than 256 MB of records (4.7M training entries x 16 B x 4 modes): the row
     kernels take the non-temporal record loads; every mode update, from the same FP32 factors, matches
     the oracle's whole update element by element."""
     O.build(force=False)
     O.set_threads(16)
-    p = synth.make_problem((20000, 10000, 200, 50), 4_600_000, 16, zipf_s=1.05, noise_var=0.05, seed=50)
+    p = synth.make_problem((20000, 10000, 200, 50), 5_200_000, 16, zipf_s=1.05, noise_var=0.05, seed=50)
     assert p.nnz * 16 * 4 > (256 << 20)
     R = 32
     init = synth.uniform_init(p.dims, R, 1, synth.init_scale(p.values, R, 4))

@@ -397,10 +397,11 @@ ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
             NTC_HIP(hipEventRecord(h->ev_fork, h->stream));
             NTC_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
         }
-        // launch order: one-row-per-lane, chunks, few-sample rows, rows, finalize of split rows.
-        // The few-sample rows (R <= 16) stay on the main stream after the chunks: the side
-        // stream already carries the one-row-per-lane rows and the group rows.
-        for (ntc::RowKernel kern : {ntc::kTiny, ntc::kChunks, ntc::kFew, ntc::kRows, ntc::kReduce, ntc::kFinalize}) {
+        // launch order: rows, chunks, few-sample rows, rows of at most tiny_max samples, finalize
+        // of split rows.  For R <= 16 the side stream runs the group rows, then the rows of at
+        // most 4 samples (C1: 0.891 against 0.898 ms per sweep the other way round); the
+        // rows of 5 to 16 samples stay on the main stream after the chunks.
+        for (ntc::RowKernel kern : {ntc::kRows, ntc::kChunks, ntc::kFew, ntc::kTiny, ntc::kReduce, ntc::kFinalize}) {
             L.blocks = ntc::row_kernel_blocks(kern, kc, md.n_items, md.n_group, md.n_split, md.n_tiny, md.n_groups,
                                               md.n_few);
             if (L.blocks <= 0)

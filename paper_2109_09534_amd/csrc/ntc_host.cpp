@@ -1599,6 +1599,9 @@ ntc_status ntc_estimate_bytes(int32_t nmodes, const int64_t *dims, int64_t nnz, 
     const double c = (q.c > 0.0 && q.c <= 1.0) ? q.c : 1.0;
     const int64_t inner = std::max<int32_t>(q.max_inner, 1);
     auto up = [](int64_t b) { return static_cast<size_t>((std::max<int64_t>(b, 1) + 255) / 256 * 256); };
+    // partial slots of one mode: a split row of B_p > smax samples takes
+    // ceil(B_p / smax) < 2 B_p / smax of them, its slot groups fewer again
+    const int64_t slots = 2 * static_cast<int64_t>(std::ceil(c * static_cast<double>(nnz) / smax)) + 1;
     size_t t = 0;
     int64_t maxI = 0;
     for (int m = 0; m < nmodes; ++m) {
@@ -1610,15 +1613,15 @@ ntc_status ntc_estimate_bytes(int32_t nmodes, const int64_t *dims, int64_t nnz, 
             t += up((dims[m] + 1) * R * 2);
         t += up((dims[m] + 1) * 8);                                   // rowptr
         t += up(nnz * rw * 4);                                        // records
-        t += up(dims[m] * 4);                                         // one-row-per-lane rows
+        t += up(dims[m] * 16);                                        // rows of a few samples
         t += up((dims[m] + nnz / smax + 1) * 16);                     // work items
         t += up(dims[m] * 16);                                        // split rows
+        t += up(slots * 16);                                          // slot groups
     }
     if (inner > 1)
         t += up((maxI + 1) * R * 4);
     if (N >= rw)
         t += up(nnz * 4);                                             // loss rows
-    const int64_t slots = 2 * static_cast<int64_t>(std::ceil(c * static_cast<double>(nnz) / smax)) + 1;
     t += up(slots * (rp + rp * rp) * 8);
     const int64_t nt = std::max<int64_t>(q.n_test, 1);
     t += up(nt * N * 4) + up(nt * 4);

@@ -52,7 +52,7 @@ def build(verbose: bool = False, out_path: str = LIB, defines=()) -> str:
             for f in [ex.submit(_run, cmd, verbose) for cmd, _ in jobs]:
                 f.result()
         out = out_path + ".tmp"
-        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + [o for _, o in jobs] + ["-lpthread"],
+        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + [o for _, o in jobs] + ["-lrocprofiler-sdk-roctx", "-lpthread"],
              verbose)
         os.replace(out, out_path)
     finally:

@@ -374,6 +374,7 @@ struct LaunchProbe {
 
 ntc_status enqueue_mode(ntc_problem *h, int mode, LaunchProbe *probe = nullptr)
 {
+    ntc::TraceRange range(ntc::mode_range_name(mode));
     const ModeState &md = h->md[mode];
     const ntc::KernelClass kc = kernel_class(h);
     for (int l = 0; l < h->max_inner; ++l) {
@@ -1094,6 +1095,7 @@ void ntc_params_default(ntc_params *p)
 ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz, const int32_t *coords,
                       const float *values, int32_t rank, const ntc_params *p)
 {
+    ntc::TraceRange range("ntc_create");
     if (!out)
         return fail(NTC_EINVAL, "out is null");
     *out = nullptr;
@@ -1122,6 +1124,7 @@ ntc_status ntc_create(ntc_handle *out, int32_t nmodes, const int64_t *dims, int6
 ntc_status ntc_create_device_csr(ntc_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
                                  const int32_t *coords, const float *values, int32_t rank, const ntc_params *p)
 {
+    ntc::TraceRange range("ntc_create_device_csr");
     if (!out)
         return fail(NTC_EINVAL, "out is null");
     *out = nullptr;
@@ -1160,6 +1163,7 @@ ntc_status ntc_create_device_csr(ntc_handle *out, int32_t nmodes, const int64_t 
 ntc_status ntc_prepare(ntc_prepared_handle *out, int32_t nmodes, const int64_t *dims, int64_t nnz,
                        const int32_t *coords, const float *values, int32_t rank, const ntc_params *p)
 {
+    ntc::TraceRange range("ntc_prepare");
     if (!out)
         return fail(NTC_EINVAL, "out is null");
     *out = nullptr;
@@ -1247,6 +1251,7 @@ ntc_status ntc_prepared_bytes(ntc_prepared_handle q, size_t *bytes)
 
 ntc_status ntc_create_prepared(ntc_handle *out, ntc_prepared_handle q, const ntc_params *p)
 {
+    ntc::TraceRange range("ntc_create_prepared");
     if (!out || !q)
         return fail(NTC_EINVAL, "null argument");
     *out = nullptr;
@@ -1277,6 +1282,7 @@ ntc_status ntc_prepared_release(ntc_prepared_handle q)
 
 ntc_status ntc_sweep(ntc_handle h, int32_t nsweeps)
 {
+    ntc::TraceRange range("ntc_sweep");
     if (!h)
         return fail(NTC_EINVAL, "null handle");
     if (nsweeps < 0)
@@ -1292,12 +1298,14 @@ ntc_status ntc_sweep(ntc_handle h, int32_t nsweeps)
 
 ntc_status ntc_update_mode(ntc_handle h, int32_t mode)
 {
+    ntc::TraceRange range("ntc_update_mode");
     NTC_TRY(check_mode(h, mode));
     return enqueue_mode(h, mode);
 }
 
 ntc_status ntc_loss(ntc_handle h, double out[4])
 {
+    ntc::TraceRange range("ntc_loss");
     if (!h || !out)
         return fail(NTC_EINVAL, "null argument");
     ntc::LossArgs a{};
@@ -1549,6 +1557,7 @@ ntc_status ntc_profile_sweep(ntc_handle h, ntc_launch_record *out, int32_t cap, 
 ntc_status ntc_profile_sweeps(ntc_handle h, int32_t nsweeps, int32_t concurrent, ntc_launch_record *out,
                               int32_t cap, int32_t *count)
 {
+    ntc::TraceRange range("ntc_profile_sweeps");
     if (!h || !count || (cap > 0 && !out))
         return fail(NTC_EINVAL, "null argument");
     if (nsweeps < 0)

@@ -604,6 +604,7 @@ ntc_status ntc_pool_admit(ntc_pool_handle pool, int32_t nmodes, const int64_t *d
                           const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
                           int32_t *slot)
 {
+    ntc::TraceRange range("ntc_pool_admit");
     if (!pool || !slot)
         return fail(NTC_EINVAL, "null argument");
     *slot = -1;
@@ -632,6 +633,7 @@ ntc_status ntc_pool_admit_device_csr(ntc_pool_handle pool, int32_t nmodes, const
                                      const int32_t *coords, const float *values, int32_t rank, const ntc_params *p,
                                      int32_t *slot)
 {
+    ntc::TraceRange range("ntc_pool_admit_device_csr");
     if (!pool || !slot)
         return fail(NTC_EINVAL, "null argument");
     *slot = -1;
@@ -658,6 +660,7 @@ ntc_status ntc_pool_admit_device_csr(ntc_pool_handle pool, int32_t nmodes, const
 
 ntc_status ntc_pool_admit_prepared(ntc_pool_handle pool, ntc_prepared_handle prepared, int32_t *slot)
 {
+    ntc::TraceRange range("ntc_pool_admit_prepared");
     if (!pool || !prepared || !slot)
         return fail(NTC_EINVAL, "null argument");
     return admit_prepared(pool, prepared, slot);
@@ -665,6 +668,7 @@ ntc_status ntc_pool_admit_prepared(ntc_pool_handle pool, ntc_prepared_handle pre
 
 ntc_status ntc_pool_step(ntc_pool_handle pool, int32_t nsweeps)
 {
+    ntc::TraceRange range("ntc_pool_step");
     if (!pool)
         return fail(NTC_EINVAL, "null pool");
     if (nsweeps < 0)
@@ -726,6 +730,7 @@ ntc_status ntc_pool_query(ntc_pool_handle pool, int32_t slot, int32_t *state, in
 
 ntc_status ntc_pool_loss(ntc_pool_handle pool, int32_t slot, double out[4])
 {
+    ntc::TraceRange range("ntc_pool_loss");
     POOL_TRY(check_slot(pool, slot));
     if (!pool->slots[slot].h)
         return fail(NTC_ESTATE, "slot is free");

@@ -6,6 +6,8 @@
 
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ntc.h"
 #include "ntc_internal.h"
 
@@ -36,6 +38,24 @@ ntc_status problem_view(ntc_handle h, ProblemView *v);
 
 // The pool advanced the device sweep counter by n: keep the host copy in step.
 void note_sweeps(ntc_handle h, int64_t n);
+
+// A ROCTX range over one host API call, shown by rocprofv3's marker trace
+// beside the kernels the call enqueued (a no-op with no profiler attached).
+// `name` must outlive the call.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
+// Range names of the modes of a sweep.
+inline const char *mode_range_name(int mode)
+{
+    static const char *const names[kMaxModes] = {"ntc mode 0", "ntc mode 1", "ntc mode 2", "ntc mode 3",
+                                                 "ntc mode 4", "ntc mode 5", "ntc mode 6", "ntc mode 7"};
+    return names[mode];
+}
 
 // Upper bound of the temporary device bytes ntc_create_device_csr takes (and
 // frees before it returns) for a problem of these sizes, allocations

@@ -5,6 +5,8 @@ the short text summaries kept beside the code:
 
 * ``trace``   -- per-kernel statistics (``--kernel-trace --stats``) and the
   dispatch table of the last sweep's row kernels, as Markdown;
+* ``ranges``  -- the library's ROCTX ranges (``--marker-trace``) with the
+  kernels each one launched (``--kernel-trace --hip-runtime-trace``);
 * ``traffic`` -- HBM bytes per launch of one kernel from two ``--pmc`` runs
   (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
   same counter reads for a plain device copy of known size, as JSON tagged
@@ -12,6 +14,7 @@ the short text summaries kept beside the code:
 
 Usage:
   python -m paper_2109_09534_amd.profiling trace DIR --title T --command C [--last 9] [--before NAME]
+  python -m paper_2109_09534_amd.profiling ranges DIR --title T --command C
   python -m paper_2109_09534_amd.profiling counters DIR [DIR ...] --title T --command C
   python -m paper_2109_09534_amd.profiling traffic --kernel K --fetch DIR --write DIR
          --copy-fetch DIR --copy-write DIR --copy-bytes B --command C [--out FILE]
@@ -78,6 +81,50 @@ def trace(path: str, title: str, command: str, last: int = 9, before: str = "") 
             "|---|---|---|---|---|---|---|---|"]
     for name, grid, wg, dur, vgpr, agpr, lds, scratch in rows[-last:]:
         out.append(f"| `{short_name(name)}` | {grid} | {wg} | {dur / 1e3:.1f} | {vgpr} | {agpr} | {lds} | {scratch} |")
+    return "\n".join(out) + "\n"
+
+
+def ranges(path: str, title: str, command: str) -> str:
+    """The library's ROCTX ranges (``--marker-trace``) with the kernels
+    rocprofv3 attributes to each (``--kernel-trace``: the innermost range
+    open on the launching thread when the kernel was enqueued)."""
+    con = _db(path)
+    marks = []
+    for name, extdata, start, end in con.execute("select name, extdata, start, end from regions where "
+                                                 "category like '%MARKER%' and end > start order by start"):
+        try:  # the range's message; the region's own name is the ROCTX call
+            name = json.loads(extdata).get("message", name)
+        except (TypeError, ValueError):
+            pass
+        marks.append((name, start, end))
+    kern = {}
+    for region, name, dur in con.execute("select region, name, duration from kernels order by start"):
+        kern.setdefault(region or "", []).append((short_name(name), dur))
+    out = [f"# {title}", "", "Command (from the repository root; REPO is its absolute path):", "",
+           "```", command, "```", "",
+           "Host time is the range's own interval on the calling thread (enqueue, not execution). Kernels are "
+           "those rocprofv3 attributes to the range: the innermost range open when each was enqueued. Kernel us is "
+           "the sum of their GPU durations; launches on the two streams of a mode overlap, so it can exceed the "
+           "mode's span.", "",
+           "| range | calls | host us per call | kernels per call | kernel us per call | kernels |",
+           "|---|---|---|---|---|---|"]
+    names = []
+    for m in marks:
+        if m[0] not in names:
+            names.append(m[0])
+    for n in names:
+        calls = [m for m in marks if m[0] == n]
+        host = sum(m[2] - m[1] for m in calls) / 1e3 / len(calls)
+        ks = kern.get(n, [])
+        gpu = sum(d for _, d in ks) / 1e3 / len(calls)
+        counts = {}
+        for k, _ in ks:
+            counts[k] = counts.get(k, 0) + 1
+        which = ", ".join(f"`{k}` x{v // len(calls) if v % len(calls) == 0 else v / len(calls):g}"
+                          for k, v in counts.items()) or "-"
+        out.append(f"| `{n}` | {len(calls)} | {host:.1f} | {len(ks) / len(calls):g} | {gpu:.1f} | {which} |")
+    if kern.get(""):
+        out += ["", f"{len(kern[''])} kernels ran outside every range."]
     return "\n".join(out) + "\n"
 
 
@@ -167,6 +214,11 @@ def main(argv=None):
     t.add_argument("--last", type=int, default=9)
     t.add_argument("--before", default="", help="end the dispatch table before the first kernel of this name")
     t.add_argument("--out")
+    g = sub.add_parser("ranges")
+    g.add_argument("dir")
+    g.add_argument("--title", required=True)
+    g.add_argument("--command", required=True)
+    g.add_argument("--out")
     c = sub.add_parser("counters")
     c.add_argument("dirs", nargs="+")
     c.add_argument("--title", required=True)
@@ -181,6 +233,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "trace":
         text = trace(a.dir, a.title, a.command, a.last, a.before)
+    elif a.what == "ranges":
+        text = ranges(a.dir, a.title, a.command)
     elif a.what == "counters":
         text = counters(a.dirs, a.title, a.command)
     else:

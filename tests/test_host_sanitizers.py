@@ -34,8 +34,8 @@ def test_host_code_under_sanitizers(kind, tmp_path):
         assert r.returncode == 0, r.stderr[-3000:]
         objs.append(obj)
     exe = str(tmp_path / "host_sanitized")
-    r = subprocess.run(["g++"] + san + objs + [f"-L{ROCM}/lib", "-lamdhip64", "-lpthread", "-o", exe],
-                       capture_output=True, text=True)
+    libs = [f"-L{ROCM}/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-lpthread"]
+    r = subprocess.run(["g++"] + san + objs + libs + ["-o", exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1",
                TSAN_OPTIONS="halt_on_error=1", LD_LIBRARY_PATH=f"{ROCM}/lib:" + os.environ.get("LD_LIBRARY_PATH", ""))

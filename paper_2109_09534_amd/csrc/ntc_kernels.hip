@@ -147,14 +147,17 @@ __device__ __forceinline__ GroupItem load_group_item(const Args &a, int id)
 // stage_record puts the zero record in its place.  With no load under a
 // branch the compiler can count the loads in flight, so a later wait for
 // older loads leaves this one outstanding.
+// spos: the item's sampled positions in increasing order (a whole row; see
+// sort_positions), else NULL and sample j is the PRP's image of j0 + j.
 template <int RW, bool NT, class Args>
 __device__ __forceinline__ bool fetch_record(const Args &a, const GroupItem &g, int jb, int r, uint4 &w0,
-                                             uint4 &w1)
+                                             uint4 &w1, const uint16_t *spos = nullptr)
 {
     const bool live = jb + r < g.len;
     int64_t e = 0;
     if (live)
-        e = g.base + prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r));
+        e = g.base + (spos ? static_cast<uint32_t>(spos[jb + r])
+                           : prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + jb + r)));
     const uint32_t *src = a.records + e * RW;
     w0 = load_record4<NT>(src);
     w1 = (RW == 8) ? load_record4<NT>(src + 4) : w0;
@@ -311,6 +314,53 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
 // H[4*(l/16) + v][l%16].  The four waves' FP64 sums and the 16 groups'
 // gradients are combined in LDS in a fixed order; a chunk that is the whole
 // row finishes it in place, otherwise it writes a partial slot.
+// A whole row of at most kSortedRowMax entries and kSortedChunkMax samples
+// runs through k_chunk16 in position order: its minibatch is the same set,
+// and records that share a cache line are then loaded by one instruction.
+constexpr int kSortedRowMax = 65536;   // positions fit 16 bits; a 2048-word bitmap
+constexpr int kSortedChunkMax = 6144;
+
+// The positions {pi(j) : j < g.len} of a whole row of n entries, in
+// increasing order, into pos[0 .. g.len): one bit per position in `bits`
+// (ceil(n / 32) words), then each of the 256 threads turns a run of words
+// into positions at the offset an exclusive scan of the runs' bit counts
+// gives (`scan`: 256 words).  The order is the positions' own, so the result
+// does not depend on the order of the atomics.  Block-wide: every thread
+// calls it.
+__device__ __forceinline__ void sort_positions(const GroupItem &g, int64_t n, uint32_t *bits, uint32_t *scan,
+                                               uint16_t *pos, int tid)
+{
+    const int W = static_cast<int>((n + 31) >> 5);
+    for (int w = tid; w < W; w += 256)
+        bits[w] = 0u;
+    __syncthreads();
+    for (int j = tid; j < g.len; j += 256) {
+        const uint32_t p = prp_index(g.prp, static_cast<uint32_t>(g.it.j0 + j));
+        atomicOr(&bits[p >> 5], 1u << (p & 31u));
+    }
+    __syncthreads();
+    const int per = (W + 255) >> 8;
+    const int w0 = min(tid * per, W);
+    const int w1 = min(w0 + per, W);
+    uint32_t cnt = 0;
+    for (int w = w0; w < w1; ++w)
+        cnt += __popc(bits[w]);
+    scan[tid] = cnt;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {  // inclusive scan (Hillis-Steele)
+        const uint32_t v = tid >= d ? scan[tid - d] : 0u;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    uint32_t o = scan[tid] - cnt;
+    for (int w = w0; w < w1; ++w) {
+        for (uint32_t m = bits[w]; m != 0u; m &= m - 1u)
+            pos[o++] = static_cast<uint16_t>(w * 32 + __builtin_ctz(m));
+    }
+    __syncthreads();
+}
+
 template <int NM, int RW, bool BF16, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_chunk16(NTC_ROW_PARAMS)
 {
@@ -338,6 +388,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
     g.prp = make_prp(static_cast<uint32_t>(n), sample_keys(a.seed, a.kptr[0], a.mode, a.l, it.row));
     const float *ysrc = (a.l == 0) ? a.A : a.Y;
     const float y = rlive ? ysrc[static_cast<int64_t>(it.row) * R + r] : 0.0f;
+    // position order for a whole row that fits (block-uniform); the bitmap
+    // and the scan reuse the buffers of the final combination
+    __shared__ uint16_t s_pos[kSortedChunkMax];
+    const uint16_t *spos = nullptr;
+    if (it.slot < 0 && n <= kSortedRowMax && g.len <= kSortedChunkMax) {
+        static_assert(sizeof(s_hw) >= (kSortedRowMax / 32) * 4 && sizeof(s_g) >= 256 * 4, "sort buffers");
+        sort_positions(g, n, reinterpret_cast<uint32_t *>(&s_hw[0][0]), reinterpret_cast<uint32_t *>(s_g), s_pos,
+                       tid);
+        spos = s_pos;
+    }
 
     const int nbatch = (g.len + 15) / 16;  // batches of the chunk
     const int nit = (nbatch + 15) / 16;    // iterations of every group (uniform in the block)
@@ -351,8 +411,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
     uint4 *rb1 = s_rec[wave][1];
     if (nit > 0) {
         uint4 v0, v1;
-        const bool l0 = fetch_record<RW, NT>(a, g, 16 * G, r, w0, w1);
-        const bool l1 = fetch_record<RW, NT>(a, g, 16 * (G + 16), r, v0, v1);
+        const bool l0 = fetch_record<RW, NT>(a, g, 16 * G, r, w0, w1, spos);
+        const bool l1 = fetch_record<RW, NT>(a, g, 16 * (G + 16), r, v0, v1, spos);
         stage_record<RW>(a, rb0, lane, l0, w0, w1);
         gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>(rb0) + grp * 16 * RW, rr, f);
         stage_record<RW>(a, rb1, lane, l1, v0, v1);
@@ -367,7 +427,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
                 k *= f[mm][t];
             kc[t] = rlive ? k : 0.0f;  // a missing sample gathered the zero rows
         }
-        const bool lv2 = fetch_record<RW, NT>(a, g, 16 * (G + 16 * (i + 2)), r, w0, w1);
+        const bool lv2 = fetch_record<RW, NT>(a, g, 16 * (G + 16 * (i + 2)), r, w0, w1, spos);
         if (i + 1 < nit)
             gather_batch<NM, RW, BF16>(a, reinterpret_cast<const uint32_t *>((i & 1) ? rb0 : rb1) + grp * 16 * RW,
                                        rr, f);

@@ -31,17 +31,17 @@ import sqlite3
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-ROW_KERNEL_SOURCES = ["ntc_kernels.hip", "ntc_dev.h", "ntc_rng.h", "ntc_bf16.h", "ntc_internal.h"]
-WIDE_KERNEL_SOURCES = ["ntc_kernels_wide.hip"]
+KERNEL_HEADERS = ["ntc_dev.h", "ntc_few.h", "ntc_rng.h", "ntc_bf16.h", "ntc_internal.h"]
 ROW_KERNELS = ("k_rows16", "k_chunk16", "k_tiny16", "k_finalize16", "k_row_items", "k_row_finalize",
                "k_rows16_nm", "k_rows32", "k_finalize32", "k_reduce_slots", "k_few16", "k_few32", "k_quad16")
 
 
 def source_hash(wide: bool = False) -> str:
-    """Hash of the sources the row kernels are compiled from (wide: the
-    R > 16 kernels too)."""
+    """Hash of the sources a row kernel is compiled from: its translation
+    unit (ntc_kernels.hip for R <= 16; wide: ntc_kernels_wide.hip for
+    R > 16) and the headers both include."""
     h = hashlib.sha256()
-    for fn in ROW_KERNEL_SOURCES + (WIDE_KERNEL_SOURCES if wide else []):
+    for fn in ["ntc_kernels_wide.hip" if wide else "ntc_kernels.hip"] + KERNEL_HEADERS:
         with open(os.path.join(PKG, "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -315,8 +315,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
 // gradients are combined in LDS in a fixed order; a chunk that is the whole
 // row finishes it in place, otherwise it writes a partial slot.
 // A whole row of at most kSortedRowMax entries and kSortedChunkMax samples
-// runs through k_chunk16 in position order: its minibatch is the same set,
-// and records that share a cache line are then loaded by one instruction.
+// runs through k_chunk16 in position order when the records stream from HBM
+// (NT, records past the last-level cache): its minibatch is the same set,
+// and records that share a line are then loaded by one instruction.  When
+// the records stay cached, the merged requests would have hit the cache
+// anyway and the ordering only delays the block's first loads.
 constexpr int kSortedRowMax = 65536;   // positions fit 16 bits; a 2048-word bitmap
 constexpr int kSortedChunkMax = 6144;
 
@@ -390,9 +393,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4
     const float y = rlive ? ysrc[static_cast<int64_t>(it.row) * R + r] : 0.0f;
     // position order for a whole row that fits (block-uniform); the bitmap
     // and the scan reuse the buffers of the final combination
-    __shared__ uint16_t s_pos[kSortedChunkMax];
+    __shared__ uint16_t s_pos[NT ? kSortedChunkMax : 1];
     const uint16_t *spos = nullptr;
-    if (it.slot < 0 && n <= kSortedRowMax && g.len <= kSortedChunkMax) {
+    if (NT && it.slot < 0 && n <= kSortedRowMax && g.len <= kSortedChunkMax) {
         static_assert(sizeof(s_hw) >= (kSortedRowMax / 32) * 4 && sizeof(s_g) >= 256 * 4, "sort buffers");
         sort_positions(g, n, reinterpret_cast<uint32_t *>(&s_hw[0][0]), reinterpret_cast<uint32_t *>(s_g), s_pos,
                        tid);

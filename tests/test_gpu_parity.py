@@ -186,6 +186,16 @@ CASES = {
                                       dict(c=0.2)),
     "few16_group_max_8": lambda: (synth.c1_small(seed=24), 16, dict(c=0.1, schedule={"group_max": 8})),
     "cw_few16_r16_power3": lambda: (synth.c1_small(seed=25), 16, dict(c=0.1, lp_bound=1, power_iters=3)),
+    # R <= 16 chunks that are whole rows read their samples in position order when the records exceed the
+    # last-level cache (281 MB here) and the row has at most 65536 entries and 6144 samples: rows on both
+    # sides of 65536 entries in one launch; then, in cached problems, rows of 90000 entries and rows of 9000
+    # samples (item_samples 16384), which keep the sampler's order
+    "chunk_sorted_rows_near_65536": lambda: (synth.make_problem((3000, 400, 89), 6_500_000, 8, seed=60), 16,
+                                             dict(c=0.09)),
+    "chunk_unsorted_rows_of_90000": lambda: (synth.make_problem((1500, 300, 4), 400_000, 8, seed=61), 16,
+                                             dict(c=0.05)),
+    "chunk_unsorted_rows_of_9000_samples": lambda: (synth.make_problem((1500, 300, 8), 400_000, 8, seed=62), 12,
+                                                    dict(c=0.2, schedule={"item_samples": 16384})),
 }
 
 

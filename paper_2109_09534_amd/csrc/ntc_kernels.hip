@@ -305,15 +305,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 
 }
 
 
-// Chunks of rows with many sampled entries: one 256-thread block (16
-// groups) per chunk of up to item_samples entries of ONE row.  Batch t of
-// the chunk (16 entries) goes to group t mod 16, so every group walks a
-// short chain of batches.  The four groups of a wave hold samples of the
-// same row, so one v_mfma_f32_16x16x4f32 per step adds all four k k^T into a
-// single 16x16 block (K = the four groups); register v of lane l holds
-// H[4*(l/16) + v][l%16].  The four waves' FP64 sums and the 16 groups'
-// gradients are combined in LDS in a fixed order; a chunk that is the whole
-// row finishes it in place, otherwise it writes a partial slot.
 // A whole row of at most kSortedRowMax entries and kSortedChunkMax samples
 // runs through k_chunk16 in position order when the records stream from HBM
 // (NT, records past the last-level cache): its minibatch is the same set,
@@ -364,6 +355,15 @@ __device__ __forceinline__ void sort_positions(const GroupItem &g, int64_t n, ui
     __syncthreads();
 }
 
+// Chunks of rows with many sampled entries: one 256-thread block (16
+// groups) per chunk of up to item_samples entries of ONE row.  Batch t of
+// the chunk (16 entries) goes to group t mod 16, so every group walks a
+// short chain of batches.  The four groups of a wave hold samples of the
+// same row, so one v_mfma_f32_16x16x4f32 per step adds all four k k^T into a
+// single 16x16 block (K = the four groups); register v of lane l holds
+// H[4*(l/16) + v][l%16].  The four waves' FP64 sums and the 16 groups'
+// gradients are combined in LDS in a fixed order; a chunk that is the whole
+// row finishes it in place, otherwise it writes a partial slot.
 template <int NM, int RW, bool BF16, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM <= 3 ? 4 : 2))) void k_chunk16(NTC_ROW_PARAMS)
 {

@@ -138,7 +138,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} (WORLD_SIZE={world}) is not supported; "
-              "the multi-GPU row sharding is a design note, not part of this build", file=sys.stderr)
+              "sharding the rows over several GPUs is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":

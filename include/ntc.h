@@ -43,7 +43,7 @@ typedef enum {
     NTC_EINVAL = -1,       /* invalid argument (message says which) */
     NTC_ENOMEM = -2,       /* device or host allocation failed */
     NTC_EDEVICE = -3,      /* HIP runtime error, including asynchronous faults */
-    NTC_EUNSUPPORTED = -4, /* valid request this build does not support */
+    NTC_EUNSUPPORTED = -4, /* a valid request the library does not support */
     NTC_ENONFINITE = -5,   /* the loss evaluated to a non-finite value */
     NTC_ESTATE = -6        /* call not valid in the handle's current state */
 } ntc_status;

@@ -160,3 +160,12 @@ def test_scaling_twin_is_the_timing_workload_of_section_iv_c():
     for m in range(4):
         ref *= p.planted[m][co[idx, m]]
     np.testing.assert_allclose(p.values[idx], ref.sum(axis=1).astype(np.float32), rtol=0, atol=0)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus above 1 exits with status 2 and a message, before any work."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
